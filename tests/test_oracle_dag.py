@@ -1,0 +1,132 @@
+"""Pins of the oracle's DAG runner and attention formulas."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dag, attention
+from oracle import kernels as K
+
+
+def test_all_topological_orders_give_identical_outputs():
+    cases = [
+        (workloads.forkjoin_spec(16), workloads.forkjoin_inputs(2, 16)),
+        (workloads.mha_spec(8, 8, 1), workloads.mha_inputs(3, 8, 8)),
+        (workloads.mha_spec(8, 8, 2), workloads.mha_inputs(4, 8, 8)),
+    ]
+    for spec, inp in cases:
+        orders = dag.all_topological_orders(spec, limit=20000)
+        assert len(orders) >= 2
+        ref = dag.run_dag(spec, inp, order=orders[0])
+        for o in orders[1:: max(1, len(orders) // 200)]:
+            st = dag.run_dag(spec, inp, order=o)
+            for k in ref:
+                np.testing.assert_array_equal(st[k], ref[k])
+
+
+def test_forkjoin_has_two_orders():
+    spec = workloads.forkjoin_spec(4)
+    assert dag.all_topological_orders(spec) == [[0, 1, 2, 3], [0, 2, 1, 3]]
+    assert dag.count_orders(spec) == 2
+
+
+def test_non_topological_order_and_cycle_rejected():
+    spec = workloads.forkjoin_spec(4)
+    with pytest.raises(ValueError):
+        dag.run_dag(spec, workloads.forkjoin_inputs(0, 4), order=[1, 0, 2, 3])
+    cyc = dict(spec, edges=spec["edges"] + [(3, "C3", 0, "A0")])
+    with pytest.raises(ValueError):
+        dag.topological_order(cyc)
+
+
+def test_unproduced_storage_reads_as_nan():
+    spec = workloads.forkjoin_spec(4)
+    inp = workloads.forkjoin_inputs(0, 4)
+    del inp["B2"]
+    st = dag.run_dag(spec, inp)
+    assert np.isnan(st["C2"]).all() and np.isnan(st["C3"]).all()
+    assert not np.isnan(st["C1"]).any()
+
+
+@pytest.mark.parametrize("n,d,h,layers", [(16, 16, 2, 1), (24, 32, 4, 2), (13, 8, 2, 1)])
+def test_mha_dag_equals_direct_formula(n, d, h, layers):
+    spec = workloads.mha_spec(n, d, h, layers)
+    inp = workloads.mha_inputs(5, n, d, layers)
+    st = dag.run_dag(spec, inp)
+    ws = [tuple(inp[f"{w}{l}"] for w in ("Wq", "Wk", "Wv", "Wo")) for l in range(layers)]
+    ref = attention.mha_stack(inp["X"], ws, h)
+    np.testing.assert_allclose(st[f"Y{layers - 1}"], ref, rtol=1e-12, atol=1e-14)
+
+
+def test_attention_zero_query_weights_give_column_means():
+    # Wq = 0  =>  S = 0  =>  every row of P is 1/n  =>  each row of O_h is the column mean of V_h
+    n, d, h = 12, 8, 2
+    inp = workloads.mha_inputs(6, n, d)
+    inp["Wq0"] = np.zeros((d, d), np.float32)
+    spec = workloads.mha_spec(n, d, h)
+    st = dag.run_dag(spec, inp)
+    x = inp["X"].astype(np.float64)
+    v = x @ inp["Wv0"].astype(np.float64)
+    ocat = np.tile(v.mean(axis=0), (n, 1))
+    np.testing.assert_allclose(st["Ocat0"], ocat, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(st["Y0"], ocat @ inp["Wo0"].astype(np.float64), rtol=1e-12,
+                               atol=1e-14)
+
+
+def test_attention_hand_example_one_head():
+    # n = 2, d = 2, one head (dh = 2, scale 1/sqrt 2).  X = I, Wq = Wk = diag(a, a) with
+    # a = 10: S = (1/sqrt 2) diag(a^2, a^2) = diag(70.71.., 70.71..), so P = diag(p, p) + (1-p)
+    # off the diagonal with p = 1/(1 + exp(-a^2/sqrt 2)); V = Wv; Y = P Wv Wo.
+    a = 10.0
+    x = np.eye(2, dtype=np.float32)
+    wq = wk = np.diag([a, a]).astype(np.float32)
+    wv = np.array([[1.0, 2.0], [3.0, 4.0]], np.float32)
+    wo = np.array([[0.5, 0.0], [0.0, 2.0]], np.float32)
+    p = 1.0 / (1.0 + math.exp(-a * a / math.sqrt(2.0)))
+    pm = np.array([[p, 1 - p], [1 - p, p]])
+    expect = pm @ wv.astype(np.float64) @ wo.astype(np.float64)
+    spec = workloads.mha_spec(2, 2, 1)
+    st = dag.run_dag(spec, {"X": x, "Wq0": wq, "Wk0": wk, "Wv0": wv, "Wo0": wo})
+    np.testing.assert_allclose(st["Y0"], expect, rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose(attention.mha_layer(x, wq, wk, wv, wo, 1), expect, rtol=1e-14)
+
+
+def test_attention_row_permutation_equivariance():
+    n, d, h = 16, 16, 4
+    inp = workloads.mha_inputs(7, n, d)
+    perm = np.random.default_rng(8).permutation(n)
+    y = attention.mha_layer(inp["X"], inp["Wq0"], inp["Wk0"], inp["Wv0"], inp["Wo0"], h)
+    yp = attention.mha_layer(inp["X"][perm], inp["Wq0"], inp["Wk0"], inp["Wv0"], inp["Wo0"], h)
+    np.testing.assert_allclose(yp, y[perm], rtol=1e-12, atol=1e-14)
+
+
+def test_emulate_mode_f32_close_and_bf16_within_budget():
+    n, d, h = 32, 32, 4
+    inp = workloads.mha_inputs(9, n, d)
+    exact = dag.run_dag(workloads.mha_spec(n, d, h), inp)["Y0"]
+    em32 = dag.run_dag(workloads.mha_spec(n, d, h), inp, emulate=True)["Y0"]
+    em16 = dag.run_dag(workloads.mha_spec(n, d, h, gemm_dtype="bf16"), inp, emulate=True)["Y0"]
+    rel = lambda a: np.linalg.norm(a - exact) / np.linalg.norm(exact)
+    assert rel(em32) < 1e-6
+    assert 1e-5 < rel(em16) < 2e-2
+
+
+def test_view_windows_write_into_parent():
+    spec = workloads.mha_spec(8, 8, 2)
+    inp = workloads.mha_inputs(10, 8, 8)
+    st = dag.run_dag(spec, inp)
+    o1 = dag.read_buffer(spec, st, "L0H1_O")
+    np.testing.assert_array_equal(o1, st["Ocat0"][:, 4:8])
+    assert not np.isnan(st["Ocat0"]).any()
+
+
+def test_spec_counts_match_structure():
+    spec = workloads.mha_spec(512, 512, 8)
+    assert len(spec["kernels"]) == 57                    # 7 per head + the join
+    assert workloads.host_inputs_of(spec) == ["X", "Wq0", "Wk0", "Wv0", "Wo0"]
+    assert workloads.host_outputs_of(spec) == ["Y0"]
+    assert workloads.spec_flops(spec) == pytest.approx(1.611e9, rel=1e-3)
+    spec12 = workloads.mha_spec(1024, 1024, 16, 12, "bf16")
+    assert len(spec12["kernels"]) == 12 * 113
+    assert workloads.spec_flops(spec12) == pytest.approx(154.6e9, rel=1e-3)
