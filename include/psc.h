@@ -1,0 +1,303 @@
+/*
+ * psc.h -- C ABI of an MI355X (gfx950) executor for application DAGs of data-parallel kernels,
+ * after PySchedCL (Ghose et al., "PySchedCL: Leveraging Concurrency in Heterogeneous
+ * Data-Parallel Systems").
+ *
+ * Model (Sec. III): an application is a DAG G = <(K, B), (E_I, E_O, E)> of kernels K that read
+ * input buffers and write output buffers; an edge of E makes a producer kernel's output buffer a
+ * consumer kernel's input buffer.  An input buffer with no incoming edge is an *isolated write*
+ * (copied host -> device, H2D) and an output buffer with no outgoing edge is an *isolated read*
+ * (copied device -> host, D2H).  A schedule (Def. 5) maps every kernel with its copies onto
+ * in-order queues -- here HIP streams -- so that kernels run in a topological order; the
+ * command-queue structure (Def. 4) is the per-stream op lists plus cross-stream precedence pairs,
+ * realised with HIP events.  Coarse-grained scheduling uses one stream; fine-grained scheduling
+ * uses several, so independent kernels run concurrently and copies overlap compute (Sec. II-A).
+ *
+ * Calling sequence: psc_dag_create -> psc_add_buffer* -> psc_add_kernel* -> psc_add_edge* ->
+ * psc_schedule(policy) -> psc_run* -> psc_sched_destroy -> psc_dag_destroy.
+ *
+ * Conventions for every function below:
+ *  - Return value: PSC_OK (0) on success, a negative psc_status on failure.  No C++ exception
+ *    crosses this boundary.  On failure psc_last_error() returns a message describing it.
+ *  - Strings are NUL-terminated; the library copies every string it keeps.
+ *  - Matrices are row-major.  A buffer has `rows` x `cols` elements of its dtype.  A *view* is a
+ *    rows x cols window at (row_off, col_off) of a parent buffer and shares the parent's storage
+ *    and leading dimension (the root buffer's `cols`).
+ *  - Pointers named *_out / *out are written only on success.
+ *  - The DAG and schedule objects are not thread safe: calls on one object must not overlap.
+ *  - Only functions marked [GPU] touch the GPU; all others are host-only and work without one.
+ */
+#ifndef PSC_H
+#define PSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSC_ABI_VERSION 1
+
+typedef enum psc_status {
+  PSC_OK = 0,
+  PSC_ERR_ARG = -1,      /* NULL pointer, bad enum, negative size, out-of-range id */
+  PSC_ERR_NAME = -2,     /* unknown or duplicate buffer / kernel name */
+  PSC_ERR_SHAPE = -3,    /* operand shapes or dtypes do not fit the kernel, or an edge joins
+                            buffers that share no storage, or an input is only partly produced */
+  PSC_ERR_CYCLE = -4,    /* the edges form a cycle */
+  PSC_ERR_RACE = -5,     /* two kernels touch overlapping storage, one writing, without an edge
+                            path ordering them; or an input that a kernel produces has no edge */
+  PSC_ERR_STATE = -6,    /* call not allowed in the object's current state */
+  PSC_ERR_HIP = -7,      /* a HIP runtime call failed (message names it) */
+  PSC_ERR_OOM = -8,      /* device or host allocation failed */
+  PSC_ERR_UNSUPPORTED = -9
+} psc_status;
+
+typedef enum psc_dtype { PSC_F32 = 0, PSC_BF16 = 1 } psc_dtype;
+
+/* Kernel kinds (Sec. V builds each attention head from these; add is the vadd of Sec. II).
+ *  PSC_GEMM      inputs {A (M x K), B (K x N)}, output {C (M x N)}: C = alpha * A * B.
+ *                A and B share a dtype: F32 runs FP32 matrix-core arithmetic, BF16 runs BF16
+ *                matrix-core products with FP32 accumulation.  C is F32 or BF16 (rounded to
+ *                nearest even from the FP32 accumulator).
+ *  PSC_TRANSPOSE inputs {A (R x C)}, output {B (C x R)}, same dtype: B[j][i] = A[i][j].
+ *  PSC_SOFTMAX   inputs {X (R x C)}, output {Y (R x C)}: each row normalised exponential,
+ *                max-subtracted, with the max and sum reductions in FP32.
+ *  PSC_ADD       inputs {A, B}, output {C}, all of one shape: C = A + B in FP32. */
+typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_ADD = 3 } psc_kind;
+
+/* Coarse: one stream, kernels in breadth-first topological order, each with its isolated
+ * writes just before and isolated reads just after it (the enq rules of Sec. III).
+ * Fine: n_streams streams, kernels mapped by the mapper below, with event precedences. */
+typedef enum psc_policy { PSC_COARSE = 0, PSC_FINE = 1 } psc_policy;
+
+/* Stream choice of the fine policy.
+ *  PSC_MAP_RR         round robin per kernel in breadth-first order from the DAG's roots
+ *                     (sel_rr of Sec. IV-B, Algorithm 1) -- the plain heuristic.
+ *  PSC_MAP_EFT        list scheduling: kernels by descending bottom-level rank (Sec. V,
+ *                     clustering), each on the stream with the earliest predicted finish time
+ *                     (the EFT rule of HEFT) under the cost model given in the options.
+ *  PSC_MAP_COMPONENT  every kernel of task component c on stream c mod n_streams. */
+typedef enum psc_mapper { PSC_MAP_RR = 0, PSC_MAP_EFT = 1, PSC_MAP_COMPONENT = 2 } psc_mapper;
+
+typedef enum psc_op_type { PSC_OP_H2D = 0, PSC_OP_KERNEL = 1, PSC_OP_D2H = 2 } psc_op_type;
+
+/* Kernel classes of a task component (Defs. 1-3 of Sec. III); a kernel may be in FRONT and END. */
+typedef enum psc_kclass { PSC_FRONT = 1, PSC_END = 2, PSC_IN = 4 } psc_kclass;
+
+typedef struct psc_dag psc_dag;
+typedef struct psc_sched psc_sched;
+typedef struct psc_mlp psc_mlp;
+
+typedef struct psc_kernel_params {
+  float alpha;          /* GEMM scale; ignored by the other kinds.  Zero-initialised params
+                           (or params == NULL) mean alpha = 1. */
+  int32_t alpha_set;    /* nonzero: use alpha as given (so alpha = 0 is expressible) */
+  int32_t tile;         /* GEMM tile configuration index, -1 or 0 = automatic */
+  int32_t reserved;
+} psc_kernel_params;
+
+typedef struct psc_sched_opts {
+  int32_t n_streams;    /* number of streams (the paper's command queues per device), 1..64;
+                           forced to 1 by PSC_COARSE */
+  int32_t mapper;       /* psc_mapper; used by PSC_FINE */
+  int32_t copy_stream;  /* 0: copies on their kernel's stream (paper's enq rules);
+                           1: every H2D on one extra stream, enqueued before any kernel, so
+                              uploads overlap compute; D2H stays on its producer's stream */
+  int32_t use_graph;    /* 1: psc_run builds the schedule as one hipGraph -- a node per op, an
+                           edge per stream-order or wait precedence -- once (again when the host
+                           pointers change) and launches it with hipGraphLaunch */
+  int32_t record_ops;   /* 1: psc_run records start/end events around every op (timeline and
+                           cost-model samples); incompatible with use_graph */
+  int32_t device;       /* HIP device ordinal */
+  const psc_mlp *cost;  /* learned cost model for PSC_MAP_EFT; NULL = heuristic model */
+  int32_t host_threads; /* host threads that enqueue in psc_run (stream s is enqueued by thread
+                           s mod host_threads); 0 = one per stream, 1 = the caller only */
+  int32_t reserved[7];
+} psc_sched_opts;
+
+/* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..
+ * wait_off + n_waits) in the array filled by psc_sched_export (ids of ops it waits for). */
+typedef struct psc_op {
+  int32_t id;
+  int32_t type;         /* psc_op_type */
+  int32_t kernel;       /* kernel id for PSC_OP_KERNEL, else -1 */
+  int32_t buffer;       /* buffer id for copies (a root buffer for H2D), else -1 */
+  int32_t stream;       /* stream index */
+  int32_t pos;          /* position in its stream */
+  int32_t host_order;   /* position in the host's enqueue sequence */
+  int32_t n_waits;
+  int32_t wait_off;
+} psc_op;
+
+/* Host memory for one isolated write (read from) or isolated read (written to).  `bytes` must
+ * equal the buffer's rows*cols*element size; data is dense row-major.  For overlap the memory
+ * should be pinned (hipHostMalloc, torch pin_memory).  A buffer with no entry is not copied:
+ * its device storage is used as it stands (device-resident inputs and outputs). */
+typedef struct psc_host_io {
+  const char *name;
+  void *host_ptr;
+  size_t bytes;
+} psc_host_io;
+
+typedef struct psc_run_stats {
+  double makespan_ms;      /* GPU time from the start event (recorded before the first op) to
+                              the end event (after every stream joined) */
+  double host_enqueue_ms;  /* host wall time spent enqueueing (graph launch only, in graph mode) */
+  int32_t n_ops, n_kernels, n_h2d, n_d2h, n_waits, n_streams, graph, reserved;
+} psc_run_stats;
+
+/* Per-op timing of the last psc_run with record_ops = 1, relative to the start event. */
+typedef struct psc_op_time {
+  int32_t op;
+  int32_t stream;
+  float start_us;
+  float end_us;
+} psc_op_time;
+
+/* ---------------------------------------------------------------------------------------------
+ * DAG construction (host-only)
+ * ------------------------------------------------------------------------------------------- */
+
+/* A new empty DAG, owned by the caller until psc_dag_destroy. */
+psc_status psc_dag_create(psc_dag **out);
+
+/* Frees the DAG.  Every schedule made from it must be destroyed first (PSC_ERR_STATE otherwise).
+ * NULL is accepted and ignored. */
+psc_status psc_dag_destroy(psc_dag *dag);
+
+/* Declares buffer `name` (B of Sec. III; the <type, size> of a buffer tuple in Sec. IV-A) of
+ * dtype x rows x cols.  With view_of != NULL it is a window of that buffer at (row_off, col_off),
+ * which must lie inside it.  Zero rows or cols are allowed (empty buffer).
+ * Errors: PSC_ERR_NAME (duplicate name, unknown parent), PSC_ERR_SHAPE (window outside the
+ * parent, dtype differs from the parent's), PSC_ERR_STATE (DAG already scheduled). */
+psc_status psc_add_buffer(psc_dag *dag, const char *name, int32_t dtype, int64_t rows,
+                          int64_t cols, const char *view_of, int64_t row_off, int64_t col_off);
+
+/* Adds kernel `name` of kind `kind` reading buffers inputs[0..n_in) and writing
+ * outputs[0..n_out) (E_I and E_O of Sec. III).  Shapes are checked when the DAG is scheduled.
+ * *kernel_id (may be NULL) receives the kernel's id: ids count up from 0 in call order.
+ * Errors: PSC_ERR_NAME, PSC_ERR_ARG (wrong operand count for the kind), PSC_ERR_STATE. */
+psc_status psc_add_kernel(psc_dag *dag, const char *name, int32_t kind,
+                          const char *const *inputs, int32_t n_in, const char *const *outputs,
+                          int32_t n_out, const psc_kernel_params *params, int32_t *kernel_id);
+
+/* Edge k_i,b_r -> k_j,b_s of the specification file (Sec. IV-A): output buffer `src_output` of
+ * kernel src_kernel feeds input buffer `dst_input` of kernel dst_kernel.  On one device the two
+ * must share storage (the same buffer, or overlapping windows of one root buffer): the consumer
+ * reads what the producer wrote, with no copy.  Errors: PSC_ERR_ARG (bad ids), PSC_ERR_NAME
+ * (buffer is not an output / input of that kernel), PSC_ERR_SHAPE (no shared storage),
+ * PSC_ERR_STATE. */
+psc_status psc_add_edge(psc_dag *dag, int32_t src_kernel, const char *src_output,
+                        int32_t dst_kernel, const char *dst_input);
+
+/* Puts a kernel in task component `component` (>= 0; all kernels start in component 0).
+ * Components drive the classification below and PSC_MAP_COMPONENT. */
+psc_status psc_set_component(psc_dag *dag, int32_t kernel, int32_t component);
+
+/* Uses caller-owned device memory at `dptr` (>= the buffer's rows*cols*element bytes, dense
+ * row-major) as the storage of root buffer `name` instead of library-allocated memory.  The
+ * memory must stay valid while schedules of this DAG run.  Errors: PSC_ERR_NAME (unknown, or a
+ * view), PSC_ERR_ARG (NULL or too small), PSC_ERR_STATE. */
+psc_status psc_bind_device(psc_dag *dag, const char *name, void *dptr, size_t bytes);
+
+/* Counts of kernels, buffers and edges (any pointer may be NULL). */
+psc_status psc_dag_info(const psc_dag *dag, int32_t *n_kernels, int32_t *n_buffers,
+                        int32_t *n_edges);
+
+/* Id of buffer `name` (ids count up from 0 in psc_add_buffer order). */
+psc_status psc_buffer_id(const psc_dag *dag, const char *name, int32_t *id);
+
+/* Classification of task component `component` (Sec. III): kclass[k] (n_kernels entries) gets
+ * PSC_FRONT | PSC_END | PSC_IN bits for kernels of the component, 0 for others: FRONT = no
+ * producer inside the component, END = no consumer inside it, IN = neither.  edge_inter[e]
+ * (n_edges entries, edge ids in psc_add_edge order) gets 1 for an inter edge (the two kernels
+ * lie in different components), 0 for an intra edge.  Either array may be NULL.
+ * Validates the DAG like psc_schedule does. */
+psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass,
+                            int32_t *edge_inter);
+
+/* ---------------------------------------------------------------------------------------------
+ * Scheduling (host-only) and execution
+ * ------------------------------------------------------------------------------------------- */
+
+/* Validates and freezes the DAG (no further psc_add_* calls), then builds the command-queue
+ * structure for `policy` (setup_cq of Sec. IV-B): per-stream op lists and the event waits that
+ * realise rules (i)-(iii) of Sec. III.  Waits already implied by stream order or by earlier waits
+ * are omitted.  opts == NULL means: 4 streams, PSC_MAP_RR, no copy stream, no graph, device 0.
+ * The schedule references the DAG, which must outlive it.  No GPU call is made here (except that
+ * a PSC_MAP_EFT with an MLP cost model evaluates the model on the GPU).
+ * Errors: PSC_ERR_SHAPE, PSC_ERR_CYCLE, PSC_ERR_RACE (see psc_status), PSC_ERR_ARG. */
+psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts,
+                        psc_sched **out);
+
+/* Copies the schedule's ops (ordered by id) into ops[0..cap) and their waits into
+ * waits[0..waits_cap); *n_ops / *n_waits receive the totals.  With ops == NULL or waits == NULL
+ * only the totals are returned.  PSC_ERR_ARG if a capacity is too small. */
+psc_status psc_sched_export(const psc_sched *sched, psc_op *ops, int32_t cap, int32_t *n_ops,
+                            int32_t *waits, int32_t waits_cap, int32_t *n_waits);
+
+/* Number of streams the schedule uses (n_streams, plus one with copy_stream). */
+psc_status psc_sched_streams(const psc_sched *sched, int32_t *n_streams);
+
+/* [GPU] Allocates device storage for every unbound root buffer (one arena), creates streams
+ * and events, and prepares kernel launches.  Called by the first psc_run if not called before.
+ * Errors: PSC_ERR_HIP, PSC_ERR_OOM. */
+psc_status psc_sched_prepare(psc_sched *sched);
+
+/* [GPU] Runs the schedule once and waits for it: records a start event, enqueues every op in
+ * host order (each wait as hipStreamWaitEvent on the producing op's event), joins all streams
+ * and waits for the end event.  io[0..n_io) gives host memory for isolated writes / reads by
+ * buffer name (see psc_host_io); buffers not listed are not copied.  stats may be NULL.
+ * Errors: PSC_ERR_NAME (io names no isolated write or read), PSC_ERR_ARG (byte count), PSC_ERR_HIP. */
+psc_status psc_run(psc_sched *sched, const psc_host_io *io, int32_t n_io, psc_run_stats *stats);
+
+/* Per-op timeline of the last psc_run made with record_ops = 1: out[0..cap), *n = op count. */
+psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t cap, int32_t *n);
+
+/* [GPU after prepare] Device address of buffer `name` (a view's address is inside its root's
+ * storage) and its leading dimension in elements.  PSC_ERR_STATE before psc_sched_prepare. */
+psc_status psc_sched_device_ptr(const psc_sched *sched, const char *name, void **dptr,
+                                int64_t *ld);
+
+/* [GPU] Launches kernel `kernel` of a prepared schedule `iters` times back to back on its own
+ * stream, on the storage the schedule uses, and returns the mean duration per launch measured
+ * with HIP events on that stream.  For kernel-level timing. */
+psc_status psc_kernel_time(psc_sched *sched, int32_t kernel, int32_t iters, float *avg_us);
+
+/* [GPU] Page-locked host memory (hipHostMalloc) of `bytes` bytes for psc_host_io buffers, so
+ * copies run asynchronously and overlap compute.  Freed with psc_host_free.  Errors: PSC_ERR_ARG
+ * (NULL out), PSC_ERR_OOM. */
+psc_status psc_host_alloc(size_t bytes, void **out);
+
+/* [GPU] Frees memory from psc_host_alloc.  NULL is ignored. */
+psc_status psc_host_free(void *ptr);
+
+/* [GPU] Waits until all work the library enqueued on `device` has finished (hipDeviceSynchronize). */
+psc_status psc_device_sync(int32_t device);
+
+/* Host-only check of the multi-threaded enqueue: runs psc_run's dispatch threads (host_threads
+ * as in psc_sched_opts) against a recording backend instead of HIP, with a random sleep of up
+ * to jitter_us microseconds before every recorded call (seeded by `seed`).  out[0 .. 3*n) gets
+ * one (kind, op, arg) triple per call in the order the calls happened: kind 0 = wait (arg = the
+ * awaited op), 1 = the op itself, 2 = event record of the op, 3 = stream finished (op = -1,
+ * arg = stream).  *n = number of triples; PSC_ERR_ARG if cap < 3 * n. */
+psc_status psc_sched_dispatch_trace(const psc_sched *sched, int32_t host_threads, int32_t jitter_us,
+                                    uint32_t seed, int32_t *out, int32_t cap, int32_t *n);
+
+/* Frees device storage, streams, events and graphs of the schedule.  NULL is ignored. */
+psc_status psc_sched_destroy(psc_sched *sched);
+
+/* Message of the most recent call on this thread if it failed, "" if it succeeded.  Valid until
+ * the next call on this thread. */
+const char *psc_last_error(void);
+
+/* PSC_ABI_VERSION of the loaded library. */
+int32_t psc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSC_H */

@@ -1,0 +1,460 @@
+"""Python binding of libpsc (include/psc.h): a fine-grained DAG executor for MI355X (gfx950).
+
+The functions below carry the C names and only marshal arguments (names to bytes, numpy/torch
+buffers to pointers, exported structs to dicts); every step of scheduling and execution runs in
+the native library.  Importing the package loads ``libpsc.so`` from this directory and raises
+ImportError if it is missing -- there is no fallback implementation.  Build it with
+``python paper_2009_07482_amd/build.py``.
+
+Workload specs from ``workloads`` (the JSON-like DAG descriptions) are lowered onto the C ABI by
+``build_dag``; ``run_spec`` runs one with host inputs and returns host outputs.
+
+Host staging memory comes from the library (psc_host_alloc, page-locked), and this package
+never initialises torch's GPU runtime: torch ships its own HIP runtime, and a second initialised
+runtime in one process cannot see the GPU.  torch is used here only for CPU dtype casts.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2009_07482_amd/build.py`")
+_lib = C.CDLL(LIB_PATH)
+
+# --- constants (psc.h) ------------------------------------------------------------------------
+PSC_OK = 0
+STATUS = {0: "PSC_OK", -1: "PSC_ERR_ARG", -2: "PSC_ERR_NAME", -3: "PSC_ERR_SHAPE", -4: "PSC_ERR_CYCLE",
+          -5: "PSC_ERR_RACE", -6: "PSC_ERR_STATE", -7: "PSC_ERR_HIP", -8: "PSC_ERR_OOM",
+          -9: "PSC_ERR_UNSUPPORTED"}
+PSC_F32, PSC_BF16 = 0, 1
+DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
+PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
+KINDS = {"gemm": PSC_GEMM, "transpose": PSC_TRANSPOSE, "softmax": PSC_SOFTMAX, "add": PSC_ADD}
+PSC_COARSE, PSC_FINE = 0, 1
+PSC_MAP_RR, PSC_MAP_EFT, PSC_MAP_COMPONENT = 0, 1, 2
+MAPPERS = {"rr": PSC_MAP_RR, "eft": PSC_MAP_EFT, "component": PSC_MAP_COMPONENT}
+PSC_OP_H2D, PSC_OP_KERNEL, PSC_OP_D2H = 0, 1, 2
+OP_TYPES = {0: "h2d", 1: "kernel", 2: "d2h"}
+PSC_FRONT, PSC_END, PSC_IN = 1, 2, 4
+
+
+class PscError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+# --- structs ------------------------------------------------------------------------------------
+class psc_kernel_params(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("alpha_set", C.c_int32), ("tile", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class psc_sched_opts(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("mapper", C.c_int32), ("copy_stream", C.c_int32),
+                ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
+                ("cost", C.c_void_p), ("host_threads", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class psc_op(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("id", "type", "kernel", "buffer", "stream", "pos",
+                                          "host_order", "n_waits", "wait_off")]
+
+
+class psc_host_io(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("host_ptr", C.c_void_p), ("bytes", C.c_size_t)]
+
+
+class psc_run_stats(C.Structure):
+    _fields_ = [("makespan_ms", C.c_double), ("host_enqueue_ms", C.c_double)] + [
+        (n, C.c_int32) for n in ("n_ops", "n_kernels", "n_h2d", "n_d2h", "n_waits", "n_streams",
+                                 "graph", "reserved")]
+
+
+class psc_op_time(C.Structure):
+    _fields_ = [("op", C.c_int32), ("stream", C.c_int32), ("start_us", C.c_float),
+                ("end_us", C.c_float)]
+
+
+_P = C.c_void_p
+_I = C.c_int32
+_I64 = C.c_int64
+_S = C.c_char_p
+_SIGS = {
+    "psc_dag_create": [C.POINTER(_P)],
+    "psc_dag_destroy": [_P],
+    "psc_add_buffer": [_P, _S, _I, _I64, _I64, _S, _I64, _I64],
+    "psc_add_kernel": [_P, _S, _I, C.POINTER(_S), _I, C.POINTER(_S), _I,
+                       C.POINTER(psc_kernel_params), C.POINTER(_I)],
+    "psc_add_edge": [_P, _I, _S, _I, _S],
+    "psc_set_component": [_P, _I, _I],
+    "psc_bind_device": [_P, _S, _P, C.c_size_t],
+    "psc_dag_info": [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
+    "psc_buffer_id": [_P, _S, C.POINTER(_I)],
+    "psc_dag_classify": [_P, _I, C.POINTER(_I), C.POINTER(_I)],
+    "psc_schedule": [_P, _I, C.POINTER(psc_sched_opts), C.POINTER(_P)],
+    "psc_sched_export": [_P, C.POINTER(psc_op), _I, C.POINTER(_I), C.POINTER(_I), _I,
+                         C.POINTER(_I)],
+    "psc_sched_streams": [_P, C.POINTER(_I)],
+    "psc_sched_prepare": [_P],
+    "psc_run": [_P, C.POINTER(psc_host_io), _I, C.POINTER(psc_run_stats)],
+    "psc_sched_op_times": [_P, C.POINTER(psc_op_time), _I, C.POINTER(_I)],
+    "psc_sched_device_ptr": [_P, _S, C.POINTER(_P), C.POINTER(_I64)],
+    "psc_kernel_time": [_P, _I, _I, C.POINTER(C.c_float)],
+    "psc_sched_destroy": [_P],
+    "psc_host_alloc": [C.c_size_t, C.POINTER(_P)],
+    "psc_host_free": [_P],
+    "psc_device_sync": [_I],
+    "psc_sched_dispatch_trace": [_P, _I, _I, C.c_uint32, C.POINTER(_I), _I, C.POINTER(_I)],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int32
+_lib.psc_last_error.argtypes = []
+_lib.psc_last_error.restype = C.c_char_p
+_lib.psc_abi_version.argtypes = []
+_lib.psc_abi_version.restype = C.c_int32
+
+EXPORTED = sorted(list(_SIGS) + ["psc_last_error", "psc_abi_version"])
+
+
+def _check(status):
+    if status != PSC_OK:
+        raise PscError(status, _lib.psc_last_error().decode())
+
+
+def _b(s):
+    return None if s is None else s.encode()
+
+
+# --- thin wrappers with the C names --------------------------------------------------------------
+def psc_abi_version():
+    return _lib.psc_abi_version()
+
+
+def psc_last_error():
+    return _lib.psc_last_error().decode()
+
+
+def psc_dag_create():
+    h = _P()
+    _check(_lib.psc_dag_create(C.byref(h)))
+    return h
+
+
+def psc_dag_destroy(dag):
+    _check(_lib.psc_dag_destroy(dag))
+
+
+def psc_add_buffer(dag, name, dtype, rows, cols, view_of=None, row_off=0, col_off=0):
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _check(_lib.psc_add_buffer(dag, _b(name), dt, int(rows), int(cols), _b(view_of), int(row_off),
+                               int(col_off)))
+
+
+def psc_add_kernel(dag, name, kind, inputs, outputs, alpha=None, tile=0):
+    k = KINDS[kind] if isinstance(kind, str) else int(kind)
+    ins = (_S * len(inputs))(*[_b(x) for x in inputs])
+    outs = (_S * len(outputs))(*[_b(x) for x in outputs])
+    p = psc_kernel_params(float(1.0 if alpha is None else alpha), 1, int(tile), 0)
+    kid = _I()
+    _check(_lib.psc_add_kernel(dag, _b(name), k, ins, len(inputs), outs, len(outputs), C.byref(p),
+                               C.byref(kid)))
+    return kid.value
+
+
+def psc_add_edge(dag, src_kernel, src_output, dst_kernel, dst_input):
+    _check(_lib.psc_add_edge(dag, int(src_kernel), _b(src_output), int(dst_kernel), _b(dst_input)))
+
+
+def psc_set_component(dag, kernel, component):
+    _check(_lib.psc_set_component(dag, int(kernel), int(component)))
+
+
+def psc_bind_device(dag, name, dptr, nbytes):
+    _check(_lib.psc_bind_device(dag, _b(name), C.c_void_p(int(dptr)), int(nbytes)))
+
+
+def psc_dag_info(dag):
+    a, b, c = _I(), _I(), _I()
+    _check(_lib.psc_dag_info(dag, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def psc_buffer_id(dag, name):
+    i = _I()
+    _check(_lib.psc_buffer_id(dag, _b(name), C.byref(i)))
+    return i.value
+
+
+def psc_dag_classify(dag, component):
+    nk, _, ne = psc_dag_info(dag)
+    kc = (_I * max(1, nk))()
+    ei = (_I * max(1, ne))()
+    _check(_lib.psc_dag_classify(dag, int(component), kc, ei))
+    return list(kc)[:nk], list(ei)[:ne]
+
+
+def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
+              device=0, cost=None, host_threads=0):
+    o = psc_sched_opts()
+    o.n_streams = int(n_streams)
+    o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
+    o.copy_stream = int(bool(copy_stream))
+    o.use_graph = int(bool(use_graph))
+    o.record_ops = int(bool(record_ops))
+    o.device = int(device)
+    o.cost = None if cost is None else C.c_void_p(int(cost.value if hasattr(cost, "value") else cost))
+    o.host_threads = int(host_threads)
+    return o
+
+
+def psc_schedule(dag, policy, opts=None, **kw):
+    pol = {"coarse": PSC_COARSE, "fine": PSC_FINE}[policy] if isinstance(policy, str) else int(policy)
+    o = opts if opts is not None else make_opts(**kw)
+    h = _P()
+    _check(_lib.psc_schedule(dag, pol, C.byref(o), C.byref(h)))
+    return h
+
+
+def psc_sched_export(sched):
+    n, nw = _I(), _I()
+    _check(_lib.psc_sched_export(sched, None, 0, C.byref(n), None, 0, C.byref(nw)))
+    ops = (psc_op * max(1, n.value))()
+    waits = (_I * max(1, nw.value))()
+    _check(_lib.psc_sched_export(sched, ops, n.value, C.byref(n), waits, nw.value, C.byref(nw)))
+    out = []
+    for i in range(n.value):
+        o = ops[i]
+        out.append({"id": o.id, "type": OP_TYPES[o.type], "kernel": o.kernel, "buffer": o.buffer,
+                    "stream": o.stream, "pos": o.pos, "host_order": o.host_order,
+                    "waits": [waits[o.wait_off + j] for j in range(o.n_waits)]})
+    return out
+
+
+def psc_sched_streams(sched):
+    n = _I()
+    _check(_lib.psc_sched_streams(sched, C.byref(n)))
+    return n.value
+
+
+def psc_sched_prepare(sched):
+    _check(_lib.psc_sched_prepare(sched))
+
+
+def psc_run(sched, io=()):
+    """io: iterable of (name, host_pointer, nbytes).  Returns psc_run_stats as a dict."""
+    io = list(io)
+    arr = (psc_host_io * max(1, len(io)))()
+    keep = []
+    for i, (name, ptr, nbytes) in enumerate(io):
+        nb = _b(name)
+        keep.append(nb)
+        arr[i] = psc_host_io(nb, C.c_void_p(int(ptr)), int(nbytes))
+    st = psc_run_stats()
+    _check(_lib.psc_run(sched, arr, len(io), C.byref(st)))
+    return {f: getattr(st, f) for f, _ in psc_run_stats._fields_}
+
+
+def psc_sched_op_times(sched):
+    n = _I()
+    _check(_lib.psc_sched_op_times(sched, None, 0, C.byref(n)))
+    buf = (psc_op_time * max(1, n.value))()
+    _check(_lib.psc_sched_op_times(sched, buf, n.value, C.byref(n)))
+    return [(t.op, t.stream, t.start_us, t.end_us) for t in buf[:n.value]]
+
+
+def psc_sched_device_ptr(sched, name):
+    p, ld = _P(), _I64()
+    _check(_lib.psc_sched_device_ptr(sched, _b(name), C.byref(p), C.byref(ld)))
+    return p.value, ld.value
+
+
+def psc_kernel_time(sched, kernel, iters=20):
+    t = C.c_float()
+    _check(_lib.psc_kernel_time(sched, int(kernel), int(iters), C.byref(t)))
+    return t.value
+
+
+def psc_sched_dispatch_trace(sched, host_threads=0, jitter_us=0, seed=0):
+    """Calls of the multi-threaded enqueue against a recording backend: [(kind, op, arg)]."""
+    n = _I()
+    cap = 3 * 16 * (len(psc_sched_export(sched)) + 64)
+    buf = (_I * cap)()
+    _check(_lib.psc_sched_dispatch_trace(sched, int(host_threads), int(jitter_us), int(seed), buf, cap,
+                                         C.byref(n)))
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n.value)]
+
+
+def psc_sched_destroy(sched):
+    _check(_lib.psc_sched_destroy(sched))
+
+
+# --- spec lowering and host marshalling ----------------------------------------------------------
+def build_dag(spec, bind=None):
+    """Lower a ``workloads`` DAG spec onto the C ABI; ``bind`` maps root names to (ptr, nbytes)."""
+    dag = psc_dag_create()
+    try:
+        for b in spec["buffers"]:
+            psc_add_buffer(dag, b["name"], b["dtype"], b["rows"], b["cols"], b["view_of"],
+                           b["row_off"], b["col_off"])
+        for k in spec["kernels"]:
+            psc_add_kernel(dag, k["name"], k["kind"], k["inputs"], k["outputs"], k.get("alpha", 1.0),
+                           k.get("tile", 0))
+        for (s, sb, t, tb) in spec["edges"]:
+            psc_add_edge(dag, s, sb, t, tb)
+        for i, c in enumerate(spec.get("component", [])):
+            if c:
+                psc_set_component(dag, i, c)
+        for name, (ptr, nbytes) in (bind or {}).items():
+            psc_bind_device(dag, name, ptr, nbytes)
+    except Exception:
+        psc_dag_destroy(dag)
+        raise
+    return dag
+
+
+def export_schedule(spec, sched):
+    """The exported schedule in the validator's format (buffer ids replaced by names)."""
+    names = [b["name"] for b in spec["buffers"]]
+    ops = psc_sched_export(sched)
+    for o in ops:
+        o["buffer"] = names[o["buffer"]] if o["buffer"] >= 0 else None
+    return {"n_streams": psc_sched_streams(sched), "ops": ops}
+
+
+def to_bf16_bits(arr):
+    """float32 array -> uint16 bfloat16 bit patterns (round to nearest even), via torch's CPU cast."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
+
+
+def from_bf16_bits(bits):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).view(torch.bfloat16)
+    return t.to(torch.float32).numpy()
+
+
+def psc_host_alloc(nbytes):
+    p = _P()
+    _check(_lib.psc_host_alloc(int(nbytes), C.byref(p)))
+    return p.value
+
+
+def psc_host_free(ptr):
+    _check(_lib.psc_host_free(C.c_void_p(ptr)))
+
+
+def psc_device_sync(device=0):
+    _check(_lib.psc_device_sync(int(device)))
+
+
+class HostBuffer:
+    """Page-locked host memory from psc_host_alloc, viewed as a rows x cols numpy array."""
+
+    def __init__(self, rows, cols, dtype):
+        self.dtype = dtype
+        es = 2 if dtype == "bf16" else 4
+        self.nbytes = int(rows) * int(cols) * es
+        self.ptr = psc_host_alloc(self.nbytes)
+        raw = (C.c_uint8 * max(1, self.nbytes)).from_address(self.ptr)
+        flat = np.frombuffer(raw, dtype=np.uint16 if es == 2 else np.float32,
+                             count=int(rows) * int(cols))
+        self.array = flat.reshape(int(rows), int(cols))
+
+    def set(self, values):
+        values = np.asarray(values, dtype=np.float32)
+        self.array[...] = to_bf16_bits(values) if self.dtype == "bf16" else values
+
+    def get(self):
+        a = self.array
+        return from_bf16_bits(a) if self.dtype == "bf16" else a.copy()
+
+    def free(self):
+        if self.ptr:
+            psc_host_free(self.ptr)
+            self.ptr = None
+            self.array = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class SpecRunner:
+    """A scheduled spec with page-locked host staging for its inputs and outputs."""
+
+    def __init__(self, spec, policy="fine", **opts):
+        import workloads
+        self.spec = spec
+        self.by = {b["name"]: b for b in spec["buffers"]}
+        self.dag = build_dag(spec)
+        self.sched = psc_schedule(self.dag, policy, **opts)
+        self.in_names = workloads.host_inputs_of(spec)
+        self.out_names = workloads.host_outputs_of(spec)
+        self.outputs = {n: HostBuffer(self.by[n]["rows"], self.by[n]["cols"], self.by[n]["dtype"])
+                        for n in self.out_names}
+        self.inputs = {}
+
+    def set_inputs(self, inputs):
+        for n in self.in_names:
+            if n in inputs:
+                if n not in self.inputs:
+                    b = self.by[n]
+                    self.inputs[n] = HostBuffer(b["rows"], b["cols"], b["dtype"])
+                self.inputs[n].set(inputs[n])
+
+    def io(self, with_inputs=True, with_outputs=True):
+        out = []
+        if with_inputs:
+            out += [(n, h.ptr, h.nbytes) for n, h in self.inputs.items()]
+        if with_outputs:
+            out += [(n, h.ptr, h.nbytes) for n, h in self.outputs.items()]
+        return out
+
+    def run(self, with_inputs=True, with_outputs=True):
+        return psc_run(self.sched, self.io(with_inputs, with_outputs))
+
+    def result(self, name):
+        return self.outputs[name].get()
+
+    def export(self):
+        return export_schedule(self.spec, self.sched)
+
+    def close(self):
+        if self.sched is not None:
+            psc_sched_destroy(self.sched)
+            self.sched = None
+        if self.dag is not None:
+            psc_dag_destroy(self.dag)
+            self.dag = None
+        for h in list(self.inputs.values()) + list(self.outputs.values()):
+            h.free()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_spec(spec, inputs, policy="fine", **opts):
+    """Schedule and run ``spec`` once on ``inputs``; returns ({output name: float32 array}, stats)."""
+    r = SpecRunner(spec, policy, **opts)
+    try:
+        r.set_inputs(inputs)
+        stats = r.run()
+        return {n: r.result(n) for n in r.out_names}, stats
+    finally:
+        r.close()

@@ -1,0 +1,395 @@
+// extern "C" entry points declared in include/psc.h.  Each call converts internal errors into a
+// psc_status and a thread-local message; no exception crosses the boundary.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include <mutex>
+#include <random>
+#include <thread>
+
+#include "core.hpp"
+#include "dispatch.hpp"
+
+namespace psc {
+void prepare(psc_sched &s);
+void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats);
+void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n);
+void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
+float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
+void *host_alloc(size_t bytes);
+void host_free(void *p);
+void device_sync(int device);
+}  // namespace psc
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+psc_status guard(F &&f) {
+  try {
+    f();
+    g_err.clear();
+    return PSC_OK;
+  } catch (const psc::Error &e) {
+    g_err = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return PSC_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return PSC_ERR_ARG;
+  } catch (...) {
+    g_err = "unknown error";
+    return PSC_ERR_ARG;
+  }
+}
+
+void need(bool cond, psc_status st, const char *msg) {
+  if (!cond) psc::fail(st, msg);
+}
+
+void not_frozen(const psc::Dag &g) {
+  if (g.frozen) psc::fail(PSC_ERR_STATE, "the DAG is frozen: it has been scheduled");
+}
+
+int32_t find_buffer(const psc::Dag &g, const char *name) {
+  need(name != nullptr, PSC_ERR_ARG, "NULL buffer name");
+  auto it = g.buf_by_name.find(name);
+  if (it == g.buf_by_name.end()) psc::fail(PSC_ERR_NAME, std::string("unknown buffer '") + name + "'");
+  return it->second;
+}
+
+psc_sched_opts default_opts() {
+  psc_sched_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.n_streams = 4;
+  o.mapper = PSC_MAP_RR;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+psc_status psc_dag_create(psc_dag **out) {
+  return guard([&] {
+    need(out != nullptr, PSC_ERR_ARG, "NULL out");
+    *out = new psc_dag();
+  });
+}
+
+psc_status psc_dag_destroy(psc_dag *dag) {
+  return guard([&] {
+    if (!dag) return;
+    if (dag->g.live_scheds) psc::fail(PSC_ERR_STATE, "destroy every schedule of this DAG first");
+    delete dag;
+  });
+}
+
+psc_status psc_add_buffer(psc_dag *dag, const char *name, int32_t dtype, int64_t rows, int64_t cols,
+                          const char *view_of, int64_t row_off, int64_t col_off) {
+  return guard([&] {
+    need(dag && name, PSC_ERR_ARG, "NULL argument");
+    psc::Dag &g = dag->g;
+    not_frozen(g);
+    need(dtype == PSC_F32 || dtype == PSC_BF16, PSC_ERR_ARG, "dtype must be PSC_F32 or PSC_BF16");
+    need(rows >= 0 && cols >= 0 && rows < (int64_t(1) << 31) && cols < (int64_t(1) << 31), PSC_ERR_ARG,
+         "rows and cols must be in [0, 2^31)");
+    need(std::strlen(name) > 0, PSC_ERR_NAME, "empty buffer name");
+    if (g.buf_by_name.count(name)) psc::fail(PSC_ERR_NAME, std::string("duplicate buffer '") + name + "'");
+    psc::Buffer b;
+    b.name = name;
+    b.dtype = dtype;
+    b.rows = rows;
+    b.cols = cols;
+    const int32_t id = static_cast<int32_t>(g.bufs.size());
+    if (view_of) {
+      const int32_t p = find_buffer(g, view_of);
+      const psc::Buffer &pb = g.bufs[p];
+      need(row_off >= 0 && col_off >= 0 && row_off + rows <= pb.rows && col_off + cols <= pb.cols,
+           PSC_ERR_SHAPE, "view window lies outside its parent");
+      need(pb.dtype == dtype, PSC_ERR_SHAPE, "a view must have its parent's dtype");
+      b.parent = p;
+      b.root = pb.root;
+      b.r0 = pb.r0 + row_off;
+      b.c0 = pb.c0 + col_off;
+    } else {
+      need(row_off == 0 && col_off == 0, PSC_ERR_ARG, "offsets need view_of");
+      b.root = id;
+    }
+    g.bufs.push_back(b);
+    g.buf_by_name[b.name] = id;
+  });
+}
+
+psc_status psc_add_kernel(psc_dag *dag, const char *name, int32_t kind, const char *const *inputs, int32_t n_in,
+                          const char *const *outputs, int32_t n_out, const psc_kernel_params *params,
+                          int32_t *kernel_id) {
+  return guard([&] {
+    need(dag && name, PSC_ERR_ARG, "NULL argument");
+    psc::Dag &g = dag->g;
+    not_frozen(g);
+    need(kind >= PSC_GEMM && kind <= PSC_ADD, PSC_ERR_ARG, "unknown kernel kind");
+    const int want_in = (kind == PSC_GEMM || kind == PSC_ADD) ? 2 : 1;
+    if (n_in != want_in || n_out != 1)
+      psc::fail(PSC_ERR_ARG, std::string("kernel '") + name + "': wrong number of inputs or outputs for its kind");
+    need(inputs && outputs, PSC_ERR_ARG, "NULL operand list");
+    need(std::strlen(name) > 0, PSC_ERR_NAME, "empty kernel name");
+    if (g.ker_by_name.count(name)) psc::fail(PSC_ERR_NAME, std::string("duplicate kernel '") + name + "'");
+    psc::Kernel k;
+    k.name = name;
+    k.kind = kind;
+    for (int32_t i = 0; i < n_in; ++i) k.ins.push_back(find_buffer(g, inputs[i]));
+    for (int32_t i = 0; i < n_out; ++i) k.outs.push_back(find_buffer(g, outputs[i]));
+    if (params) {
+      if (params->alpha_set || params->alpha != 0.0f) k.alpha = params->alpha;
+      k.tile = params->tile;
+    }
+    const int32_t id = static_cast<int32_t>(g.kers.size());
+    g.kers.push_back(k);
+    g.ker_by_name[k.name] = id;
+    if (kernel_id) *kernel_id = id;
+  });
+}
+
+psc_status psc_add_edge(psc_dag *dag, int32_t src_kernel, const char *src_output, int32_t dst_kernel,
+                        const char *dst_input) {
+  return guard([&] {
+    need(dag && src_output && dst_input, PSC_ERR_ARG, "NULL argument");
+    psc::Dag &g = dag->g;
+    not_frozen(g);
+    const int32_t nk = static_cast<int32_t>(g.kers.size());
+    need(src_kernel >= 0 && src_kernel < nk && dst_kernel >= 0 && dst_kernel < nk, PSC_ERR_ARG, "kernel id out of range");
+    const int32_t sb = find_buffer(g, src_output), db = find_buffer(g, dst_input);
+    const auto &so = g.kers[src_kernel].outs;
+    const auto &di = g.kers[dst_kernel].ins;
+    if (std::find(so.begin(), so.end(), sb) == so.end())
+      psc::fail(PSC_ERR_NAME, std::string("'") + src_output + "' is not an output of kernel '" + g.kers[src_kernel].name + "'");
+    if (std::find(di.begin(), di.end(), db) == di.end())
+      psc::fail(PSC_ERR_NAME, std::string("'") + dst_input + "' is not an input of kernel '" + g.kers[dst_kernel].name + "'");
+    if (!g.bufs[sb].region().overlaps(g.bufs[db].region()))
+      psc::fail(PSC_ERR_SHAPE, std::string("edge joins '") + src_output + "' and '" + dst_input + "', which share no storage");
+    g.edges.push_back({src_kernel, sb, dst_kernel, db});
+  });
+}
+
+psc_status psc_set_component(psc_dag *dag, int32_t kernel, int32_t component) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    not_frozen(dag->g);
+    need(kernel >= 0 && kernel < int32_t(dag->g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
+    need(component >= 0, PSC_ERR_ARG, "component must be >= 0");
+    dag->g.kers[kernel].component = component;
+  });
+}
+
+psc_status psc_bind_device(psc_dag *dag, const char *name, void *dptr, size_t bytes) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    psc::Dag &g = dag->g;
+    not_frozen(g);
+    const int32_t b = find_buffer(g, name);
+    psc::Buffer &x = g.bufs[b];
+    if (x.parent >= 0) psc::fail(PSC_ERR_NAME, std::string("'") + name + "' is a view; bind its root");
+    need(dptr != nullptr, PSC_ERR_ARG, "NULL device pointer");
+    need(bytes >= size_t(x.rows) * x.cols * psc::elem_size(x.dtype), PSC_ERR_ARG, "device memory too small");
+    x.bound = dptr;
+    x.bound_bytes = bytes;
+  });
+}
+
+psc_status psc_dag_info(const psc_dag *dag, int32_t *n_kernels, int32_t *n_buffers, int32_t *n_edges) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    if (n_kernels) *n_kernels = int32_t(dag->g.kers.size());
+    if (n_buffers) *n_buffers = int32_t(dag->g.bufs.size());
+    if (n_edges) *n_edges = int32_t(dag->g.edges.size());
+  });
+}
+
+psc_status psc_buffer_id(const psc_dag *dag, const char *name, int32_t *id) {
+  return guard([&] {
+    need(dag && id, PSC_ERR_ARG, "NULL argument");
+    *id = find_buffer(dag->g, name);
+  });
+}
+
+psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass, int32_t *edge_inter) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    dag->g.validate();
+    dag->g.classify(component, kclass, edge_inter);
+  });
+}
+
+psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, psc_sched **out) {
+  return guard([&] {
+    need(dag && out, PSC_ERR_ARG, "NULL argument");
+    need(policy == PSC_COARSE || policy == PSC_FINE, PSC_ERR_ARG, "policy must be PSC_COARSE or PSC_FINE");
+    psc_sched_opts o = opts ? *opts : default_opts();
+    if (policy == PSC_COARSE) o.n_streams = 1;
+    need(o.n_streams >= 1 && o.n_streams <= 64, PSC_ERR_ARG, "n_streams must be in [1, 64]");
+    need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
+    need(!(o.use_graph && o.record_ops), PSC_ERR_ARG, "record_ops cannot be combined with use_graph");
+    need(o.device >= 0, PSC_ERR_ARG, "negative device");
+    psc::Dag &g = dag->g;
+    if (!g.validated || !g.frozen) g.validate();
+    g.frozen = true;
+    auto s = std::make_unique<psc_sched>();
+    s->dag = dag;
+    s->opts = o;
+    s->policy = policy;
+    s->plan = psc::build_plan(g, policy, o);
+    ++g.live_scheds;
+    *out = s.release();
+  });
+}
+
+psc_status psc_sched_export(const psc_sched *sched, psc_op *ops, int32_t cap, int32_t *n_ops, int32_t *waits,
+                            int32_t waits_cap, int32_t *n_waits) {
+  return guard([&] {
+    need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    const auto &P = sched->plan.ops;
+    int32_t nw = 0;
+    for (const auto &op : P) nw += int32_t(op.waits.size());
+    if (n_ops) *n_ops = int32_t(P.size());
+    if (n_waits) *n_waits = nw;
+    if (ops && waits) {
+      need(cap >= int32_t(P.size()) && waits_cap >= nw, PSC_ERR_ARG, "capacity too small");
+      int32_t off = 0;
+      for (size_t i = 0; i < P.size(); ++i) {
+        const auto &op = P[i];
+        ops[i] = psc_op{int32_t(i), op.type, op.kernel, op.buffer, op.stream, op.pos, op.host_order,
+                        int32_t(op.waits.size()), off};
+        for (int32_t w : op.waits) waits[off++] = w;
+      }
+    }
+  });
+}
+
+psc_status psc_sched_streams(const psc_sched *sched, int32_t *n_streams) {
+  return guard([&] {
+    need(sched && n_streams, PSC_ERR_ARG, "NULL argument");
+    *n_streams = sched->plan.total_streams;
+  });
+}
+
+psc_status psc_sched_prepare(psc_sched *sched) {
+  return guard([&] {
+    need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    psc::prepare(*sched);
+  });
+}
+
+psc_status psc_run(psc_sched *sched, const psc_host_io *io, int32_t n_io, psc_run_stats *stats) {
+  return guard([&] {
+    need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    need(n_io >= 0 && (n_io == 0 || io), PSC_ERR_ARG, "bad io list");
+    psc::run(*sched, io, n_io, stats);
+  });
+}
+
+psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t cap, int32_t *n) {
+  return guard([&] {
+    need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    psc::op_times(*sched, out, cap, n);
+  });
+}
+
+psc_status psc_sched_device_ptr(const psc_sched *sched, const char *name, void **dptr, int64_t *ld) {
+  return guard([&] {
+    need(sched && name, PSC_ERR_ARG, "NULL argument");
+    psc::device_ptr(*sched, name, dptr, ld);
+  });
+}
+
+psc_status psc_kernel_time(psc_sched *sched, int32_t kernel, int32_t iters, float *avg_us) {
+  return guard([&] {
+    need(sched && avg_us, PSC_ERR_ARG, "NULL argument");
+    need(kernel >= 0 && kernel < int32_t(sched->dag->g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
+    need(iters >= 1, PSC_ERR_ARG, "iters must be >= 1");
+    *avg_us = psc::kernel_time(*sched, kernel, iters);
+  });
+}
+
+psc_status psc_host_alloc(size_t bytes, void **out) {
+  return guard([&] {
+    need(out != nullptr, PSC_ERR_ARG, "NULL out");
+    *out = psc::host_alloc(bytes);
+  });
+}
+
+psc_status psc_host_free(void *ptr) {
+  return guard([&] { psc::host_free(ptr); });
+}
+
+psc_status psc_device_sync(int32_t device) {
+  return guard([&] {
+    need(device >= 0, PSC_ERR_ARG, "negative device");
+    psc::device_sync(device);
+  });
+}
+
+namespace {
+struct TraceBackend final : psc::Backend {
+  std::mutex m;
+  std::vector<int32_t> ev;
+  int32_t jitter_us;
+  uint32_t seed;
+  explicit TraceBackend(int32_t j, uint32_t s) : jitter_us(j), seed(s) {}
+  void jitter(int32_t salt) {
+    if (jitter_us <= 0) return;
+    thread_local std::mt19937 rng;
+    thread_local bool seeded = false;
+    if (!seeded) {
+      rng.seed(seed ^ (uint32_t(std::hash<std::thread::id>()(std::this_thread::get_id())) + uint32_t(salt)));
+      seeded = true;
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(rng() % uint32_t(jitter_us + 1)));
+  }
+  void push(int32_t a, int32_t b, int32_t c) {
+    std::lock_guard<std::mutex> lk(m);
+    ev.insert(ev.end(), {a, b, c});
+  }
+  void wait(int32_t op, int32_t awaited) override { jitter(op); push(0, op, awaited); }
+  void exec(int32_t op) override { jitter(op); push(1, op, -1); }
+  void record(int32_t op) override { jitter(op); push(2, op, -1); }
+  void stream_done(int32_t stream) override { push(3, -1, stream); }
+};
+}  // namespace
+
+psc_status psc_sched_dispatch_trace(const psc_sched *sched, int32_t host_threads, int32_t jitter_us, uint32_t seed,
+                                    int32_t *out, int32_t cap, int32_t *n) {
+  return guard([&] {
+    need(sched && n, PSC_ERR_ARG, "NULL argument");
+    need(host_threads >= 0 && jitter_us >= 0, PSC_ERR_ARG, "negative argument");
+    const int32_t nt = host_threads > 0 ? host_threads : sched->plan.total_streams;
+    psc::Dispatcher disp(sched->plan, nt);
+    TraceBackend tb(jitter_us, seed);
+    disp.run(tb);
+    *n = int32_t(tb.ev.size() / 3);
+    if (out) {
+      need(cap >= int32_t(tb.ev.size()), PSC_ERR_ARG, "capacity too small");
+      std::copy(tb.ev.begin(), tb.ev.end(), out);
+    }
+  });
+}
+
+psc_status psc_sched_destroy(psc_sched *sched) {
+  return guard([&] {
+    if (!sched) return;
+    --sched->dag->g.live_scheds;
+    delete sched;
+  });
+}
+
+const char *psc_last_error(void) { return g_err.c_str(); }
+
+int32_t psc_abi_version(void) { return PSC_ABI_VERSION; }
+
+}  // extern "C"

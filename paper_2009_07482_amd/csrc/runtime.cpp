@@ -1,0 +1,440 @@
+// Stream/event dispatcher (the dispatch step of Algorithm 1, Sec. IV-B) on HIP.
+//
+// prepare(): one device arena for every unbound root buffer, the schedule's streams (default
+// priority, non-blocking), one event per op that another stream waits for, and a prepared launch
+// per kernel.  run(): record a start event, make every stream wait for it, enqueue the ops in host
+// order -- each wait is a hipStreamWaitEvent on the producing op's event, which HIP requires to
+// have been recorded (enqueued) earlier, so host order is topological -- then join every stream
+// into stream 0, record the end event and wait for it.  In graph mode the same enqueue sequence
+// is built once as an explicit hipGraph (a node per op, an edge per precedence) and replayed with
+// one hipGraphLaunch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "core.hpp"
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace psc {
+
+#define PSC_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) fail(PSC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct CopyDesc {  // one resolved host copy
+  bool active = false;
+  void *dst = nullptr;
+  const void *src = nullptr;
+  size_t dpitch = 0, spitch = 0, width = 0, height = 0;
+  hipMemcpyKind kind = hipMemcpyHostToDevice;
+};
+
+struct Device {
+  int device = 0;
+  void *arena = nullptr;
+  std::vector<char *> base;  // per buffer id (roots only): device storage
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> op_ev;
+  std::vector<hipEvent_t> join_ev;
+  hipEvent_t start = nullptr, end = nullptr;
+  std::vector<hipEvent_t> t0, t1;  // per-op timing (record_ops)
+  std::vector<Launch> launch;      // per kernel id
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> graph_key;
+  std::vector<psc_op_time> times;
+  bool have_times = false;
+  std::unique_ptr<Dispatcher> disp;
+
+  ~Device() {
+    disp.reset();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : op_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t0)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t1)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {start, end})
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : streams)
+      if (s) (void)hipStreamDestroy(s);
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+namespace {
+
+char *buffer_ptr(const Dag &g, const Device &d, int32_t b) {
+  const Buffer &x = g.bufs[b];
+  const Buffer &r = g.bufs[x.root];
+  return d.base[x.root] + (x.r0 * r.cols + x.c0) * elem_size(r.dtype);
+}
+int64_t buffer_ld(const Dag &g, int32_t b) { return g.bufs[g.bufs[b].root].cols; }
+
+void build_launch(const Dag &g, const Device &d, int32_t k, Launch &L) {
+  const Kernel &ker = g.kers[k];
+  auto P = [&](int32_t b) { return buffer_ptr(g, d, b); };
+  auto LD = [&](int32_t b) { return buffer_ld(g, b); };
+  bool ok = false;
+  switch (ker.kind) {
+    case PSC_GEMM: {
+      const Buffer &a = g.bufs[ker.ins[0]], &b = g.bufs[ker.ins[1]], &c = g.bufs[ker.outs[0]];
+      GemmArgs ga{};
+      ga.A = P(ker.ins[0]);
+      ga.B = P(ker.ins[1]);
+      ga.C = P(ker.outs[0]);
+      ga.lda = LD(ker.ins[0]);
+      ga.ldb = LD(ker.ins[1]);
+      ga.ldc = LD(ker.outs[0]);
+      ga.M = int32_t(a.rows);
+      ga.N = int32_t(b.cols);
+      ga.K = int32_t(a.cols);
+      ga.alpha = ker.alpha;
+      ok = make_gemm(L, ga, a.dtype, c.dtype, ker.tile);
+      break;
+    }
+    case PSC_SOFTMAX: {
+      const Buffer &x = g.bufs[ker.ins[0]], &y = g.bufs[ker.outs[0]];
+      SoftmaxArgs sa{P(ker.ins[0]), P(ker.outs[0]), LD(ker.ins[0]), LD(ker.outs[0]), int32_t(x.rows), int32_t(x.cols)};
+      ok = make_softmax(L, sa, x.dtype, y.dtype);
+      break;
+    }
+    case PSC_TRANSPOSE: {
+      const Buffer &x = g.bufs[ker.ins[0]];
+      TransArgs ta{P(ker.ins[0]), P(ker.outs[0]), LD(ker.ins[0]), LD(ker.outs[0]), int32_t(x.rows), int32_t(x.cols)};
+      ok = make_transpose(L, ta, x.dtype);
+      break;
+    }
+    case PSC_ADD: {
+      const Buffer &x = g.bufs[ker.ins[0]], &c = g.bufs[ker.outs[0]];
+      AddArgs aa{P(ker.ins[0]), P(ker.ins[1]), P(ker.outs[0]), LD(ker.ins[0]), LD(ker.ins[1]), LD(ker.outs[0]),
+                 int32_t(x.rows), int32_t(x.cols)};
+      ok = make_add(L, aa, x.dtype, c.dtype);
+      break;
+    }
+  }
+  if (!ok) fail(PSC_ERR_UNSUPPORTED, "no kernel instance for '" + ker.name + "'");
+}
+
+void launch(const Launch &L, hipStream_t s) {
+  if (L.empty) return;
+  void *args[] = {const_cast<unsigned char *>(L.args)};
+  PSC_HIP(hipLaunchKernel(L.func, L.grid, L.block, args, L.shmem, s));
+}
+
+}  // namespace
+
+void prepare(psc_sched &s) {
+  if (s.dev) return;
+  const Dag &g = s.dag->g;
+  auto d = std::make_unique<Device>();
+  d->device = s.opts.device;
+  PSC_HIP(hipSetDevice(d->device));
+  // arena for unbound roots, 256-byte aligned slots
+  std::vector<size_t> off(g.bufs.size(), 0);
+  size_t total = 0;
+  for (size_t b = 0; b < g.bufs.size(); ++b) {
+    const Buffer &x = g.bufs[b];
+    if (x.parent >= 0 || x.bound) continue;
+    off[b] = total;
+    total += (size_t(x.rows) * x.cols * elem_size(x.dtype) + 255) & ~size_t(255);
+  }
+  if (total) {
+    hipError_t e = hipMalloc(&d->arena, total);
+    if (e != hipSuccess) fail(PSC_ERR_OOM, "hipMalloc of " + std::to_string(total) + " bytes: " + hipGetErrorString(e));
+  }
+  d->base.assign(g.bufs.size(), nullptr);
+  for (size_t b = 0; b < g.bufs.size(); ++b) {
+    const Buffer &x = g.bufs[b];
+    if (x.parent >= 0) continue;
+    d->base[b] = x.bound ? static_cast<char *>(x.bound) : static_cast<char *>(d->arena) + off[b];
+  }
+  d->streams.assign(s.plan.total_streams, nullptr);
+  for (auto &st : d->streams) PSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  d->op_ev.assign(s.plan.ops.size(), nullptr);
+  for (size_t i = 0; i < s.plan.ops.size(); ++i)
+    if (s.plan.ops[i].recorded) PSC_HIP(hipEventCreateWithFlags(&d->op_ev[i], hipEventDisableTiming));
+  d->join_ev.assign(s.plan.total_streams, nullptr);
+  for (auto &e : d->join_ev) PSC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  PSC_HIP(hipEventCreate(&d->start));
+  PSC_HIP(hipEventCreate(&d->end));
+  if (s.opts.record_ops) {
+    d->t0.assign(s.plan.ops.size(), nullptr);
+    d->t1.assign(s.plan.ops.size(), nullptr);
+    for (auto &e : d->t0) PSC_HIP(hipEventCreate(&e));
+    for (auto &e : d->t1) PSC_HIP(hipEventCreate(&e));
+  }
+  d->launch.assign(g.kers.size(), Launch{});
+  for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, *d, int32_t(k), d->launch[k]);
+  const int32_t nt = s.opts.host_threads > 0 ? s.opts.host_threads : s.plan.total_streams;
+  d->disp = std::make_unique<Dispatcher>(s.plan, nt);
+  s.dev = std::move(d);
+}
+
+namespace {
+
+// Resolve host copies: for every copy op, the io entry whose buffer covers the op's buffer.
+std::vector<CopyDesc> resolve_io(const psc_sched &s, const psc_host_io *io, int32_t n_io) {
+  const Dag &g = s.dag->g;
+  const Device &d = *s.dev;
+  std::vector<int32_t> io_buf(n_io, -1);
+  for (int32_t i = 0; i < n_io; ++i) {
+    if (!io[i].name) fail(PSC_ERR_ARG, "psc_host_io entry with NULL name");
+    auto it = g.buf_by_name.find(io[i].name);
+    if (it == g.buf_by_name.end()) fail(PSC_ERR_NAME, std::string("unknown buffer '") + io[i].name + "'");
+    const Buffer &b = g.bufs[it->second];
+    const size_t want = size_t(b.rows) * b.cols * elem_size(b.dtype);
+    if (io[i].bytes != want)
+      fail(PSC_ERR_ARG, "host buffer for '" + b.name + "' has " + std::to_string(io[i].bytes) +
+                            " bytes, expected " + std::to_string(want));
+    if (!io[i].host_ptr && want) fail(PSC_ERR_ARG, "NULL host pointer for '" + b.name + "'");
+    io_buf[i] = it->second;
+  }
+  std::vector<CopyDesc> cd(s.plan.ops.size());
+  std::vector<char> used(n_io, 0);
+  for (size_t o = 0; o < s.plan.ops.size(); ++o) {
+    const Op &op = s.plan.ops[o];
+    if (op.type == PSC_OP_KERNEL) continue;
+    const Buffer &b = g.bufs[op.buffer];
+    for (int32_t i = 0; i < n_io; ++i) {
+      const Buffer &e = g.bufs[io_buf[i]];
+      if (!e.region().covers(b.region())) continue;
+      const int64_t es = elem_size(b.dtype);
+      char *host = static_cast<char *>(io[i].host_ptr) + ((b.r0 - e.r0) * e.cols + (b.c0 - e.c0)) * es;
+      char *dev = buffer_ptr(g, d, op.buffer);
+      CopyDesc &c = cd[o];
+      c.active = b.rows > 0 && b.cols > 0;
+      c.width = size_t(b.cols) * es;
+      c.height = size_t(b.rows);
+      const size_t dev_pitch = size_t(buffer_ld(g, op.buffer)) * es;
+      const size_t host_pitch = size_t(e.cols) * es;
+      if (op.type == PSC_OP_H2D) {
+        c.dst = dev; c.dpitch = dev_pitch; c.src = host; c.spitch = host_pitch; c.kind = hipMemcpyHostToDevice;
+      } else {
+        c.dst = host; c.dpitch = host_pitch; c.src = dev; c.spitch = dev_pitch; c.kind = hipMemcpyDeviceToHost;
+      }
+      used[i] = 1;
+      break;
+    }
+  }
+  for (int32_t i = 0; i < n_io; ++i)
+    if (!used[i]) fail(PSC_ERR_NAME, std::string("'") + io[i].name + "' covers no isolated write or read of the schedule");
+  return cd;
+}
+
+void do_copy(const CopyDesc &c, hipStream_t st) {
+  if (!c.active) return;
+  if (c.dpitch == c.width && c.spitch == c.width)
+    PSC_HIP(hipMemcpyAsync(c.dst, c.src, c.width * c.height, c.kind, st));
+  else
+    PSC_HIP(hipMemcpy2DAsync(c.dst, c.dpitch, c.src, c.spitch, c.width, c.height, c.kind, st));
+}
+
+struct HipBackend final : Backend {
+  psc_sched &s;
+  Device &d;
+  const std::vector<CopyDesc> &cd;
+  bool timed;
+  HipBackend(psc_sched &s_, const std::vector<CopyDesc> &cd_, bool timed_)
+      : s(s_), d(*s_.dev), cd(cd_), timed(timed_) {}
+  hipStream_t st(int32_t op) const { return d.streams[s.plan.ops[op].stream]; }
+  void wait(int32_t op, int32_t awaited) override { PSC_HIP(hipStreamWaitEvent(st(op), d.op_ev[awaited], 0)); }
+  void exec(int32_t o) override {
+    const Op &op = s.plan.ops[o];
+    if (timed) PSC_HIP(hipEventRecord(d.t0[o], st(o)));
+    if (op.type == PSC_OP_KERNEL) launch(d.launch[op.kernel], st(o));
+    else do_copy(cd[o], st(o));
+    if (timed) PSC_HIP(hipEventRecord(d.t1[o], st(o)));
+  }
+  void record(int32_t o) override { PSC_HIP(hipEventRecord(d.op_ev[o], st(o))); }
+  void stream_done(int32_t stream) override {
+    if (stream != 0) PSC_HIP(hipEventRecord(d.join_ev[stream], d.streams[stream]));
+  }
+};
+
+void fork_streams(Device &d, hipEvent_t ev) {
+  for (size_t i = 1; i < d.streams.size(); ++i) PSC_HIP(hipStreamWaitEvent(d.streams[i], ev, 0));
+}
+
+void join_streams(Device &d) {  // join events were recorded by the dispatch threads
+  for (size_t i = 1; i < d.streams.size(); ++i) PSC_HIP(hipStreamWaitEvent(d.streams[0], d.join_ev[i], 0));
+}
+
+}  // namespace
+
+namespace {
+
+// The schedule as an explicit graph: one node per op; its dependencies are the previous op on the
+// same stream and the ops it waits for, so the graph has exactly the schedule's precedences.
+void build_graph(psc_sched &s, const std::vector<CopyDesc> &cd) {
+  Device &d = *s.dev;
+  PSC_HIP(hipGraphCreate(&d.graph, 0));
+  const size_t n = s.plan.ops.size();
+  std::vector<hipGraphNode_t> node(n, nullptr), last(s.plan.total_streams, nullptr);
+  std::vector<hipGraphNode_t> deps;
+  for (size_t o = 0; o < n; ++o) {
+    const Op &op = s.plan.ops[o];
+    deps.clear();
+    if (last[op.stream]) deps.push_back(last[op.stream]);
+    for (int32_t w : op.waits) deps.push_back(node[w]);
+    hipGraphNode_t nd = nullptr;
+    const hipGraphNode_t *dp = deps.empty() ? nullptr : deps.data();
+    if (op.type == PSC_OP_KERNEL && !d.launch[op.kernel].empty) {
+      const Launch &L = d.launch[op.kernel];
+      void *args[] = {const_cast<unsigned char *>(L.args)};
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void *>(L.func);
+      kp.gridDim = L.grid;
+      kp.blockDim = L.block;
+      kp.sharedMemBytes = L.shmem;
+      kp.kernelParams = args;
+      kp.extra = nullptr;
+      PSC_HIP(hipGraphAddKernelNode(&nd, d.graph, dp, deps.size(), &kp));
+    } else if (op.type != PSC_OP_KERNEL && cd[o].active) {
+      const CopyDesc &c = cd[o];
+      if (c.dpitch == c.width && c.spitch == c.width) {
+        PSC_HIP(hipGraphAddMemcpyNode1D(&nd, d.graph, dp, deps.size(), c.dst, c.src, c.width * c.height, c.kind));
+      } else {
+        hipMemcpy3DParms mp{};
+        mp.srcPtr = make_hipPitchedPtr(const_cast<void *>(c.src), c.spitch, c.width, c.height);
+        mp.dstPtr = make_hipPitchedPtr(c.dst, c.dpitch, c.width, c.height);
+        mp.extent = make_hipExtent(c.width, c.height, 1);
+        mp.kind = c.kind;
+        PSC_HIP(hipGraphAddMemcpyNode(&nd, d.graph, dp, deps.size(), &mp));
+      }
+    } else {
+      PSC_HIP(hipGraphAddEmptyNode(&nd, d.graph, dp, deps.size()));
+    }
+    node[o] = nd;
+    last[op.stream] = nd;
+  }
+  PSC_HIP(hipGraphInstantiate(&d.exec, d.graph, nullptr, nullptr, 0));
+}
+
+}  // namespace
+
+void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats) {
+  prepare(s);
+  Device &d = *s.dev;
+  PSC_HIP(hipSetDevice(d.device));
+  const std::vector<CopyDesc> cd = resolve_io(s, io, n_io);
+  const bool timed = s.opts.record_ops != 0;
+  hipStream_t s0 = d.streams[0];
+  double host_ms = 0;
+  if (s.opts.use_graph) {
+    std::vector<const void *> key;
+    for (const CopyDesc &c : cd) key.push_back(c.active ? (c.kind == hipMemcpyHostToDevice ? c.src : c.dst) : nullptr);
+    if (!d.exec || key != d.graph_key) {
+      if (d.exec) { PSC_HIP(hipGraphExecDestroy(d.exec)); d.exec = nullptr; }
+      if (d.graph) { PSC_HIP(hipGraphDestroy(d.graph)); d.graph = nullptr; }
+      build_graph(s, cd);
+      d.graph_key = key;
+    }
+    const auto h0 = std::chrono::steady_clock::now();
+    PSC_HIP(hipEventRecord(d.start, s0));
+    PSC_HIP(hipGraphLaunch(d.exec, s0));
+    PSC_HIP(hipEventRecord(d.end, s0));
+    host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  } else {
+    const auto h0 = std::chrono::steady_clock::now();
+    PSC_HIP(hipEventRecord(d.start, s0));
+    fork_streams(d, d.start);
+    HipBackend backend(s, cd, timed);
+    d.disp->run(backend);
+    join_streams(d);
+    PSC_HIP(hipEventRecord(d.end, s0));
+    host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  }
+  PSC_HIP(hipEventSynchronize(d.end));
+  float ms = 0;
+  PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
+  if (timed) {
+    d.times.resize(s.plan.ops.size());
+    for (size_t o = 0; o < s.plan.ops.size(); ++o) {
+      float a = 0, b = 0;
+      PSC_HIP(hipEventElapsedTime(&a, d.start, d.t0[o]));
+      PSC_HIP(hipEventElapsedTime(&b, d.start, d.t1[o]));
+      d.times[o] = psc_op_time{int32_t(o), s.plan.ops[o].stream, a * 1000.f, b * 1000.f};
+    }
+    d.have_times = true;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->makespan_ms = ms;
+    stats->host_enqueue_ms = host_ms;
+    stats->n_ops = int32_t(s.plan.ops.size());
+    for (const Op &op : s.plan.ops) {
+      stats->n_kernels += op.type == PSC_OP_KERNEL;
+      stats->n_h2d += op.type == PSC_OP_H2D;
+      stats->n_d2h += op.type == PSC_OP_D2H;
+      stats->n_waits += int32_t(op.waits.size());
+    }
+    stats->n_streams = s.plan.total_streams;
+    stats->graph = s.opts.use_graph != 0;
+  }
+}
+
+void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n) {
+  if (!s.dev || !s.dev->have_times) fail(PSC_ERR_STATE, "no recorded run (set record_ops and call psc_run)");
+  const auto &t = s.dev->times;
+  if (n) *n = int32_t(t.size());
+  if (out) {
+    if (cap < int32_t(t.size())) fail(PSC_ERR_ARG, "capacity too small");
+    std::copy(t.begin(), t.end(), out);
+  }
+}
+
+void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) {
+  if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
+  const Dag &g = s.dag->g;
+  auto it = g.buf_by_name.find(name);
+  if (it == g.buf_by_name.end()) fail(PSC_ERR_NAME, std::string("unknown buffer '") + name + "'");
+  if (dptr) *dptr = buffer_ptr(g, *s.dev, it->second);
+  if (ld) *ld = buffer_ld(g, it->second);
+}
+
+void *host_alloc(size_t bytes) {
+  void *p = nullptr;
+  hipError_t e = hipHostMalloc(&p, bytes ? bytes : 1, hipHostMallocDefault);
+  if (e != hipSuccess) fail(PSC_ERR_OOM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  return p;
+}
+
+void host_free(void *p) {
+  if (p) PSC_HIP(hipHostFree(p));
+}
+
+void device_sync(int device) {
+  PSC_HIP(hipSetDevice(device));
+  PSC_HIP(hipDeviceSynchronize());
+}
+
+float kernel_time(psc_sched &s, int32_t kernel, int32_t iters) {
+  prepare(s);
+  Device &d = *s.dev;
+  PSC_HIP(hipSetDevice(d.device));
+  const Op &op = s.plan.ops[s.plan.kernel_op[kernel]];
+  hipStream_t st = d.streams[op.stream];
+  PSC_HIP(hipEventRecord(d.start, st));
+  for (int32_t i = 0; i < iters; ++i) launch(d.launch[kernel], st);
+  PSC_HIP(hipEventRecord(d.end, st));
+  PSC_HIP(hipEventSynchronize(d.end));
+  float ms = 0;
+  PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
+  return ms * 1000.f / float(std::max(1, iters));
+}
+
+}  // namespace psc
+
+psc_sched::psc_sched() = default;
+psc_sched::~psc_sched() = default;

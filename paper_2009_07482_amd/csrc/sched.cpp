@@ -1,0 +1,211 @@
+// Command-queue setup (setup_cq of Sec. IV-B, Algorithm 1) for one GPU.
+//
+// Every policy produces a kernel order, which is a topological order (Def. 5), and a stream per
+// kernel.  Ops are then emitted per kernel following the enq rules of Sec. III: the kernel's
+// isolated writes before its ndrange on its stream, its isolated reads right after it.  All
+// kernels share one device here, so the dependent copies of inter edges are not needed: a
+// consumer reads the producer's output where it lies.  Cross-stream precedences (rules (i)-(iii))
+// become waits on the producing op; a vector clock per op drops waits already implied by stream
+// order or by other waits.
+#include <algorithm>
+#include <cmath>
+#include <queue>
+
+#include "core.hpp"
+
+namespace psc {
+
+namespace {
+
+constexpr double kCUs = 256.0;
+
+struct HeuristicCost final : CostModel {
+  // Roofline-style estimate: a kernel occupies min(1, workgroups / CUs) of the chip and runs at
+  // that share of the matrix-core or HBM peak, plus a fixed dispatch latency.
+  std::vector<double> kernel_us(const Dag &g, const std::vector<int32_t> &in_flight) override {
+    std::vector<double> out(g.kers.size());
+    for (size_t k = 0; k < g.kers.size(); ++k) {
+      const Kernel &ker = g.kers[k];
+      const Buffer &o = g.bufs[ker.outs[0]];
+      double t;
+      if (ker.kind == PSC_GEMM) {
+        const Buffer &a = g.bufs[ker.ins[0]], &b = g.bufs[ker.ins[1]];
+        const double M = a.rows, K = a.cols, N = b.cols;
+        const double flops = 2.0 * M * N * K;
+        const double peak = a.dtype == PSC_BF16 ? 1.2e15 : 9.0e13;
+        const double tiles = std::ceil(M / 64.0) * std::ceil(N / 64.0);
+        const double share = std::min(1.0, tiles / kCUs);
+        const double bytes = (M * K + K * N) * elem_size(a.dtype) + M * N * elem_size(o.dtype);
+        t = std::max(flops / (peak * share), bytes / 4.0e12) * 1e6;
+      } else {
+        double bytes = 0;
+        for (int32_t b : ker.ins) bytes += double(g.bufs[b].rows) * g.bufs[b].cols * elem_size(g.bufs[b].dtype);
+        bytes += double(o.rows) * o.cols * elem_size(o.dtype);
+        const double blocks = std::ceil(double(o.rows) * o.cols / 4096.0);
+        t = bytes / (4.0e12 * std::min(1.0, blocks / kCUs)) * 1e6;
+      }
+      const double flight = k < in_flight.size() ? std::max(1, in_flight[k]) : 1;
+      out[k] = 3.0 + t * (flight > 1 ? 1.0 + 0.15 * (flight - 1) : 1.0);
+    }
+    return out;
+  }
+  double copy_us(const Dag &g, int32_t buffer, bool) override {
+    const Buffer &b = g.bufs[buffer];
+    return 4.0 + double(b.rows) * b.cols * elem_size(b.dtype) / 50.0e9 * 1e6;
+  }
+};
+
+// EFT list scheduling: kernels by descending bottom-level rank (ties: lower id), each placed on
+// the stream where it is predicted to finish first.
+void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &order,
+             std::vector<int32_t> &stream_of) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  std::vector<int32_t> flight(nk, std::min<int32_t>(S, 4));
+  const std::vector<double> w = cost.kernel_us(g, flight);
+  std::vector<double> copy_in(nk, 0.0);
+  for (int32_t k = 0; k < nk; ++k)
+    for (int32_t b : g.iso_in[k]) copy_in[k] += cost.copy_us(g, b, true);
+  // bottom-level rank over a reverse topological order
+  std::vector<int32_t> topo = g.bfs_order();
+  std::vector<double> bl(nk, 0.0);
+  for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
+    double m = 0;
+    for (int32_t s : g.succ[*it]) m = std::max(m, bl[s]);
+    bl[*it] = w[*it] + m;
+  }
+  using Item = std::pair<double, int32_t>;  // (-rank, id)
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
+  std::vector<int32_t> indeg(nk);
+  for (int32_t k = 0; k < nk; ++k) {
+    indeg[k] = static_cast<int32_t>(g.pred[k].size());
+    if (!indeg[k]) ready.push({-bl[k], k});
+  }
+  std::vector<double> avail(S, 0.0), finish(nk, 0.0);
+  std::vector<char> uploaded(g.bufs.size(), 0);
+  order.clear();
+  while (!ready.empty()) {
+    const int32_t k = ready.top().second;
+    ready.pop();
+    double dep_ready = 0;
+    for (int32_t p : g.pred[k]) dep_ready = std::max(dep_ready, finish[p]);
+    double up = 0;
+    for (int32_t b : g.iso_in[k])
+      if (!uploaded[b]) up += cost.copy_us(g, b, true);
+    int32_t best = 0;
+    double best_f = 1e300;
+    for (int32_t s = 0; s < S; ++s) {
+      const double f = std::max(avail[s] + up, dep_ready) + w[k];
+      if (f < best_f - 1e-9) { best_f = f; best = s; }
+    }
+    for (int32_t b : g.iso_in[k]) uploaded[b] = 1;
+    stream_of[k] = best;
+    avail[best] = finish[k] = best_f;
+    order.push_back(k);
+    for (int32_t s : g.succ[k])
+      if (--indeg[s] == 0) ready.push({-bl[s], s});
+  }
+}
+
+}  // namespace
+
+std::unique_ptr<CostModel> make_heuristic_cost() { return std::make_unique<HeuristicCost>(); }
+
+CostModel *mlp_cost_model(const psc_mlp *m);  // mlp.cpp
+
+SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  SchedPlan plan;
+  const int32_t S = policy == PSC_COARSE ? 1 : o.n_streams;
+  plan.n_streams = S;
+  const bool cs = policy != PSC_COARSE && o.copy_stream;
+  const int32_t copy_s = cs ? S : -1;
+  plan.total_streams = S + (cs ? 1 : 0);
+
+  std::vector<int32_t> order, stream_of(nk, 0);
+  if (policy == PSC_COARSE) {
+    order = g.bfs_order();
+  } else if (o.mapper == PSC_MAP_RR) {
+    order = g.bfs_order();
+    for (int32_t i = 0; i < nk; ++i) stream_of[order[i]] = i % S;
+  } else if (o.mapper == PSC_MAP_COMPONENT) {
+    order = g.bfs_order();
+    for (int32_t k = 0; k < nk; ++k) stream_of[k] = g.kers[k].component % S;
+  } else if (o.mapper == PSC_MAP_EFT) {
+    if (o.cost) {
+      map_eft(g, S, *mlp_cost_model(o.cost), order, stream_of);
+    } else {
+      auto h = make_heuristic_cost();
+      map_eft(g, S, *h, order, stream_of);
+    }
+  } else {
+    fail(PSC_ERR_ARG, "unknown mapper");
+  }
+
+  // emit ops with their dependencies (ids of earlier ops)
+  std::vector<std::vector<int32_t>> deps;
+  std::vector<int32_t> h2d_op(g.bufs.size(), -1);
+  plan.kernel_op.assign(nk, -1);
+  std::vector<int32_t> pos(plan.total_streams, 0);
+  auto emit = [&](int32_t type, int32_t kernel, int32_t buffer, int32_t stream,
+                  std::vector<int32_t> d) {
+    Op op;
+    op.type = type;
+    op.kernel = kernel;
+    op.buffer = buffer;
+    op.stream = stream;
+    op.pos = pos[stream]++;
+    op.host_order = static_cast<int32_t>(plan.ops.size());
+    plan.ops.push_back(std::move(op));
+    deps.push_back(std::move(d));
+    return static_cast<int32_t>(plan.ops.size() - 1);
+  };
+  if (cs)
+    for (int32_t k : order)
+      for (int32_t b : g.iso_in[k])
+        if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, copy_s, {});
+  for (int32_t k : order) {
+    const int32_t s = stream_of[k];
+    if (!cs)
+      for (int32_t b : g.iso_in[k])
+        if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, s, {});
+    std::vector<int32_t> d;
+    for (int32_t p : g.pred[k]) d.push_back(plan.kernel_op[p]);
+    for (int32_t b : g.iso_in[k]) d.push_back(h2d_op[b]);
+    const int32_t kop = emit(PSC_OP_KERNEL, k, -1, s, d);
+    plan.kernel_op[k] = kop;
+    for (int32_t b : g.iso_out[k]) emit(PSC_OP_D2H, -1, b, s, {kop});
+  }
+
+  // waits: vector clocks over streams; vc[i][t] = last position on stream t known to precede op i
+  const int32_t T = plan.total_streams;
+  const size_t n = plan.ops.size();
+  std::vector<int32_t> vc(n * T, -1);
+  std::vector<int32_t> last_on(T, -1);
+  std::vector<int32_t> cur(T);
+  for (size_t i = 0; i < n; ++i) {
+    Op &op = plan.ops[i];
+    const int32_t prev = last_on[op.stream];
+    if (prev >= 0)
+      std::copy(vc.begin() + prev * T, vc.begin() + (prev + 1) * T, cur.begin());
+    else
+      std::fill(cur.begin(), cur.end(), -1);
+    std::vector<int32_t> d = deps[i];
+    std::sort(d.begin(), d.end(), std::greater<int32_t>());  // later ops first
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    for (int32_t dep : d) {
+      const Op &p = plan.ops[dep];
+      if (p.stream == op.stream) continue;  // stream order covers it
+      if (cur[p.stream] >= p.pos) continue;  // implied by an earlier wait
+      op.waits.push_back(dep);
+      plan.ops[dep].recorded = true;
+      for (int32_t t = 0; t < T; ++t) cur[t] = std::max(cur[t], vc[dep * T + t]);
+    }
+    std::sort(op.waits.begin(), op.waits.end());
+    cur[op.stream] = op.pos;
+    std::copy(cur.begin(), cur.end(), vc.begin() + i * T);
+    last_on[op.stream] = static_cast<int32_t>(i);
+  }
+  return plan;
+}
+
+}  // namespace psc

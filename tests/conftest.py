@@ -3,6 +3,8 @@ import sys
 
 import pytest
 
+import paper_2009_07482_amd  # noqa: F401  (load libpsc.so and its HIP runtime before torch)
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -1,0 +1,248 @@
+"""Host-side tests of the C ABI (no GPU): symbol export, IR errors, classification, and the
+command-queue structures the schedulers build, checked by the oracle's validator."""
+import json
+import os
+import re
+
+import pytest
+
+import workloads
+import paper_2009_07482_amd as psc
+from oracle import validator
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "psc.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"^\S.*?\b(psc_\w+)\(", hdr, flags=re.M))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(psc._lib, name), name
+    assert declared <= set(psc.EXPORTED)
+    assert psc.psc_abi_version() == 1
+
+
+def _load(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+def test_fig6_classification(golden_dir):
+    g = _load(golden_dir, "fig6_classification.json")
+    spec = g["dag"]
+    dag = psc.build_dag(spec)
+    try:
+        kclass, inter = psc.psc_dag_classify(dag, g["component"])
+    finally:
+        psc.psc_dag_destroy(dag)
+    names = [k["name"] for k in spec["kernels"]]
+    front = sorted(n for n, c in zip(names, kclass) if c & psc.PSC_FRONT)
+    end = sorted(n for n, c in zip(names, kclass) if c & psc.PSC_END)
+    inn = sorted(n for n, c in zip(names, kclass) if c & psc.PSC_IN)
+    assert front == g["front"] and end == g["end"] and inn == g["in"]
+    pairs = [(e[1], e[3]) for e in spec["edges"]]
+    got_inter = sorted(list(p) for p, x in zip(pairs, inter) if x)
+    got_intra = sorted(list(p) for p, x in zip(pairs, inter) if not x)
+    assert got_inter == sorted(g["inter_edges"])
+    assert got_intra == sorted(g["intra_edges"])
+    # isolated writes of T: inputs of T's kernels that no edge feeds
+    writes, _ = validator.isolated_io(spec)
+    tk = {i for i, c in enumerate(spec["component"]) if c == g["component"]}
+    iso_t = sorted([b, names[k]] for (k, b) in writes if k in tk)
+    assert iso_t == sorted(g["isolated_writes_in_T"])
+
+
+def _queues(exp):
+    qs = {}
+    for o in sorted(exp["ops"], key=lambda o: (o["stream"], o["pos"])):
+        qs.setdefault(o["stream"], []).append(o)
+    return [qs[s] for s in sorted(qs)]
+
+
+def _label(spec, o):
+    if o["type"] == "kernel":
+        return "kernel:" + spec["kernels"][o["kernel"]]["name"]
+    return f"{o['type']}:{o['buffer']}"
+
+
+def test_fig9_setup_cq_round_robin(golden_dir):
+    g = _load(golden_dir, "fig9_setup_cq.json")
+    spec = g["dag"]
+    dag = psc.build_dag(spec)
+    s = psc.psc_schedule(dag, "fine", n_streams=g["n_streams"], mapper="rr")
+    try:
+        exp = psc.export_schedule(spec, s)
+    finally:
+        psc.psc_sched_destroy(s)
+        psc.psc_dag_destroy(dag)
+    assert [[_label(spec, o) for o in q] for q in _queues(exp)] == g["queues"]
+    by_id = {o["id"]: o for o in exp["ops"]}
+    eq = sorted([_label(spec, by_id[w]), _label(spec, o)] for o in exp["ops"] for w in o["waits"])
+    assert eq == sorted(g["eq_stated"] + g["eq_derived"])
+    ok, errs, _ = validator.check_schedule(spec, exp)
+    assert ok, errs
+    assert validator.brute_force(spec, exp) == set()
+
+
+def _schedules(spec, configs):
+    dag = psc.build_dag(spec)
+    out = []
+    try:
+        for policy, kw in configs:
+            s = psc.psc_schedule(dag, policy, **kw)
+            out.append(((policy, tuple(sorted(kw.items()))), psc.export_schedule(spec, s)))
+            psc.psc_sched_destroy(s)
+    finally:
+        psc.psc_dag_destroy(dag)
+    return out
+
+
+CONFIGS = [("coarse", {})] + [
+    ("fine", dict(n_streams=s, mapper=m, copy_stream=c))
+    for s in (1, 2, 3, 4, 8) for m in ("rr", "eft", "component") for c in (False, True)]
+
+
+@pytest.mark.parametrize("name,spec", [
+    ("forkjoin", workloads.forkjoin_spec(64)),
+    ("mha1", workloads.mha_spec(64, 64, 4)),
+    ("mha2x", workloads.mha_spec(32, 32, 2, layers=2)),
+    ("mha_bf16", workloads.mha_spec(64, 64, 2, gemm_dtype="bf16")),
+    ("random", workloads.random_dag_spec(3, n_nodes=(20, 40), dim=(8, 64))),
+    ("batch", workloads.batch_spec([5, 17, 9], d=16, heads=2, layers=2)),
+])
+def test_every_schedule_is_valid(name, spec):
+    for key, exp in _schedules(spec, CONFIGS):
+        ok, errs, _ = validator.check_schedule(spec, exp)
+        assert ok, (key, errs[:5])
+        if key[0] == "coarse":
+            assert exp["n_streams"] == 1 and all(not o["waits"] for o in exp["ops"])
+
+
+def test_tiny_schedules_agree_with_brute_force():
+    spec = workloads.forkjoin_spec(8)
+    for key, exp in _schedules(spec, CONFIGS):
+        assert validator.brute_force(spec, exp) == set(), key
+
+
+def test_schedules_are_deterministic():
+    spec = workloads.mha_spec(32, 32, 4)
+    a = _schedules(spec, CONFIGS)
+    b = _schedules(spec, CONFIGS)
+    assert a == b
+
+
+def test_fine_round_robin_spreads_heads_and_reduces_waits():
+    spec = workloads.mha_spec(512, 512, 8)
+    (_, exp), = _schedules(spec, [("fine", dict(n_streams=4, mapper="rr"))])
+    kern = [o for o in exp["ops"] if o["type"] == "kernel"]
+    assert sorted({o["stream"] for o in kern}) == [0, 1, 2, 3]
+    assert len(kern) == 57
+    assert sum(1 for o in exp["ops"] if o["type"] == "h2d") == 1 + 3 * 8 + 1   # X, 24 slices, Wo
+    assert sum(1 for o in exp["ops"] if o["type"] == "d2h") == 1
+    # every wait is needed: no wait is implied by the stream order plus the other waits
+    anc = validator.hb_closure(exp)
+    for o in exp["ops"]:
+        for w in o["waits"]:
+            others = [x for x in o["waits"] if x != w]
+            prev = [p["id"] for p in exp["ops"] if p["stream"] == o["stream"] and p["pos"] == o["pos"] - 1]
+            implied = any((anc[x] >> w) & 1 or x == w for x in others + prev)
+            assert not implied
+
+
+def _err(fn):
+    with pytest.raises(psc.PscError) as e:
+        fn()
+    return e.value.name
+
+
+def _dag_from(spec):
+    return psc.build_dag(spec)
+
+
+def test_ir_errors():
+    # cycle
+    spec = workloads.forkjoin_spec(4)
+    d = psc.psc_dag_create()
+    for b in spec["buffers"]:
+        psc.psc_add_buffer(d, b["name"], "f32", 4, 4)
+    k0 = psc.psc_add_kernel(d, "a", "add", ["A0", "B0"], ["C0"])
+    k1 = psc.psc_add_kernel(d, "b", "add", ["C0", "B1"], ["A0"])
+    psc.psc_add_edge(d, k0, "C0", k1, "C0")
+    psc.psc_add_edge(d, k1, "A0", k0, "A0")
+    assert _err(lambda: psc.psc_schedule(d, "coarse")) == "PSC_ERR_CYCLE"
+    psc.psc_dag_destroy(d)
+    # unknown name, duplicate, wrong arity, bad view
+    d = psc.psc_dag_create()
+    psc.psc_add_buffer(d, "A", "f32", 4, 8)
+    assert _err(lambda: psc.psc_add_buffer(d, "A", "f32", 4, 8)) == "PSC_ERR_NAME"
+    assert _err(lambda: psc.psc_add_kernel(d, "k", "transpose", ["nope"], ["A"])) == "PSC_ERR_NAME"
+    assert _err(lambda: psc.psc_add_kernel(d, "k", "gemm", ["A"], ["A"])) == "PSC_ERR_ARG"
+    assert _err(lambda: psc.psc_add_buffer(d, "V", "f32", 4, 4, "A", 0, 5)) == "PSC_ERR_SHAPE"
+    assert _err(lambda: psc.psc_add_buffer(d, "V", "bf16", 4, 4, "A", 0, 0)) == "PSC_ERR_SHAPE"
+    psc.psc_dag_destroy(d)
+    # shape mismatch in a GEMM
+    d = psc.psc_dag_create()
+    for n, r, c in (("A", 4, 5), ("B", 6, 3), ("C", 4, 3)):
+        psc.psc_add_buffer(d, n, "f32", r, c)
+    psc.psc_add_kernel(d, "g", "gemm", ["A", "B"], ["C"])
+    assert _err(lambda: psc.psc_schedule(d, "fine")) == "PSC_ERR_SHAPE"
+    psc.psc_dag_destroy(d)
+
+
+def test_race_and_state_errors():
+    # an input produced by a kernel but with no edge feeding it
+    spec = workloads.forkjoin_spec(4)
+    bad = dict(spec, edges=[e for e in spec["edges"] if e != (0, "C0", 2, "C0")])
+    d = _dag_from(bad)
+    assert _err(lambda: psc.psc_schedule(d, "fine")) == "PSC_ERR_RACE"
+    psc.psc_dag_destroy(d)
+    # two unordered writers of one buffer
+    d = psc.psc_dag_create()
+    for n in ("A", "B", "C"):
+        psc.psc_add_buffer(d, n, "f32", 4, 4)
+    psc.psc_add_kernel(d, "t1", "transpose", ["A"], ["C"])
+    psc.psc_add_kernel(d, "t2", "transpose", ["B"], ["C"])
+    assert _err(lambda: psc.psc_schedule(d, "fine")) == "PSC_ERR_RACE"
+    psc.psc_dag_destroy(d)
+    # in-place kernel
+    d = psc.psc_dag_create()
+    psc.psc_add_buffer(d, "A", "f32", 4, 4)
+    psc.psc_add_buffer(d, "B", "f32", 4, 4)
+    psc.psc_add_kernel(d, "s", "add", ["A", "B"], ["A"])
+    assert _err(lambda: psc.psc_schedule(d, "fine")) == "PSC_ERR_SHAPE"
+    psc.psc_dag_destroy(d)
+    # partly produced input: only one head writes into Ocat
+    spec = workloads.mha_spec(8, 8, 2)
+    bad = dict(spec, edges=[e for e in spec["edges"] if not (e[1] == "L0H1_O")])
+    d = _dag_from(bad)
+    assert _err(lambda: psc.psc_schedule(d, "fine")) in ("PSC_ERR_RACE", "PSC_ERR_SHAPE")
+    psc.psc_dag_destroy(d)
+    # frozen after scheduling; DAG outlives schedules
+    d = _dag_from(workloads.forkjoin_spec(4))
+    s = psc.psc_schedule(d, "coarse")
+    assert _err(lambda: psc.psc_add_buffer(d, "Z", "f32", 1, 1)) == "PSC_ERR_STATE"
+    assert _err(lambda: psc.psc_dag_destroy(d)) == "PSC_ERR_STATE"
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(d)
+    # edge between buffers that share no storage
+    d = _dag_from(dict(workloads.forkjoin_spec(4), edges=[]))
+    assert _err(lambda: psc.psc_add_edge(d, 0, "C0", 1, "B1")) == "PSC_ERR_SHAPE"
+    assert _err(lambda: psc.psc_add_edge(d, 0, "A0", 1, "C0")) == "PSC_ERR_NAME"
+    psc.psc_dag_destroy(d)
+    assert psc.psc_last_error() == ""          # the last call succeeded
+
+
+def test_classify_default_component_is_whole_dag():
+    spec = workloads.mha_spec(16, 16, 2)
+    spec = dict(spec, component=[0] * len(spec["kernels"]))
+    d = _dag_from(spec)
+    kc, inter = psc.psc_dag_classify(d, 0)
+    psc.psc_dag_destroy(d)
+    names = [k["name"] for k in spec["kernels"]]
+    front = {n for n, c in zip(names, kc) if c & psc.PSC_FRONT}
+    end = {n for n, c in zip(names, kc) if c & psc.PSC_END}
+    assert front == {f"L0H{h}_{x}" for h in range(2) for x in "qkv"}
+    assert end == {"L0_y"}
+    assert not any(inter)

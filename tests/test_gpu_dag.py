@@ -1,0 +1,177 @@
+"""DAG-level parity on the GPU: the fork-join and attention DAGs under every policy against the
+FP64 oracle; coarse, fine, graph and device-resident runs bit-identical to each other; the fine
+schedule's timeline shows concurrent kernels."""
+import numpy as np
+import pytest
+
+import workloads
+import paper_2009_07482_amd as psc
+from oracle import dag as odag
+from oracle import validator
+from gpu_helpers import normwise, oracle_outputs
+
+pytestmark = pytest.mark.gpu
+
+POLICIES = [("coarse", {}), ("fine", dict(n_streams=2, mapper="rr")), ("fine", dict(n_streams=3, mapper="rr")),
+            ("fine", dict(n_streams=4, mapper="eft")), ("fine", dict(n_streams=4, mapper="component")),
+            ("fine", dict(n_streams=4, mapper="rr", copy_stream=True)),
+            ("fine", dict(n_streams=4, mapper="rr", use_graph=True))]
+
+
+def _pid(p):
+    policy, kw = p
+    return "-".join([policy] + [f"{k}{int(v) if isinstance(v, bool) else v}" for k, v in kw.items()]).replace(
+        "use_graph1", "graph")
+
+
+POLICY_PARAMS = [pytest.param(p, kw, id=_pid((p, kw))) for p, kw in POLICIES]
+
+
+@pytest.mark.parametrize("policy,kw", POLICY_PARAMS)
+def test_forkjoin_ternary_bit_exact(policy, kw):
+    print(f"forkjoin ternary {policy} {kw}", flush=True)
+    spec = workloads.forkjoin_spec(256)
+    inp = workloads.forkjoin_inputs(0, 256, ternary=True)
+    out, st = psc.run_spec(spec, inp, policy, **kw)
+    np.testing.assert_array_equal(out["C3"], oracle_outputs(spec, inp)["C3"])
+    assert st["n_kernels"] == 4
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("policy,kw", POLICY_PARAMS)
+def test_forkjoin_uniform(seed, policy, kw):
+    spec = workloads.forkjoin_spec(256)
+    inp = workloads.forkjoin_inputs(seed, 256)
+    out, _ = psc.run_spec(spec, inp, policy, **kw)
+    assert normwise(out["C3"], oracle_outputs(spec, inp)["C3"]) < 1e-4
+
+
+def test_forkjoin_bf16_c0_ternary_exact():
+    spec = workloads.forkjoin_spec(256, dtype="bf16", c0_dtype="bf16")
+    inp = workloads.forkjoin_inputs(1, 256, ternary=True)
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=3)
+    np.testing.assert_array_equal(out["C3"], oracle_outputs(spec, inp)["C3"])
+
+
+@pytest.fixture(scope="module")
+def mha512():
+    spec = workloads.mha_spec(512, 512, 8)
+    inp = workloads.mha_inputs(0, 512, 512)
+    ref = oracle_outputs(spec, inp)["Y0"]
+    return spec, inp, ref
+
+
+@pytest.mark.parametrize("policy,kw", POLICY_PARAMS + [pytest.param("fine", dict(n_streams=8, mapper="rr"), id="fine-8rr")])
+def test_mha_fp32_against_oracle(mha512, policy, kw):
+    print(f"mha512 {policy} {kw}", flush=True)
+    spec, inp, ref = mha512
+    out, _ = psc.run_spec(spec, inp, policy, **kw)
+    assert normwise(out["Y0"], ref) < 1e-4
+
+
+def test_mha_coarse_fine_resident_bit_identical(mha512):
+    spec, inp, _ = mha512
+    outs = []
+    for policy, kw in [p for p in POLICIES if not p[1].get("use_graph")]:
+        r = psc.SpecRunner(spec, policy, **kw)
+        r.set_inputs(inp)
+        r.run()
+        outs.append(r.result("Y0"))
+        # device-resident second run: no copies in, results stay on the device and are read back
+        r.run(with_inputs=False, with_outputs=False)
+        r.run(with_inputs=False, with_outputs=True)
+        outs.append(r.result("Y0"))
+        r.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_graph_matches_eager_bit_identical(mha512):
+    spec, inp, _ = mha512
+    outs = []
+    for kw in (dict(n_streams=4, mapper="rr"), dict(n_streams=4, mapper="rr", use_graph=True)):
+        r = psc.SpecRunner(spec, "fine", **kw)
+        r.set_inputs(inp)
+        r.run()
+        outs.append(r.result("Y0"))
+        r.run(with_inputs=False, with_outputs=True)
+        outs.append(r.result("Y0"))
+        r.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_graph_replays_match_eager(mha512):
+    spec, inp, _ = mha512
+    eager = psc.SpecRunner(spec, "fine", n_streams=4)
+    eager.set_inputs(inp)
+    eager.run()
+    want = eager.result("Y0")
+    g = psc.SpecRunner(spec, "fine", n_streams=4, use_graph=True)
+    g.set_inputs(inp)
+    for i in range(4):
+        g.outputs["Y0"].array[...] = 0
+        g.run()
+        np.testing.assert_array_equal(g.result("Y0"), want)
+        eager.run()  # eager work between replays
+    eager.close()
+    g.close()
+
+
+def test_fine_timeline_overlaps_kernels(mha512):
+    spec, inp, _ = mha512
+    r = psc.SpecRunner(spec, "fine", n_streams=4, record_ops=True)
+    r.set_inputs(inp)
+    r.run()
+    r.run()
+    times = psc.psc_sched_op_times(r.sched)
+    exp = r.export()
+    r.close()
+    kern = [(t[1], t[2], t[3]) for t, o in zip(times, exp["ops"]) if o["type"] == "kernel"]
+    overlaps = 0
+    for i in range(len(kern)):
+        for j in range(i + 1, len(kern)):
+            a, b = kern[i], kern[j]
+            if a[0] != b[0] and a[1] < b[2] and b[1] < a[2]:
+                overlaps += 1
+    print("overlapping kernel pairs on different streams:", overlaps)
+    assert overlaps >= 1
+    ok, errs, _ = validator.check_schedule(spec, exp)
+    assert ok, errs
+
+
+@pytest.mark.parametrize("n,d,h,layers,dt", [(137, 64, 2, 2, "f32"), (200, 128, 4, 1, "bf16"),
+                                             (1000, 64, 1, 1, "f32"), (64, 512, 8, 3, "bf16")])
+def test_ragged_attention(n, d, h, layers, dt):
+    print(f"ragged mha n={n} d={d} h={h} L={layers} {dt}", flush=True)
+    spec = workloads.mha_spec(n, d, h, layers, gemm_dtype=dt)
+    inp = workloads.mha_inputs(3, n, d, layers)
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=4, copy_stream=True)
+    y = f"Y{layers - 1}"
+    exact = oracle_outputs(spec, inp)[y]
+    assert normwise(out[y], exact) < (1e-4 if dt == "f32" else 2e-2)
+
+
+def test_random_dags_against_oracle():
+    for seed in range(4):
+        spec = workloads.random_dag_spec(seed, n_nodes=(20, 40), dim=(8, 160))
+        inp = workloads.random_dag_inputs(seed, spec)
+        ref = oracle_outputs(spec, inp)
+        for policy, kw in [("coarse", {}), ("fine", dict(n_streams=4, mapper="eft"))]:
+            out, _ = psc.run_spec(spec, inp, policy, **kw)
+            for name, want in ref.items():
+                tol = 1e-4 if spec["dtype"] == "f32" else 5e-2
+                assert normwise(out[name], want) < tol, (seed, policy, name)
+
+
+def test_io_errors():
+    spec = workloads.forkjoin_spec(16)
+    r = psc.SpecRunner(spec, "fine")
+    with pytest.raises(psc.PscError) as e:
+        psc.psc_run(r.sched, [("C1", 0, 16 * 16 * 4)])   # C1 is neither written nor read back
+    assert e.value.name in ("PSC_ERR_NAME", "PSC_ERR_ARG")
+    with pytest.raises(psc.PscError) as e:
+        t = psc.HostBuffer(16, 16, "f32")
+        psc.psc_run(r.sched, [("A0", t.ptr, 7)])
+    assert e.value.name == "PSC_ERR_ARG"
+    r.close()
