@@ -117,6 +117,10 @@ def main():
     runners = {
         "coarse": psc.SpecRunner(spec, "coarse"),
         "fine": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr"),
+        "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", host_threads=1),
+        "fine_component": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component"),
+        "fine_eft": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="eft"),
+        "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="rr"),
     }
     if a.graph:
         runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", use_graph=True)
