@@ -6,7 +6,9 @@ Default workload: one multi-head attention layer, n = d = 512, 8 heads of dim 64
 kernels: per head three projection GEMMs, a transpose, the score GEMM, a row softmax and the
 P*V GEMM; then the output projection).  A step is one pass of the whole DAG -- every kernel
 enqueued on the schedule's streams with its event waits, then a join -- over device-resident
-inputs.  ``value`` is inferences/s of the fine-grained schedule (4 streams, round robin).
+inputs.  ``value`` is inferences/s of the fine-grained schedule: the clustering scheme of Sec. V
+(each head's kernels form one task component, components on 4 HIP streams), each stream enqueued
+by its own host thread.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha512|mha1024x12|forkjoin]
 """
@@ -35,6 +37,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--graph", action="store_true", help="also time the schedule launched as one hipGraph")
+    p.add_argument("--kernel-iters", type=int, default=200)
     return p.parse_args()
 
 
@@ -116,11 +119,12 @@ def main():
     spec, inp, desc = workload(a.config)
     runners = {
         "coarse": psc.SpecRunner(spec, "coarse"),
-        "fine": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr"),
-        "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", host_threads=1),
-        "fine_component": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component"),
+        "fine": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component"),
+        "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component", host_threads=1),
+        "fine_rr": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr"),
+        "fine_rr_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", host_threads=1),
         "fine_eft": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="eft"),
-        "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="rr"),
+        "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="component"),
     }
     if a.graph:
         runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", use_graph=True)
@@ -137,40 +141,55 @@ def main():
                      "n_waits": st["n_waits"], "n_streams": st["n_streams"]}
         print(f"# {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
 
-    # per-kernel durations inside the fine schedule (HIP events on each op's stream)
-    rec = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", record_ops=True)
-    rec.set_inputs(inp)
-    rec.run()
-    classes = {}
-    for _ in range(5):
-        rec.run(with_inputs=False, with_outputs=False)
-        times = psc.psc_sched_op_times(rec.sched)
-        ops = psc.psc_sched_export(rec.sched)
-        for (oid, s, t0, t1), o in zip(times, ops):
-            if o["type"] != "kernel":
-                continue
-            key, work, bound, dt = kernel_class(spec, o["kernel"])
-            c = classes.setdefault(key, {"work": work, "bound": bound, "dtype": dt, "us": []})
-            c["us"].append(t1 - t0)
-    rec.close()
-    dom_key = max(classes, key=lambda k: sum(classes[k]["us"]))
-    dom = classes[dom_key]
-    avg_us = float(np.mean(dom["us"]))
+    # Dominant kernel: per kernel class, the mean duration of back-to-back launches on the
+    # class's own stream (HIP events around the launches, on that stream) times its launches per
+    # step; the class with the largest product dominates the step.
+    r = runners["fine"]
+    kers = {}
+    for k in range(len(spec["kernels"])):
+        key, work, bound, dt = kernel_class(spec, k)
+        kers.setdefault(key, {"work": work, "bound": bound, "dtype": dt, "ids": []})["ids"].append(k)
+    for key, c in kers.items():
+        psc.psc_kernel_time(r.sched, c["ids"][0], 10)
+        c["avg_us"] = psc.psc_kernel_time(r.sched, c["ids"][0], a.kernel_iters)
+        c["total_us"] = c["avg_us"] * len(c["ids"])
+    print("# kernel classes (isolated mean us per launch x launches per step):", file=sys.stderr)
+    for key, c in sorted(kers.items(), key=lambda kv: -kv[1]["total_us"]):
+        print(f"#   {key}: {c['avg_us']:.2f} us x {len(c['ids'])}", file=sys.stderr)
+    dom_key = max(kers, key=lambda k: kers[k]["total_us"])
+    dom = kers[dom_key]
+    avg_us = dom["avg_us"]
+    achieved = dom["work"] / (avg_us * 1e-6)
     if dom["bound"] == "mfma":
         peak = PEAK["mfma_bf16"] if dom["dtype"] == "bf16" else PEAK["mfma_f32"]
-        achieved = dom["work"] / (avg_us * 1e-6)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
     else:
-        achieved = dom["work"] / (avg_us * 1e-6)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                 "frac": achieved / PEAK["hbm"], "traffic": None}
-    roof["kernel"] = dom_key
-    roof["avg_us"] = avg_us
-    roof["launches_per_step"] = len(dom["us"]) // 5
-    print("# kernel classes (mean us per launch inside the fine schedule):", file=sys.stderr)
-    for k, c in sorted(classes.items(), key=lambda kv: -sum(kv[1]["us"])):
-        print(f"#   {k}: {np.mean(c['us']):.2f} us x {len(c['us']) // 5}", file=sys.stderr)
+    roof.update({"kernel": dom_key, "avg_us": avg_us, "launches_per_step": len(dom["ids"]),
+                 "work_per_launch": dom["work"], "timing": f"{a.kernel_iters} back-to-back launches, HIP events on its stream"})
+
+    # per-op timeline of the fine schedule (start/end events around every op): concurrency
+    rec = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component", record_ops=True)
+    rec.set_inputs(inp)
+    rec.run()
+    rec.run(with_inputs=False, with_outputs=False)
+    times = psc.psc_sched_op_times(rec.sched)
+    rec.close()
+    ivals = sorted((t[2], t[3]) for t in times)
+    busy, cur_s, cur_e = 0.0, None, None
+    for s0, e0 in ivals:
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    op_sum = sum(e0 - s0 for s0, e0 in ivals)
+    concurrency = op_sum / busy if busy > 0 else 0.0
 
     fine = res["fine"]
     value = 1e3 / fine["ms_per_step"]
@@ -180,12 +199,14 @@ def main():
         "ms_per_step": fine["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if desc.get("gemm_dtype", "f32") == "f32" else "bf16",
         "data": "synthetic (seeded N(0,1) inputs, N(0,1/d) weights)",
-        "config": dict(desc, schedule=f"fine, {a.streams} HIP streams, round robin, eager enqueue",
+        "config": dict(desc, schedule=f"fine (clustering: one task component per head), {a.streams} HIP streams, "
+                                      f"one enqueue thread per stream",
                        inputs="device-resident"),
         "makespan_ms": {k: v["makespan_ms_median"] for k, v in res.items()},
         "ms_per_step_by_schedule": {k: v["ms_per_step"] for k, v in res.items()},
         "makespan_with_copies_ms": {k: v["makespan_with_copies_ms"] for k, v in res.items()},
         "fine_vs_coarse_speedup": res["coarse"]["ms_per_step"] / fine["ms_per_step"],
+        "fine_mean_ops_in_flight": concurrency,
         "roofline": roof,
     }
     for r in runners.values():

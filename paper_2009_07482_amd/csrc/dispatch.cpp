@@ -14,7 +14,7 @@ namespace psc {
 
 namespace {
 using Clock = std::chrono::steady_clock;
-constexpr auto kIdleSpin = std::chrono::microseconds(300);  // spin before parking when idle
+constexpr auto kIdleSpin = std::chrono::milliseconds(20);  // spin before parking when idle
 }  // namespace
 
 Dispatcher::Dispatcher(const SchedPlan &plan, int32_t n_threads)
