@@ -125,6 +125,7 @@ def main():
         "fine_rr_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", host_threads=1),
         "fine_eft": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="eft"),
         "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="component"),
+        "device": psc.SpecRunner(spec, "device"),
     }
     if a.graph:
         runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", use_graph=True)

@@ -69,8 +69,13 @@ typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_AD
 
 /* Coarse: one stream, kernels in breadth-first topological order, each with its isolated
  * writes just before and isolated reads just after it (the enq rules of Sec. III).
- * Fine: n_streams streams, kernels mapped by the mapper below, with event precedences. */
-typedef enum psc_policy { PSC_COARSE = 0, PSC_FINE = 1 } psc_policy;
+ * Fine: n_streams streams, kernels mapped by the mapper below, with event precedences.
+ * Device: the precedences are enforced on the GPU at tile granularity: one persistent kernel
+ * pulls the tiles of every kernel from a device work queue and releases a kernel's tiles when
+ * all its predecessor kernels have completed; host copies run before (H2D) and after (D2H) it on
+ * one stream.  Its exported structure puts each kernel on its own queue with a wait on every
+ * predecessor kernel and on the H2D copies of its inputs, which is what the device enforces. */
+typedef enum psc_policy { PSC_COARSE = 0, PSC_FINE = 1, PSC_DEVICE = 2 } psc_policy;
 
 /* Stream choice of the fine policy.
  *  PSC_MAP_RR         round robin per kernel in breadth-first order from the DAG's roots

@@ -36,7 +36,7 @@ PSC_F32, PSC_BF16 = 0, 1
 DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
 PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
 KINDS = {"gemm": PSC_GEMM, "transpose": PSC_TRANSPOSE, "softmax": PSC_SOFTMAX, "add": PSC_ADD}
-PSC_COARSE, PSC_FINE = 0, 1
+PSC_COARSE, PSC_FINE, PSC_DEVICE = 0, 1, 2
 PSC_MAP_RR, PSC_MAP_EFT, PSC_MAP_COMPONENT = 0, 1, 2
 MAPPERS = {"rr": PSC_MAP_RR, "eft": PSC_MAP_EFT, "component": PSC_MAP_COMPONENT}
 PSC_OP_H2D, PSC_OP_KERNEL, PSC_OP_D2H = 0, 1, 2
@@ -218,7 +218,8 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
 
 
 def psc_schedule(dag, policy, opts=None, **kw):
-    pol = {"coarse": PSC_COARSE, "fine": PSC_FINE}[policy] if isinstance(policy, str) else int(policy)
+    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+           if isinstance(policy, str) else int(policy))
     o = opts if opts is not None else make_opts(**kw)
     h = _P()
     _check(_lib.psc_schedule(dag, pol, C.byref(o), C.byref(h)))

@@ -230,9 +230,11 @@ psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass, in
 psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, psc_sched **out) {
   return guard([&] {
     need(dag && out, PSC_ERR_ARG, "NULL argument");
-    need(policy == PSC_COARSE || policy == PSC_FINE, PSC_ERR_ARG, "policy must be PSC_COARSE or PSC_FINE");
+    need(policy == PSC_COARSE || policy == PSC_FINE || policy == PSC_DEVICE, PSC_ERR_ARG,
+         "policy must be PSC_COARSE, PSC_FINE or PSC_DEVICE");
     psc_sched_opts o = opts ? *opts : default_opts();
-    if (policy == PSC_COARSE) o.n_streams = 1;
+    if (policy != PSC_FINE) o.n_streams = 1;
+    need(!(policy == PSC_DEVICE && o.use_graph), PSC_ERR_ARG, "PSC_DEVICE runs one kernel; use_graph does not apply");
     need(o.n_streams >= 1 && o.n_streams <= 64, PSC_ERR_ARG, "n_streams must be in [1, 64]");
     need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
     need(!(o.use_graph && o.record_ops), PSC_ERR_ARG, "record_ops cannot be combined with use_graph");

@@ -94,6 +94,7 @@ struct Op {
 };
 
 struct SchedPlan {
+  bool device = false;         // PSC_DEVICE: streams beyond 0 only describe precedences
   int32_t n_streams = 1;       // compute streams
   int32_t total_streams = 1;   // + copy stream
   std::vector<Op> ops;         // index = op id; host order = id order

@@ -1,635 +1,52 @@
-// gfx950 kernels of the attention DAG: GEMM on the matrix cores (FP32 and BF16 operands, FP32
-// accumulation), row softmax with wavefront reductions, LDS-tiled transpose, element-wise add.
-//
-// Every kernel takes one argument struct by value and handles ragged shapes (any M, N, K, rows,
-// cols >= 0) with bounds checks; vector loads are used only where the host has checked alignment.
-// The launch factories at the end pick a kernel instance for a problem and fill a Launch record
-// that the runtime passes to hipLaunchKernel.
-#include <hip/hip_runtime.h>
-
-#include <cstdint>
-#include <cstring>
-
-#include "kernels.hpp"
+// Standalone gfx950 kernels of the DAG (one tile function call per block; the tile functions live
+// in tiles.hpp) and the launch factories that pick a kernel instance for a problem and fill a
+// Launch record that the runtime passes to hipLaunchKernel.
+#include "tiles.hpp"
 
 namespace psc {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 // ---------------------------------------------------------------------------------------------
-// bfloat16 <-> float.  A bfloat16 is the upper 16 bits of an IEEE binary32; conversion from
-// float rounds to nearest, ties to even, on those 16 bits; NaN stays a (quiet) NaN.
-// ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return uint16_t((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
-
-template <bool BF16>
-__device__ __forceinline__ float load_elem(const void *p, int64_t i) {
-  if constexpr (BF16) return bf16_to_f32(static_cast<const uint16_t *>(p)[i]);
-  else return static_cast<const float *>(p)[i];
-}
-template <bool BF16>
-__device__ __forceinline__ void store_elem(void *p, int64_t i, float v) {
-  if constexpr (BF16) static_cast<uint16_t *>(p)[i] = f32_to_bf16(v);
-  else static_cast<float *>(p)[i] = v;
-}
-
-// ---------------------------------------------------------------------------------------------
-// GEMM, C = alpha * A * B.  Block tile BM x BN, K step BK, each wavefront a WM x WN sub-tile made
-// of 16 x 16 matrix-core blocks.  Operand tiles are staged through LDS with padded pitches so that
-// the per-lane fragment reads hit distinct banks.
-//
-// Matrix-core operand layouts (16 x 16 output block, lane l of 64):
-//   v_mfma_f32_16x16x4_f32:   A: row l%16, k l/16          B: col l%16, k l/16
-//   v_mfma_f32_16x16x32_bf16: A: row l%16, k 8*(l/16)+e    B: col l%16, k 8*(l/16)+e  (e < 8)
-//   accumulator (both): element r of lane l is row 4*(l/16)+r, col l%16.
+// Standalone kernels: one tile function call per 256-thread block.
 // ---------------------------------------------------------------------------------------------
 template <int BM, int BN, int BK, int WM, int WN, bool VEC, bool OUT_BF16>
-__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void gemm_f32_kernel(GemmArgs p) {
-  constexpr int NWN = BN / WN, NT = 64 * (BM / WM) * NWN;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int SA = ((BM + 63) / 64) * 64 + 16;  // pitch = 16 (mod 64) dwords
-  constexpr int SB = ((BN + 63) / 64) * 64 + 16;
-  constexpr int UA = BM * (BK / 4), UB = BK * (BN / 4);  // float4 units per tile
-  constexpr int NA = (UA + NT - 1) / NT, NB = (UB + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) float As[BK * SA];  // k-major: As[k][m]
-  __shared__ __attribute__((aligned(16))) float Bs[BK * SB];  // k-major: Bs[k][n]
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / NWN, wn = wave % NWN;
-  const int tm = blockIdx.x / p.tiles_n, tn = blockIdx.x % p.tiles_n;
-  const int m0 = tm * BM, n0 = tn * BN;
-  const float *A = static_cast<const float *>(p.A);
-  const float *B = static_cast<const float *>(p.B);
-
-  float4 ra[NA], rb[NB];
-  auto load = [&](int k0) {  // next tile into registers (zero outside the matrices)
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
-      const int gr = m0 + r, gc = k0 + c;
-      if (u < UA && VEC && gr < p.M && gc + 3 < p.K) {
-        ra[j] = *reinterpret_cast<const float4 *>(A + int64_t(gr) * p.lda + gc);
-      } else {
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          v[e] = (u < UA && gr < p.M && gc + e < p.K) ? A[int64_t(gr) * p.lda + gc + e] : 0.f;
-        ra[j] = make_float4(v[0], v[1], v[2], v[3]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, r = u / (BN / 4), c = (u % (BN / 4)) * 4;
-      const int gr = k0 + r, gc = n0 + c;
-      if (u < UB && VEC && gr < p.K && gc + 3 < p.N) {
-        rb[j] = *reinterpret_cast<const float4 *>(B + int64_t(gr) * p.ldb + gc);
-      } else {
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          v[e] = (u < UB && gr < p.K && gc + e < p.N) ? B[int64_t(gr) * p.ldb + gc + e] : 0.f;
-        rb[j] = make_float4(v[0], v[1], v[2], v[3]);
-      }
-    }
-  };
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  load(0);
-  for (int k0 = 0; k0 < p.K; k0 += BK) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
-      if (u < UA) {
-        As[(c + 0) * SA + r] = ra[j].x;
-        As[(c + 1) * SA + r] = ra[j].y;
-        As[(c + 2) * SA + r] = ra[j].z;
-        As[(c + 3) * SA + r] = ra[j].w;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, r = u / (BN / 4), c = (u % (BN / 4)) * 4;
-      if (u < UB) *reinterpret_cast<float4 *>(&Bs[r * SB + c]) = rb[j];
-    }
-    __syncthreads();
-    if (k0 + BK < p.K) load(k0 + BK);  // in flight while this tile is multiplied
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + (lane >> 4);
-      float a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[k * SA + wm * WM + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[k * SB + wn * WN + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * WN + j * 16 + (lane & 15);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
-        if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
-      }
-    }
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_f32_smem<BM, BN, BK>()];
+  gemm_f32_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, bool VEC, bool OUT_BF16>
-__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void gemm_bf16_kernel(GemmArgs p) {
-  static_assert(BK % 32 == 0, "BK must be a multiple of the 32-deep matrix-core step");
-  constexpr int NWN = BN / WN, NT = 64 * (BM / WM) * NWN;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int KP = BK + 8;  // row pitch in bf16 elements: (KP/2) = 4 * odd dwords
-  constexpr int UA = BM * (BK / 8), UB = (BK / 2) * (BN / 8);
-  constexpr int NA = (UA + NT - 1) / NT, NB = (UB + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * KP];  // As[m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bt[BN * KP];  // Bt[n][k] (B transposed)
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / NWN, wn = wave % NWN;
-  const int tm = blockIdx.x / p.tiles_n, tn = blockIdx.x % p.tiles_n;
-  const int m0 = tm * BM, n0 = tn * BN;
-  const uint16_t *A = static_cast<const uint16_t *>(p.A);
-  const uint16_t *B = static_cast<const uint16_t *>(p.B);
-
-  uint4 ra[NA], rb0[NB], rb1[NB];
-  auto load = [&](int k0) {
-    // A: units of 8 consecutive k in one row
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      const int gr = m0 + r, gc = k0 + c;
-      if (u < UA && VEC && gr < p.M && gc + 7 < p.K) {
-        ra[j] = *reinterpret_cast<const uint4 *>(A + int64_t(gr) * p.lda + gc);
-      } else {
-        uint16_t v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (u < UA && gr < p.M && gc + e < p.K) ? A[int64_t(gr) * p.lda + gc + e] : 0;
-        memcpy(&ra[j], v, 16);
-      }
-    }
-    // B: units of two consecutive k rows x 8 consecutive n, stored transposed as (k, k+1) pairs
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
-      const int gk = k0 + 2 * kp, gc = n0 + c;
-      if (u < UB && VEC && gk + 1 < p.K && gc + 7 < p.N) {
-        rb0[j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk) * p.ldb + gc);
-        rb1[j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk + 1) * p.ldb + gc);
-      } else {
-        uint16_t lo[8], hi[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          lo[e] = (u < UB && gk < p.K && gc + e < p.N) ? B[int64_t(gk) * p.ldb + gc + e] : 0;
-          hi[e] = (u < UB && gk + 1 < p.K && gc + e < p.N) ? B[int64_t(gk + 1) * p.ldb + gc + e] : 0;
-        }
-        memcpy(&rb0[j], lo, 16);
-        memcpy(&rb1[j], hi, 16);
-      }
-    }
-  };
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  load(0);
-  for (int k0 = 0; k0 < p.K; k0 += BK) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      if (u < UA) *reinterpret_cast<uint4 *>(&As[r * KP + c]) = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
-      if (u < UB) {
-        uint16_t lo[8], hi[8];
-        memcpy(lo, &rb0[j], 16);
-        memcpy(hi, &rb1[j], 16);
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          *reinterpret_cast<uint32_t *>(&Bt[(c + e) * KP + 2 * kp]) = uint32_t(lo[e]) | (uint32_t(hi[e]) << 16);
-      }
-    }
-    __syncthreads();
-    if (k0 + BK < p.K) load(k0 + BK);  // in flight while this tile is multiplied
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 32) {
-      const int kq = kk + 8 * (lane >> 4);
-      bf16x8 a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * WM + i * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bt[(wn * WN + j * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * WN + j * 16 + (lane & 15);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
-        if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
-      }
-    }
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_smem<BM, BN, BK>()];
+  gemm_bf16_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
-
-// ---------------------------------------------------------------------------------------------
-// Small-output GEMM with the K dimension split across the block's four wavefronts.  The block
-// owns a TM x TN output tile; wavefront w multiplies K chunks w, w+4, w+8, ... into its own
-// accumulators (each wavefront stages its chunk in a private LDS region), prefetching the next
-// chunk into registers while it multiplies the current one.  The four partial tiles are then
-// summed through LDS in the fixed order w = 0, 1, 2, 3, so results do not depend on timing.
-// Trip counts are uniform across wavefronts (chunks past the end are zero-filled), so every
-// __syncthreads is reached by all of them.
-// ---------------------------------------------------------------------------------------------
-template <int TM>
-struct SkPitch {  // k-major FP32 pitch = 16 (mod 32) dwords: conflict-free fragment reads
-  static constexpr int value = (TM % 32 == 0) ? TM + 16 : TM + 32;
-};
 
 template <int TM, int TN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_f32_splitk_kernel(GemmArgs p) {
-  constexpr int BK = 32, FM = TM / 16, FN = TN / 16;
-  constexpr int SA = SkPitch<TM>::value, SB = SkPitch<TN>::value;
-  constexpr int UA = TM * BK / 4 / 64, UB = BK * TN / 4 / 64;  // float4 loads per lane
-  constexpr int OPER = 4 * BK * (SA + SB);
-  constexpr int RED = 4 * TM * TN;
-  __shared__ __attribute__((aligned(16))) float smem[OPER > RED ? OPER : RED];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  float *As = smem + w * BK * SA;
-  float *Bs = smem + 4 * BK * SA + w * BK * SB;
-  const int tm = blockIdx.x / p.tiles_n, tn = blockIdx.x % p.tiles_n;
-  const int m0 = tm * TM, n0 = tn * TN;
-  const float *A = static_cast<const float *>(p.A);
-  const float *B = static_cast<const float *>(p.B);
-  const int nchunks = (p.K + BK - 1) / BK;
-  const int iters = (nchunks + 3) / 4;
-
-  float4 ra[UA], rb[UB];
-  auto load = [&](int chunk) {
-    const int k0 = chunk * BK;
-#pragma unroll
-    for (int j = 0; j < UA; ++j) {
-      const int u = lane + 64 * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
-      const int gr = m0 + r, gc = k0 + c;
-      if (VEC && gr < p.M && gc + 3 < p.K) {
-        ra[j] = *reinterpret_cast<const float4 *>(A + int64_t(gr) * p.lda + gc);
-      } else {
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (gr < p.M && gc + e < p.K) ? A[int64_t(gr) * p.lda + gc + e] : 0.f;
-        ra[j] = make_float4(v[0], v[1], v[2], v[3]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < UB; ++j) {
-      const int u = lane + 64 * j, r = u / (TN / 4), c = (u % (TN / 4)) * 4;
-      const int gr = k0 + r, gc = n0 + c;
-      if (VEC && gr < p.K && gc + 3 < p.N) {
-        rb[j] = *reinterpret_cast<const float4 *>(B + int64_t(gr) * p.ldb + gc);
-      } else {
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (gr < p.K && gc + e < p.N) ? B[int64_t(gr) * p.ldb + gc + e] : 0.f;
-        rb[j] = make_float4(v[0], v[1], v[2], v[3]);
-      }
-    }
-  };
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  load(w);  // chunk w; chunks >= nchunks load zeros
-  for (int it = 0; it < iters; ++it) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < UA; ++j) {
-      const int u = lane + 64 * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
-      As[(c + 0) * SA + r] = ra[j].x;
-      As[(c + 1) * SA + r] = ra[j].y;
-      As[(c + 2) * SA + r] = ra[j].z;
-      As[(c + 3) * SA + r] = ra[j].w;
-    }
-#pragma unroll
-    for (int j = 0; j < UB; ++j) {
-      const int u = lane + 64 * j, r = u / (TN / 4), c = (u % (TN / 4)) * 4;
-      *reinterpret_cast<float4 *>(&Bs[r * SB + c]) = rb[j];
-    }
-    __syncthreads();
-    if (it + 1 < iters) load((it + 1) * 4 + w);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + (lane >> 4);
-      float a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[k * SA + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[k * SB + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  }
-  __syncthreads();
-  float *red = smem;
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        red[w * TM * TN + (i * 16 + (lane >> 4) * 4 + r) * TN + j * 16 + (lane & 15)] = acc[i][j][r];
-  __syncthreads();
-  for (int e = tid; e < TM * TN; e += 256) {
-    const int row = m0 + e / TN, col = n0 + e % TN;
-    const float v = ((red[e] + red[TM * TN + e]) + red[2 * TM * TN + e]) + red[3 * TM * TN + e];
-    if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * v);
-  }
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_f32_splitk_smem<TM, TN>()];
+  gemm_f32_splitk_tile<TM, TN, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 
 template <int TM, int TN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
-  constexpr int BK = 64, KP = BK + 8, FM = TM / 16, FN = TN / 16;
-  constexpr int UA = TM * (BK / 8) / 64;        // uint4 (8 x bf16) loads per lane
-  constexpr int UB = (BK / 2) * (TN / 8) / 64;  // (k, k+1) x 8-column units per lane
-  static_assert(UA >= 1 && UB >= 1, "tile too small for one load per lane");
-  constexpr int OPER_B = 4 * (TM + TN) * KP * 2;  // bytes
-  constexpr int RED_B = 4 * TM * TN * 4;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[OPER_B > RED_B ? OPER_B : RED_B];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint16_t *As = reinterpret_cast<uint16_t *>(smem) + w * TM * KP;
-  uint16_t *Bt = reinterpret_cast<uint16_t *>(smem) + 4 * TM * KP + w * TN * KP;
-  const int tm = blockIdx.x / p.tiles_n, tn = blockIdx.x % p.tiles_n;
-  const int m0 = tm * TM, n0 = tn * TN;
-  const uint16_t *A = static_cast<const uint16_t *>(p.A);
-  const uint16_t *B = static_cast<const uint16_t *>(p.B);
-  const int nchunks = (p.K + BK - 1) / BK;
-  const int iters = (nchunks + 3) / 4;
-
-  uint4 ra[UA], rb0[UB], rb1[UB];
-  auto load = [&](int chunk) {
-    const int k0 = chunk * BK;
-#pragma unroll
-    for (int j = 0; j < UA; ++j) {
-      const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      const int gr = m0 + r, gc = k0 + c;
-      if (VEC && gr < p.M && gc + 7 < p.K) {
-        ra[j] = *reinterpret_cast<const uint4 *>(A + int64_t(gr) * p.lda + gc);
-      } else {
-        uint16_t v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (gr < p.M && gc + e < p.K) ? A[int64_t(gr) * p.lda + gc + e] : 0;
-        memcpy(&ra[j], v, 16);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < UB; ++j) {
-      const int u = lane + 64 * j, kp = u / (TN / 8), c = (u % (TN / 8)) * 8;
-      const int gk = k0 + 2 * kp, gc = n0 + c;
-      if (VEC && gk + 1 < p.K && gc + 7 < p.N) {
-        rb0[j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk) * p.ldb + gc);
-        rb1[j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk + 1) * p.ldb + gc);
-      } else {
-        uint16_t lo[8], hi[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          lo[e] = (gk < p.K && gc + e < p.N) ? B[int64_t(gk) * p.ldb + gc + e] : 0;
-          hi[e] = (gk + 1 < p.K && gc + e < p.N) ? B[int64_t(gk + 1) * p.ldb + gc + e] : 0;
-        }
-        memcpy(&rb0[j], lo, 16);
-        memcpy(&rb1[j], hi, 16);
-      }
-    }
-  };
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  load(w);
-  for (int it = 0; it < iters; ++it) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < UA; ++j) {
-      const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      *reinterpret_cast<uint4 *>(&As[r * KP + c]) = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < UB; ++j) {
-      const int u = lane + 64 * j, kp = u / (TN / 8), c = (u % (TN / 8)) * 8;
-      uint16_t lo[8], hi[8];
-      memcpy(lo, &rb0[j], 16);
-      memcpy(hi, &rb1[j], 16);
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        *reinterpret_cast<uint32_t *>(&Bt[(c + e) * KP + 2 * kp]) = uint32_t(lo[e]) | (uint32_t(hi[e]) << 16);
-    }
-    __syncthreads();
-    if (it + 1 < iters) load((it + 1) * 4 + w);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 32) {
-      const int kq = kk + 8 * (lane >> 4);
-      bf16x8 a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[(i * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bt[(j * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  }
-  __syncthreads();
-  float *red = reinterpret_cast<float *>(smem);
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        red[w * TM * TN + (i * 16 + (lane >> 4) * 4 + r) * TN + j * 16 + (lane & 15)] = acc[i][j][r];
-  __syncthreads();
-  for (int e = tid; e < TM * TN; e += 256) {
-    const int row = m0 + e / TN, col = n0 + e % TN;
-    const float v = ((red[e] + red[TM * TN + e]) + red[2 * TM * TN + e]) + red[3 * TM * TN + e];
-    if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * v);
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Row softmax: one wavefront per row, four rows per 256-thread block.  NV > 0: the row is held in
-// registers as NV chunks of 4 per lane (rows up to 256*NV); NV == 0: three passes over memory.
-// The max and the sum are reduced across the wavefront with butterfly shuffles, in FP32.
-// ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_splitk_smem<TM, TN>()];
+  gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 
 template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16>
 __global__ __launch_bounds__(256) void softmax_kernel(SoftmaxArgs p) {
-  const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= p.R) return;
-  const int64_t xo = int64_t(row) * p.ldx, yo = int64_t(row) * p.ldy;
-  const float ninf = -__builtin_huge_valf();
-  if constexpr (NV > 0) {
-    float v[NV][4];
-    float m = ninf;
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      const int c = (t * 64 + lane) * 4;
-      if (VEC && c + 3 < p.C) {
-        if constexpr (IN_BF16) {
-          const uint2 w = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(p.X) + xo + c);
-          v[t][0] = __uint_as_float(w.x << 16); v[t][1] = __uint_as_float(w.x & 0xffff0000u);
-          v[t][2] = __uint_as_float(w.y << 16); v[t][3] = __uint_as_float(w.y & 0xffff0000u);
-        } else {
-          const float4 w = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.X) + xo + c);
-          v[t][0] = w.x; v[t][1] = w.y; v[t][2] = w.z; v[t][3] = w.w;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[t][e] = (c + e < p.C) ? load_elem<IN_BF16>(p.X, xo + c + e) : ninf;
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) m = fmaxf(m, v[t][e]);
-    }
-    m = wave_max(m);
-    float s = 0.f;
-#pragma unroll
-    for (int t = 0; t < NV; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float ex = (v[t][e] == ninf) ? 0.f : __expf(v[t][e] - m);
-        v[t][e] = ex;
-        s += ex;
-      }
-    s = wave_sum(s);
-    const float inv = 1.0f / s;
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      const int c = (t * 64 + lane) * 4;
-      if (VEC && c + 3 < p.C) {
-        if constexpr (OUT_BF16) {
-          uint2 w;
-          w.x = uint32_t(f32_to_bf16(v[t][0] * inv)) | (uint32_t(f32_to_bf16(v[t][1] * inv)) << 16);
-          w.y = uint32_t(f32_to_bf16(v[t][2] * inv)) | (uint32_t(f32_to_bf16(v[t][3] * inv)) << 16);
-          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(p.Y) + yo + c) = w;
-        } else {
-          *reinterpret_cast<float4 *>(static_cast<float *>(p.Y) + yo + c) =
-              make_float4(v[t][0] * inv, v[t][1] * inv, v[t][2] * inv, v[t][3] * inv);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (c + e < p.C) store_elem<OUT_BF16>(p.Y, yo + c + e, v[t][e] * inv);
-      }
-    }
-  } else {
-    float m = ninf;
-    for (int c = lane; c < p.C; c += 64) m = fmaxf(m, load_elem<IN_BF16>(p.X, xo + c));
-    m = wave_max(m);
-    float s = 0.f;
-    for (int c = lane; c < p.C; c += 64) s += __expf(load_elem<IN_BF16>(p.X, xo + c) - m);
-    s = wave_sum(s);
-    const float inv = 1.0f / s;
-    for (int c = lane; c < p.C; c += 64)
-      store_elem<OUT_BF16>(p.Y, yo + c, __expf(load_elem<IN_BF16>(p.X, xo + c) - m) * inv);
-  }
+  if (row < p.R) softmax_row<NV, VEC, IN_BF16, OUT_BF16>(p, row);
 }
 
-// ---------------------------------------------------------------------------------------------
-// Transpose through a padded 64 x 64 LDS tile: coalesced reads along A's rows, coalesced writes
-// along B's rows.  Element size ES bytes (4: f32, 2: bf16); bit-exact.
-// ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_kernel(TransArgs p) {
-  __shared__ T tile[64][65];
-  const int tiles_c = (p.C + 63) / 64;
-  const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const T *A = static_cast<const T *>(p.A);
-  T *B = static_cast<T *>(p.B);
-  T v[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {  // all sixteen loads in flight before the first LDS write
-    const int r = tr * 64 + ty + 4 * i, c = tc * 64 + tx;
-    v[i] = (r < p.R && c < p.C) ? A[int64_t(r) * p.lda + c] : T(0);
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) tile[ty + 4 * i][tx] = v[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = tile[tx][ty + 4 * i];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int orow = tc * 64 + ty + 4 * i, ocol = tr * 64 + tx;
-    if (orow < p.C && ocol < p.R) B[int64_t(orow) * p.ldb + ocol] = v[i];
-  }
+  __shared__ __attribute__((aligned(16))) unsigned char smem[64 * 65 * sizeof(T)];
+  transpose_tile<T>(p, blockIdx.x, smem);
 }
 
-// ---------------------------------------------------------------------------------------------
-// Element-wise add in FP32: grid (ceil(C/256), R), one element per thread.
-// ---------------------------------------------------------------------------------------------
 template <bool IN_BF16, bool OUT_BF16>
 __global__ __launch_bounds__(256) void add_kernel(AddArgs p) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c >= p.C || r >= p.R) return;
-  const float a = load_elem<IN_BF16>(p.A, int64_t(r) * p.lda + c);
-  const float b = load_elem<IN_BF16>(p.B, int64_t(r) * p.ldb + c);
-  store_elem<OUT_BF16>(p.Cp, int64_t(r) * p.ldc + c, a + b);
+  add_block<IN_BF16, OUT_BF16>(p, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -784,7 +201,7 @@ bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype) {
   const bool ib = in_dtype == 1, ob = out_dtype == 1;
   L.func = ib ? (ob ? (const void *)&add_kernel<true, true> : (const void *)&add_kernel<true, false>)
               : (ob ? (const void *)&add_kernel<false, true> : (const void *)&add_kernel<false, false>);
-  L.grid = dim3(unsigned((a.C + 255) / 256), unsigned(a.R), 1);
+  L.grid = dim3(unsigned(int64_t((a.C + 255) / 256) * a.R), 1, 1);
   L.block = dim3(256, 1, 1);
   L.shmem = 0;
   L.empty = a.R == 0 || a.C == 0;

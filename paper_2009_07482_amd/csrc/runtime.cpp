@@ -18,6 +18,7 @@
 #include "core.hpp"
 #include "dispatch.hpp"
 #include "kernels.hpp"
+#include "persistent.hpp"
 
 namespace psc {
 
@@ -51,9 +52,17 @@ struct Device {
   std::vector<psc_op_time> times;
   bool have_times = false;
   std::unique_ptr<Dispatcher> disp;
+  // PSC_DEVICE executor
+  void *exec_mem = nullptr;
+  ExecArgs ea{};
+  int exec_workers = 0;
+  uint32_t *h_err = nullptr;  // page-locked word receiving the executor's error flag
+  double clock_mhz = 100.0;   // device wall clock rate
 
   ~Device() {
     disp.reset();
+    if (exec_mem) (void)hipFree(exec_mem);
+    if (h_err) (void)hipHostFree(h_err);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (hipEvent_t e : op_ev)
@@ -134,6 +143,73 @@ void launch(const Launch &L, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+int in_dtype_of(const Dag &g, const Kernel &k) { return g.bufs[k.ins[0]].dtype; }
+
+// Device-side executor state: node descriptions, successor lists, root tasks, counters, queue.
+void prepare_executor(const Dag &g, Device &d) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  std::vector<ExecNode> nodes(nk);
+  std::vector<int32_t> succ;
+  std::vector<uint64_t> roots;
+  uint64_t total = 0;
+  for (int32_t k = 0; k < nk; ++k) {
+    const Kernel &ker = g.kers[k];
+    nodes[k] = make_exec_node(ker.kind, d.launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
+                              d.launch[k].tile);
+    nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
+    nodes[k].succ_off = static_cast<int32_t>(succ.size());
+    nodes[k].n_succ = static_cast<int32_t>(g.succ[k].size());
+    succ.insert(succ.end(), g.succ[k].begin(), g.succ[k].end());
+    total += uint64_t(nodes[k].n_tiles);
+  }
+  if (total >= (uint64_t(1) << 31)) fail(PSC_ERR_UNSUPPORTED, "too many executor tasks");
+  for (int32_t k = 0; k < nk; ++k)
+    if (!nodes[k].n_pred)
+      for (int32_t t = 0; t < nodes[k].n_tiles; ++t) roots.push_back((uint64_t(k + 1) << 32) | uint32_t(t));
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_nodes = 0, o_succ = o_nodes + up(sizeof(ExecNode) * std::max(1, nk));
+  const size_t o_roots = o_succ + up(4 * std::max<size_t>(1, succ.size()));
+  const size_t o_ctl = o_roots + up(8 * std::max<size_t>(1, roots.size()));
+  const size_t o_pending = o_ctl + 256;
+  const size_t o_done = o_pending + up(4 * std::max(1, nk));
+  const size_t o_slots = o_done + up(4 * std::max(1, nk));
+  const size_t o_tf = o_slots + up(8 * std::max<uint64_t>(1, total));
+  const size_t o_tl = o_tf + up(8 * std::max(1, nk));
+  const size_t o_ts = o_tl + up(8 * std::max(1, nk));
+  const size_t bytes = o_ts + 256;
+  hipError_t e = hipMalloc(&d.exec_mem, bytes);
+  if (e != hipSuccess) fail(PSC_ERR_OOM, std::string("hipMalloc (executor state): ") + hipGetErrorString(e));
+  char *base = static_cast<char *>(d.exec_mem);
+  PSC_HIP(hipMemcpy(base + o_nodes, nodes.data(), sizeof(ExecNode) * nk, hipMemcpyHostToDevice));
+  if (!succ.empty()) PSC_HIP(hipMemcpy(base + o_succ, succ.data(), 4 * succ.size(), hipMemcpyHostToDevice));
+  if (!roots.empty()) PSC_HIP(hipMemcpy(base + o_roots, roots.data(), 8 * roots.size(), hipMemcpyHostToDevice));
+  ExecArgs &a = d.ea;
+  a.nodes = reinterpret_cast<const ExecNode *>(base + o_nodes);
+  a.succ = reinterpret_cast<const int32_t *>(base + o_succ);
+  a.roots = reinterpret_cast<const uint64_t *>(base + o_roots);
+  a.ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
+  a.pending = reinterpret_cast<uint32_t *>(base + o_pending);
+  a.done = reinterpret_cast<uint32_t *>(base + o_done);
+  a.slots = reinterpret_cast<uint64_t *>(base + o_slots);
+  a.t_first = reinterpret_cast<uint64_t *>(base + o_tf);
+  a.t_last = reinterpret_cast<uint64_t *>(base + o_tl);
+  a.t_start = reinterpret_cast<uint64_t *>(base + o_ts);
+  a.n_nodes = nk;
+  a.n_roots = static_cast<int32_t>(roots.size());
+  a.total_tasks = static_cast<uint32_t>(total);
+  a.max_spin = 200000u;
+  d.exec_workers = static_cast<int>(std::min<uint64_t>(total, uint64_t(exec_max_workers(d.device))));
+  PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
+  *d.h_err = 0;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
+    d.clock_mhz = khz / 1000.0;
+}
+
+}  // namespace
+
 void prepare(psc_sched &s) {
   if (s.dev) return;
   const Dag &g = s.dag->g;
@@ -159,16 +235,18 @@ void prepare(psc_sched &s) {
     if (x.parent >= 0) continue;
     d->base[b] = x.bound ? static_cast<char *>(x.bound) : static_cast<char *>(d->arena) + off[b];
   }
-  d->streams.assign(s.plan.total_streams, nullptr);
+  const bool dev_mode = s.plan.device;
+  d->streams.assign(dev_mode ? 1 : s.plan.total_streams, nullptr);
   for (auto &st : d->streams) PSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   d->op_ev.assign(s.plan.ops.size(), nullptr);
-  for (size_t i = 0; i < s.plan.ops.size(); ++i)
-    if (s.plan.ops[i].recorded) PSC_HIP(hipEventCreateWithFlags(&d->op_ev[i], hipEventDisableTiming));
-  d->join_ev.assign(s.plan.total_streams, nullptr);
+  if (!dev_mode)
+    for (size_t i = 0; i < s.plan.ops.size(); ++i)
+      if (s.plan.ops[i].recorded) PSC_HIP(hipEventCreateWithFlags(&d->op_ev[i], hipEventDisableTiming));
+  d->join_ev.assign(d->streams.size(), nullptr);
   for (auto &e : d->join_ev) PSC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   PSC_HIP(hipEventCreate(&d->start));
   PSC_HIP(hipEventCreate(&d->end));
-  if (s.opts.record_ops) {
+  if (s.opts.record_ops && !dev_mode) {
     d->t0.assign(s.plan.ops.size(), nullptr);
     d->t1.assign(s.plan.ops.size(), nullptr);
     for (auto &e : d->t0) PSC_HIP(hipEventCreate(&e));
@@ -176,8 +254,12 @@ void prepare(psc_sched &s) {
   }
   d->launch.assign(g.kers.size(), Launch{});
   for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, *d, int32_t(k), d->launch[k]);
-  const int32_t nt = s.opts.host_threads > 0 ? s.opts.host_threads : s.plan.total_streams;
-  d->disp = std::make_unique<Dispatcher>(s.plan, nt);
+  if (dev_mode) {
+    prepare_executor(g, *d);
+  } else {
+    const int32_t nt = s.opts.host_threads > 0 ? s.opts.host_threads : s.plan.total_streams;
+    d->disp = std::make_unique<Dispatcher>(s.plan, nt);
+  }
   s.dev = std::move(d);
 }
 
@@ -331,7 +413,19 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   const bool timed = s.opts.record_ops != 0;
   hipStream_t s0 = d.streams[0];
   double host_ms = 0;
-  if (s.opts.use_graph) {
+  if (s.plan.device) {
+    const auto h0 = std::chrono::steady_clock::now();
+    PSC_HIP(hipEventRecord(d.start, s0));
+    for (size_t o = 0; o < s.plan.ops.size(); ++o)
+      if (s.plan.ops[o].type == PSC_OP_H2D) do_copy(cd[o], s0);
+    PSC_HIP(launch_exec_reset(d.ea, s0));
+    PSC_HIP(launch_exec(d.ea, d.exec_workers, s0));
+    PSC_HIP(hipMemcpyAsync(d.h_err, d.ea.ctl + 2, 4, hipMemcpyDeviceToHost, s0));
+    for (size_t o = 0; o < s.plan.ops.size(); ++o)
+      if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
+    PSC_HIP(hipEventRecord(d.end, s0));
+    host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  } else if (s.opts.use_graph) {
     std::vector<const void *> key;
     for (const CopyDesc &c : cd) key.push_back(c.active ? (c.kind == hipMemcpyHostToDevice ? c.src : c.dst) : nullptr);
     if (!d.exec || key != d.graph_key) {
@@ -358,7 +452,28 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   PSC_HIP(hipEventSynchronize(d.end));
   float ms = 0;
   PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
-  if (timed) {
+  if (s.plan.device && *d.h_err)
+    fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) +
+                          "): a queue wait or a worker loop exceeded its bound");
+  if (timed && s.plan.device) {
+    const int32_t nk = d.ea.n_nodes;
+    std::vector<uint64_t> tf(nk), tl(nk);
+    uint64_t t0 = 0;
+    PSC_HIP(hipMemcpy(tf.data(), d.ea.t_first, 8 * nk, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(tl.data(), d.ea.t_last, 8 * nk, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(&t0, d.ea.t_start, 8, hipMemcpyDeviceToHost));
+    d.times.assign(s.plan.ops.size(), psc_op_time{0, 0, 0.f, 0.f});
+    for (size_t o = 0; o < s.plan.ops.size(); ++o) {
+      const Op &op = s.plan.ops[o];
+      d.times[o].op = int32_t(o);
+      d.times[o].stream = op.stream;
+      if (op.type == PSC_OP_KERNEL) {
+        d.times[o].start_us = float(double(int64_t(tf[op.kernel] - t0)) / d.clock_mhz);
+        d.times[o].end_us = float(double(int64_t(tl[op.kernel] - t0)) / d.clock_mhz);
+      }
+    }
+    d.have_times = true;
+  } else if (timed) {
     d.times.resize(s.plan.ops.size());
     for (size_t o = 0; o < s.plan.ops.size(); ++o) {
       float a = 0, b = 0;
@@ -424,7 +539,7 @@ float kernel_time(psc_sched &s, int32_t kernel, int32_t iters) {
   Device &d = *s.dev;
   PSC_HIP(hipSetDevice(d.device));
   const Op &op = s.plan.ops[s.plan.kernel_op[kernel]];
-  hipStream_t st = d.streams[op.stream];
+  hipStream_t st = d.streams[s.plan.device ? 0 : op.stream];
   PSC_HIP(hipEventRecord(d.start, st));
   for (int32_t i = 0; i < iters; ++i) launch(d.launch[kernel], st);
   PSC_HIP(hipEventRecord(d.end, st));

@@ -112,7 +112,53 @@ std::unique_ptr<CostModel> make_heuristic_cost() { return std::make_unique<Heuri
 
 CostModel *mlp_cost_model(const psc_mlp *m);  // mlp.cpp
 
+namespace {
+
+// PSC_DEVICE: every H2D first on queue 0, then each kernel on a queue of its own waiting for its
+// predecessor kernels and its inputs' H2D, then every D2H on queue 0 waiting for its producer.
+SchedPlan build_device_plan(const Dag &g) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  SchedPlan plan;
+  plan.device = true;
+  plan.n_streams = plan.total_streams = 1 + nk;
+  const std::vector<int32_t> order = g.bfs_order();
+  std::vector<int32_t> h2d_op(g.bufs.size(), -1);
+  int32_t pos0 = 0;
+  auto emit = [&](int32_t type, int32_t kernel, int32_t buffer, int32_t stream, int32_t pos,
+                  std::vector<int32_t> waits) {
+    Op op;
+    op.type = type;
+    op.kernel = kernel;
+    op.buffer = buffer;
+    op.stream = stream;
+    op.pos = pos;
+    op.host_order = static_cast<int32_t>(plan.ops.size());
+    std::sort(waits.begin(), waits.end());
+    waits.erase(std::unique(waits.begin(), waits.end()), waits.end());
+    for (int32_t w : waits) plan.ops[w].recorded = true;
+    op.waits = std::move(waits);
+    plan.ops.push_back(std::move(op));
+    return static_cast<int32_t>(plan.ops.size() - 1);
+  };
+  for (int32_t k : order)
+    for (int32_t b : g.iso_in[k])
+      if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, 0, pos0++, {});
+  plan.kernel_op.assign(nk, -1);
+  for (int32_t k : order) {
+    std::vector<int32_t> w;
+    for (int32_t p : g.pred[k]) w.push_back(plan.kernel_op[p]);
+    for (int32_t b : g.iso_in[k]) w.push_back(h2d_op[b]);
+    plan.kernel_op[k] = emit(PSC_OP_KERNEL, k, -1, 1 + k, 0, w);
+  }
+  for (int32_t k : order)
+    for (int32_t b : g.iso_out[k]) emit(PSC_OP_D2H, -1, b, 0, pos0++, {plan.kernel_op[k]});
+  return plan;
+}
+
+}  // namespace
+
 SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
+  if (policy == PSC_DEVICE) return build_device_plan(g);
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   SchedPlan plan;
   const int32_t S = policy == PSC_COARSE ? 1 : o.n_streams;

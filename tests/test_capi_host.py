@@ -99,7 +99,7 @@ def _schedules(spec, configs):
     return out
 
 
-CONFIGS = [("coarse", {})] + [
+CONFIGS = [("coarse", {}), ("device", {})] + [
     ("fine", dict(n_streams=s, mapper=m, copy_stream=c))
     for s in (1, 2, 3, 4, 8) for m in ("rr", "eft", "component") for c in (False, True)]
 
@@ -118,6 +118,9 @@ def test_every_schedule_is_valid(name, spec):
         assert ok, (key, errs[:5])
         if key[0] == "coarse":
             assert exp["n_streams"] == 1 and all(not o["waits"] for o in exp["ops"])
+        if key[0] == "device":
+            kern = [o for o in exp["ops"] if o["type"] == "kernel"]
+            assert all(o["pos"] == 0 for o in kern) and len({o["stream"] for o in kern}) == len(kern)
 
 
 def test_tiny_schedules_agree_with_brute_force():
