@@ -2,19 +2,20 @@
 schedules on one MI355X, with a roofline figure for the dominant kernel and the CPU oracle's
 throughput beside it.
 
-Default workload: one multi-head attention layer, n = d = 512, 8 heads of dim 64, FP32 (57
-kernels: per head three projection GEMMs, a transpose, the score GEMM, a row softmax and the
-P*V GEMM; then the output projection).  A step is one pass of the whole DAG -- every kernel
-enqueued on the schedule's streams with its event waits, then a join -- over device-resident
-inputs.  ``value`` is inferences/s of the fine-grained schedule: the clustering scheme of Sec. V
-(each head's kernels form one task component, components on 4 HIP streams), each stream enqueued
-by its own host thread.
+Default workload (--config mha512): one multi-head attention layer, n = d = 512, 8 heads of
+dim 64, FP32: 57 kernels (per head three projection GEMMs, a transpose, the score GEMM, a row
+softmax and the P*V GEMM; then the output projection).  --config mha1024x12: 12 stacked layers,
+16 heads, n = d = 1024, BF16 GEMM operands (1,356 kernels).  A step is one pass of the whole DAG
+over device-resident inputs -- every kernel enqueued on the schedule's streams with its event
+waits, then a join.  ``value`` is inferences/s of the fine-grained schedule: the clustering scheme
+of Sec. V (each head's kernels one task component, components on 4 HIP streams, each stream
+enqueued by its own host thread).  GEMM tiles are chosen by the autotuner first (--no-tune: size
+heuristic).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha512|mha1024x12|forkjoin]
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -30,33 +31,43 @@ PEAK = {"mfma_f32": 157.3e12, "mfma_bf16": 2.5e15, "hbm": 8.0e12}
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--config", default="mha512")
     p.add_argument("--streams", type=int, default=4)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--graph", action="store_true", help="also time the schedule launched as one hipGraph")
+    p.add_argument("--variants", action="store_true", help="also time other fine-grained variants")
     p.add_argument("--kernel-iters", type=int, default=200)
-    return p.parse_args()
+    a = p.parse_args()
+    big = a.config == "mha1024x12"
+    if a.steps is None:
+        a.steps = 20 if big else 300
+    if a.warmup is None:
+        a.warmup = 3 if big else 30
+    return a
 
 
 def workload(name):
     import workloads
+    if name == "forkjoin":
+        spec = workloads.forkjoin_spec(256)
+        return spec, workloads.forkjoin_inputs(0, 256), {"workload": "fork-join DAG (Fig. 1 shape), 3 GEMMs 256^3 + add, FP32",
+                                                         "gemm_dtype": "f32"}
     if name == "mha512":
         n, d, h, L, dt = 512, 512, 8, 1, "f32"
     elif name == "mha1024x12":
         n, d, h, L, dt = 1024, 1024, 16, 12, "bf16"
-    elif name == "forkjoin":
-        spec = workloads.forkjoin_spec(256)
-        return spec, workloads.forkjoin_inputs(0, 256), {"workload": "fork-join 4 GEMM/add, 256x256, FP32"}
     else:
         raise SystemExit(f"unknown config {name}")
     spec = workloads.mha_spec(n, d, h, L, gemm_dtype=dt)
     inp = workloads.mha_inputs(0, n, d, L)
     desc = {"workload": f"multi-head attention inference DAG, {L} layer(s), n={n}, d_model={d}, "
-                        f"{h} heads of dim {d // h}, GEMM {dt.upper()}",
-            "seq_len": n, "d_model": d, "heads": h, "layers": L, "gemm_dtype": dt}
+                        f"{h} heads of dim {d // h}, GEMM {dt.upper()}" + (" (FP32 accumulation)" if dt == "bf16" else ""),
+            "seq_len": n, "d_model": d, "heads": h, "layers": L, "gemm_dtype": dt,
+            "kernels": len(spec["kernels"])}
     return spec, inp, desc
 
 
@@ -106,7 +117,23 @@ def cpu_baseline(spec, inp, seconds):
         if el >= seconds or n >= 1000:
             break
     return {"value": n / el, "unit": "inferences/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} full runs of the same DAG in FP64 (numpy), {el:.1f} s"}
+            "sample": f"{n} full run(s) of the same DAG in FP64 (numpy), {el:.1f} s"}
+
+
+def overlap(times):
+    """Mean number of ops in flight over the busy time of a per-op timeline."""
+    ivals = sorted((t[2], t[3]) for t in times if t[3] > t[2])
+    busy, cs, ce = 0.0, None, None
+    for s0, e0 in ivals:
+        if ce is None or s0 > ce:
+            if ce is not None:
+                busy += ce - cs
+            cs, ce = s0, e0
+        else:
+            ce = max(ce, e0)
+    if ce is not None:
+        busy += ce - cs
+    return sum(e - s for s, e in ivals) / busy if busy > 0 else 0.0
 
 
 def main():
@@ -117,23 +144,43 @@ def main():
     import paper_2009_07482_amd as psc
 
     spec, inp, desc = workload(a.config)
+    tuned = 0
+    if not a.no_tune:
+        d0 = psc.build_dag(spec)
+        tuned = psc.psc_autotune_dag(d0, iters=20)
+        psc.psc_dag_destroy(d0)
+
+    S = a.streams
+    # schedule autotuner: stream count, mapper and enqueue threads of the fine schedule
+    cands = [dict(n_streams=s_, mapper=m_, host_threads=t_) for s_ in (2, 4, 8) for m_ in ("component", "rr")
+             for t_ in (1, 0)]
+    d1 = psc.build_dag(spec)
+    bi, cms = psc.psc_autotune_schedule(d1, "fine", cands, iters=max(5, a.steps // 10))
+    psc.psc_dag_destroy(d1)
+    fine_opts = cands[bi]
+    print(f"# schedule autotuner: chose {fine_opts} ({cms[bi]:.3f} ms/run) among "
+          + ", ".join(f"{c['n_streams']}/{c['mapper']}/{'1t' if c['host_threads'] == 1 else 'mt'}={m:.3f}"
+                      for c, m in zip(cands, cms)), file=sys.stderr, flush=True)
     runners = {
         "coarse": psc.SpecRunner(spec, "coarse"),
-        "fine": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component"),
-        "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component", host_threads=1),
-        "fine_rr": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr"),
-        "fine_rr_1thread": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", host_threads=1),
-        "fine_eft": psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="eft"),
-        "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="component"),
-        "device": psc.SpecRunner(spec, "device"),
+        "fine": psc.SpecRunner(spec, "fine", **fine_opts),
     }
+    if a.variants:
+        runners.update({
+            "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", host_threads=1),
+            "fine_rr": psc.SpecRunner(spec, "fine", n_streams=S, mapper="rr"),
+            "fine_eft": psc.SpecRunner(spec, "fine", n_streams=S, mapper="eft"),
+            "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="component"),
+            "fine_copystream": psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", copy_stream=True),
+            "device": psc.SpecRunner(spec, "device"),
+        })
     if a.graph:
-        runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="rr", use_graph=True)
+        runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", use_graph=True)
     res = {}
     for name, r in runners.items():
         r.set_inputs(inp)
-        st_io = r.run()                      # uploads inputs (and measures the PCIe-inclusive makespan)
-        for _ in range(3):
+        st_io = r.run()                      # uploads inputs; PCIe-inclusive makespan
+        for _ in range(2):
             st_io = r.run()
         wall, mk, st = timed(r, a.steps, a.warmup)
         res[name] = {"ms_per_step": wall / a.steps * 1e3, "makespan_ms_median": float(np.median(mk)),
@@ -154,9 +201,12 @@ def main():
         psc.psc_kernel_time(r.sched, c["ids"][0], 10)
         c["avg_us"] = psc.psc_kernel_time(r.sched, c["ids"][0], a.kernel_iters)
         c["total_us"] = c["avg_us"] * len(c["ids"])
+        if c["bound"] == "mfma":
+            c["tile"] = psc.psc_sched_kernel_tile(r.sched, c["ids"][0])
     print("# kernel classes (isolated mean us per launch x launches per step):", file=sys.stderr)
     for key, c in sorted(kers.items(), key=lambda kv: -kv[1]["total_us"]):
-        print(f"#   {key}: {c['avg_us']:.2f} us x {len(c['ids'])}", file=sys.stderr)
+        print(f"#   {key}: {c['avg_us']:.2f} us x {len(c['ids'])}" + (f" (tile {c['tile']})" if "tile" in c else ""),
+              file=sys.stderr)
     dom_key = max(kers, key=lambda k: kers[k]["total_us"])
     dom = kers[dom_key]
     avg_us = dom["avg_us"]
@@ -169,40 +219,28 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                 "frac": achieved / PEAK["hbm"], "traffic": None}
     roof.update({"kernel": dom_key, "avg_us": avg_us, "launches_per_step": len(dom["ids"]),
-                 "work_per_launch": dom["work"], "timing": f"{a.kernel_iters} back-to-back launches, HIP events on its stream"})
+                 "work_per_launch": dom["work"],
+                 "timing": f"{a.kernel_iters} back-to-back launches, HIP events on its stream"})
 
-    # per-op timeline of the fine schedule (start/end events around every op): concurrency
-    rec = psc.SpecRunner(spec, "fine", n_streams=a.streams, mapper="component", record_ops=True)
+    # concurrency of the fine schedule from a per-op timeline (start/end events around every op)
+    rec = psc.SpecRunner(spec, "fine", record_ops=True, **fine_opts)
     rec.set_inputs(inp)
     rec.run()
     rec.run(with_inputs=False, with_outputs=False)
-    times = psc.psc_sched_op_times(rec.sched)
+    concurrency = overlap(psc.psc_sched_op_times(rec.sched))
     rec.close()
-    ivals = sorted((t[2], t[3]) for t in times)
-    busy, cur_s, cur_e = 0.0, None, None
-    for s0, e0 in ivals:
-        if cur_e is None or s0 > cur_e:
-            if cur_e is not None:
-                busy += cur_e - cur_s
-            cur_s, cur_e = s0, e0
-        else:
-            cur_e = max(cur_e, e0)
-    if cur_e is not None:
-        busy += cur_e - cur_s
-    op_sum = sum(e0 - s0 for s0, e0 in ivals)
-    concurrency = op_sum / busy if busy > 0 else 0.0
 
     fine = res["fine"]
-    value = 1e3 / fine["ms_per_step"]
     line = {
         "metric": "DAG makespan (ms) + inferences/s, fine vs coarse schedule, BF16 vs FP32",
-        "value": value, "unit": "inferences/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": fine["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if desc.get("gemm_dtype", "f32") == "f32" else "bf16",
+        "value": 1e3 / fine["ms_per_step"], "unit": "inferences/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": fine["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": desc.get("gemm_dtype", "f32"),
         "data": "synthetic (seeded N(0,1) inputs, N(0,1/d) weights)",
-        "config": dict(desc, schedule=f"fine (clustering: one task component per head), {a.streams} HIP streams, "
-                                      f"one enqueue thread per stream",
-                       inputs="device-resident"),
+        "config": dict(desc, schedule=f"fine, chosen by the schedule autotuner: {fine_opts['n_streams']} HIP streams, "
+                                      f"{'clustering (one task component per head per stream)' if fine_opts['mapper'] == 'component' else 'round robin per kernel'}, "
+                                      f"{'one enqueue thread' if fine_opts['host_threads'] == 1 else 'one enqueue thread per stream'}",
+                       inputs="device-resident", gemm_tiles="autotuned" if tuned else "size heuristic"),
         "makespan_ms": {k: v["makespan_ms_median"] for k, v in res.items()},
         "ms_per_step_by_schedule": {k: v["ms_per_step"] for k, v in res.items()},
         "makespan_with_copies_ms": {k: v["makespan_with_copies_ms"] for k, v in res.items()},
@@ -213,7 +251,17 @@ def main():
     for r in runners.values():
         r.close()
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(spec, inp, a.cpu_seconds)
+        if a.config == "mha1024x12":
+            # bounded sample: the first 2 of the 12 identical-shape layers, scaled to 12
+            import workloads
+            sub = workloads.mha_spec(1024, 1024, 16, 2, gemm_dtype="bf16")
+            sub_inp = {k: v for k, v in inp.items() if k in set(workloads.host_inputs_of(sub))}
+            cb = cpu_baseline(sub, sub_inp, a.cpu_seconds)
+            cb["value"] *= 2.0 / 12.0
+            cb["sample"] += "; first 2 of 12 layers, rate scaled by 2/12"
+            line["cpu_baseline"] = cb
+        else:
+            line["cpu_baseline"] = cpu_baseline(spec, inp, a.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

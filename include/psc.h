@@ -291,6 +291,124 @@ psc_status psc_device_sync(int32_t device);
 psc_status psc_sched_dispatch_trace(const psc_sched *sched, int32_t host_threads, int32_t jitter_us,
                                     uint32_t seed, int32_t *out, int32_t cap, int32_t *n);
 
+/* ---------------------------------------------------------------------------------------------
+ * Learned cost model (machine-learning assisted scheduling, future work of Sec. VII).
+ *
+ * Every op is described by PSC_FEATURES float32 features:
+ *   [0..5]  one-hot kind: GEMM, transpose, softmax, add, H2D, D2H
+ *   [6]     log2 M (output rows; for a copy, the buffer's rows)   [7] log2 N (output columns)
+ *   [8]     log2 K (GEMM inner dimension, else 0)                 [9] log2 of the algorithmic bytes
+ *   [10]    1 if the first operand (or the copied buffer) is BF16  [11] other streams with an op
+ *                                                                      in flight when it starts
+ * The model is a perceptron PSC_FEATURES -> 64 -> 64 -> 1 with ReLU that predicts ln(duration in
+ * microseconds) from z-scored features; parameters are PSC_MLP_PARAMS float32 values laid out as
+ * W1 (64 x 12, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (64), b3 (1).  It is trained on the
+ * GPU (forward, back-propagation and Adam kernels) from the samples psc_sched_samples returns and
+ * is used by PSC_MAP_EFT through psc_sched_opts.cost.  A model belongs to one device; calls on one
+ * model are serialised internally.
+ * ------------------------------------------------------------------------------------------- */
+#define PSC_FEATURES 12
+#define PSC_MLP_PARAMS 5057
+
+typedef struct psc_mlp_train_opts {
+  int32_t epochs;         /* passes over the samples (>= 1) */
+  int32_t batch;          /* samples per Adam step (>= 1); the last step of a pass may be smaller */
+  float lr, beta1, beta2, eps;  /* Adam (Kingma and Ba, 2015); e.g. 1e-3, 0.9, 0.999, 1e-8 */
+  uint64_t shuffle_seed;  /* 0: samples in their given order every pass; else a seeded shuffle */
+  int32_t reserved[4];
+} psc_mlp_train_opts;
+
+/* [GPU] A model on `device` with all parameters zero and identity feature scaling. */
+psc_status psc_mlp_create(int32_t device, psc_mlp **out);
+psc_status psc_mlp_destroy(psc_mlp *m);
+
+/* [GPU] Sets / reads the PSC_MLP_PARAMS parameters (n must equal it).  Setting them also clears
+ * the Adam moments and step count.  PSC_ERR_ARG on a wrong n or NULL. */
+psc_status psc_mlp_set_params(psc_mlp *m, const float *params, int64_t n);
+psc_status psc_mlp_get_params(psc_mlp *m, float *params, int64_t n);
+
+/* [GPU] Feature scaling: the network sees (x[f] - mean[f]) / std[f].  std must be > 0. */
+psc_status psc_mlp_set_norm(psc_mlp *m, const float *mean, const float *std_dev);
+
+/* [GPU] Predictions (ln microseconds) y[0..n) for feature rows x[n][PSC_FEATURES] (host memory). */
+psc_status psc_mlp_predict(psc_mlp *m, const float *x, int64_t n, float *y);
+
+/* [GPU] Gradient of the mean squared error mean((y - t)^2) over the n rows with respect to every
+ * parameter (grads: PSC_MLP_PARAMS floats, may be NULL) and the loss itself (*loss, may be NULL),
+ * without changing the parameters.  For gradient checks. */
+psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss);
+
+/* [GPU] Trains on n samples (features x, targets t = ln microseconds): opts->epochs passes of
+ * mini-batch Adam steps.  epoch_loss[e] (may be NULL) receives the mean squared error over all n
+ * samples after pass e.  Errors: PSC_ERR_ARG (sizes, hyper-parameters), PSC_ERR_HIP. */
+psc_status psc_mlp_train(psc_mlp *m, const float *x, const float *t, int64_t n, const psc_mlp_train_opts *opts,
+                         float *epoch_loss);
+
+/* Predicted microseconds of each feature row under the cost model `m`, or under the roofline
+ * heuristic when m == NULL (host only in that case). */
+psc_status psc_cost_predict(psc_mlp *m, const float *x, int64_t n, float *us);
+
+/* Feature row (PSC_FEATURES floats into f) of kernel `kernel` of a validated DAG (one that has
+ * been scheduled) with `in_flight` other streams busy.  Host only.  Errors: PSC_ERR_ARG,
+ * PSC_ERR_STATE (DAG not validated yet). */
+psc_status psc_kernel_features(const psc_dag *dag, int32_t kernel, int32_t in_flight, float *f);
+
+/* Training samples from the last psc_run made with record_ops = 1: one per op that did work (a
+ * launched kernel, a copy that was given host memory), in op order.  features[i][PSC_FEATURES]
+ * and log_us[i] = ln(measured duration in microseconds); feature 11 counts the other streams
+ * with an op whose recorded interval contains this op's start.  Either array may be NULL;
+ * *n = number of samples; PSC_ERR_ARG if cap < *n; PSC_ERR_STATE without a recorded run. */
+psc_status psc_sched_samples(const psc_sched *sched, float *features, float *log_us, int32_t cap, int32_t *n);
+
+/* ---------------------------------------------------------------------------------------------
+ * GEMM tile autotuner.  Tile configurations are numbered 1 .. n-1 (psc_gemm_tile_count gives n):
+ * 1..5 large-tile kernels (128x128, 64x64, 32x32, 128x64, 64x128), 6..12 K-split small-tile
+ * kernels (64x64, 32x64, 64x32, 32x32, 16x32, 32x16, 16x16).  A GEMM whose params leave tile at
+ * 0 takes the process-wide cache entry for its (M, N, K, operand dtype, output dtype) when there
+ * is one, and a size heuristic otherwise; the choice is made when a schedule is prepared.  The
+ * cache is thread safe.  (The paper leaves autotuning to future work, Sec. VII.)
+ * ------------------------------------------------------------------------------------------- */
+
+/* Number of tile configuration indices (valid configurations are 1 .. *n - 1). */
+psc_status psc_gemm_tile_count(int32_t *n);
+
+/* Sets (tile > 0) or removes (tile = 0) the cache entry for one GEMM shape and dtype pair. */
+psc_status psc_tile_cache_set(int32_t M, int32_t N, int32_t K, int32_t ab_dtype, int32_t c_dtype,
+                              int32_t tile);
+
+/* Cache entry for a shape, 0 if none. */
+psc_status psc_tile_cache_get(int32_t M, int32_t N, int32_t K, int32_t ab_dtype, int32_t c_dtype,
+                              int32_t *tile);
+
+/* Empties the cache; *n_removed (may be NULL) receives the number of entries it held. */
+psc_status psc_tile_cache_clear(int32_t *n_removed);
+
+/* [GPU] Times every tile configuration for C (M x N) = A (M x K) * B (K x N) on zero-filled
+ * device buffers (iters back-to-back launches between HIP events, after 3 warm-up launches),
+ * stores the fastest in the cache and returns it in *best_tile and its mean microseconds in
+ * *best_us.  us_per_tile[t] for t < cap receives every configuration's time (index 0 unused).
+ * Any output pointer may be NULL.  Errors: PSC_ERR_ARG, PSC_ERR_HIP, PSC_ERR_OOM. */
+psc_status psc_autotune_gemm(int32_t device, int32_t M, int32_t N, int32_t K, int32_t ab_dtype,
+                             int32_t c_dtype, int32_t iters, int32_t *best_tile, float *best_us,
+                             float *us_per_tile, int32_t cap);
+
+/* [GPU] psc_autotune_gemm for every distinct GEMM shape of the DAG whose tile is automatic;
+ * *n_tuned (may be NULL) receives the number of shapes tuned.  Schedules prepared afterwards
+ * use the tuned tiles. */
+psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t *n_tuned);
+
+/* [GPU] Schedule autotuner: builds a `policy` schedule of the DAG for each of the n candidate
+ * option sets, runs each `iters` times on device-resident data (after 2 warm-up runs) and returns
+ * the index of the one with the smallest mean wall time per run in *best; ms_per_run[i] (may be
+ * NULL) receives candidate i's mean milliseconds.  Candidates that fail to schedule get a time
+ * of -1 and are skipped.  Paired with psc_autotune_dag it chooses tiles, stream count, mapper
+ * and enqueue threads by measurement.  Errors: PSC_ERR_ARG (no candidate ran), PSC_ERR_HIP. */
+psc_status psc_autotune_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *candidates,
+                                 int32_t n, int32_t iters, int32_t *best, float *ms_per_run);
+
+/* [GPU after prepare] Tile configuration a prepared schedule uses for GEMM kernel `kernel`. */
+psc_status psc_sched_kernel_tile(const psc_sched *sched, int32_t kernel, int32_t *tile);
+
 /* Frees device storage, streams, events and graphs of the schedule.  NULL is ignored. */
 psc_status psc_sched_destroy(psc_sched *sched);
 

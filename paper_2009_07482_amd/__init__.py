@@ -83,6 +83,15 @@ class psc_op_time(C.Structure):
                 ("end_us", C.c_float)]
 
 
+class psc_mlp_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("shuffle_seed", C.c_uint64),
+                ("reserved", C.c_int32 * 4)]
+
+
+PSC_FEATURES = 12
+PSC_MLP_PARAMS = 5057
+
 _P = C.c_void_p
 _I = C.c_int32
 _I64 = C.c_int64
@@ -113,6 +122,27 @@ _SIGS = {
     "psc_host_free": [_P],
     "psc_device_sync": [_I],
     "psc_sched_dispatch_trace": [_P, _I, _I, C.c_uint32, C.POINTER(_I), _I, C.POINTER(_I)],
+    "psc_gemm_tile_count": [C.POINTER(_I)],
+    "psc_tile_cache_set": [_I, _I, _I, _I, _I, _I],
+    "psc_tile_cache_get": [_I, _I, _I, _I, _I, C.POINTER(_I)],
+    "psc_tile_cache_clear": [C.POINTER(_I)],
+    "psc_autotune_gemm": [_I, _I, _I, _I, _I, _I, _I, C.POINTER(_I), C.POINTER(C.c_float),
+                          C.POINTER(C.c_float), _I],
+    "psc_autotune_dag": [_P, _I, _I, C.POINTER(_I)],
+    "psc_sched_kernel_tile": [_P, _I, C.POINTER(_I)],
+    "psc_mlp_create": [_I, C.POINTER(_P)],
+    "psc_mlp_destroy": [_P],
+    "psc_mlp_set_params": [_P, C.c_void_p, _I64],
+    "psc_mlp_get_params": [_P, C.c_void_p, _I64],
+    "psc_mlp_set_norm": [_P, C.c_void_p, C.c_void_p],
+    "psc_mlp_predict": [_P, C.c_void_p, _I64, C.c_void_p],
+    "psc_mlp_grad": [_P, C.c_void_p, C.c_void_p, _I64, C.c_void_p, C.POINTER(C.c_double)],
+    "psc_mlp_train": [_P, C.c_void_p, C.c_void_p, _I64, C.POINTER(psc_mlp_train_opts), C.c_void_p],
+    "psc_cost_predict": [_P, C.c_void_p, _I64, C.c_void_p],
+    "psc_kernel_features": [_P, _I, _I, C.c_void_p],
+    "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
+    "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
+                              C.POINTER(C.c_float)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -273,6 +303,119 @@ def psc_sched_op_times(sched):
     return [(t.op, t.stream, t.start_us, t.end_us) for t in buf[:n.value]]
 
 
+def psc_sched_samples(sched):
+    """Cost-model samples of the last recorded run: (features [n, 12] float32, ln us [n])."""
+    import numpy as np
+    n = _I()
+    _check(_lib.psc_sched_samples(sched, None, None, 0, C.byref(n)))
+    f = np.zeros((max(1, n.value), PSC_FEATURES), np.float32)
+    t = np.zeros(max(1, n.value), np.float32)
+    _check(_lib.psc_sched_samples(sched, f.ctypes.data, t.ctypes.data, n.value, C.byref(n)))
+    return f[:n.value], t[:n.value]
+
+
+def _f32(a, shape=None):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def psc_mlp_create(device=0):
+    h = _P()
+    _check(_lib.psc_mlp_create(int(device), C.byref(h)))
+    return h
+
+
+def psc_mlp_destroy(m):
+    _check(_lib.psc_mlp_destroy(m))
+
+
+def psc_mlp_set_params(m, flat):
+    flat = _f32(flat, (-1,))
+    _check(_lib.psc_mlp_set_params(m, flat.ctypes.data, flat.size))
+
+
+def psc_mlp_get_params(m):
+    import numpy as np
+    out = np.zeros(PSC_MLP_PARAMS, np.float32)
+    _check(_lib.psc_mlp_get_params(m, out.ctypes.data, out.size))
+    return out
+
+
+def psc_mlp_set_norm(m, mean, std):
+    mean, std = _f32(mean, (PSC_FEATURES,)), _f32(std, (PSC_FEATURES,))
+    _check(_lib.psc_mlp_set_norm(m, mean.ctypes.data, std.ctypes.data))
+
+
+def psc_mlp_predict(m, x):
+    import numpy as np
+    x = _f32(x, (-1, PSC_FEATURES))
+    y = np.zeros(x.shape[0], np.float32)
+    _check(_lib.psc_mlp_predict(m, x.ctypes.data, x.shape[0], y.ctypes.data))
+    return y
+
+
+def psc_mlp_grad(m, x, t):
+    """(flat gradient [PSC_MLP_PARAMS], loss) of the mean squared error at the current parameters."""
+    import numpy as np
+    x = _f32(x, (-1, PSC_FEATURES))
+    t = _f32(t, (-1,))
+    g = np.zeros(PSC_MLP_PARAMS, np.float32)
+    loss = C.c_double()
+    _check(_lib.psc_mlp_grad(m, x.ctypes.data, t.ctypes.data, x.shape[0], g.ctypes.data, C.byref(loss)))
+    return g, loss.value
+
+
+def psc_mlp_train(m, x, t, epochs=50, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, shuffle_seed=0):
+    """Mini-batch Adam on the GPU; returns the per-epoch training loss."""
+    import numpy as np
+    x = _f32(x, (-1, PSC_FEATURES))
+    t = _f32(t, (-1,))
+    o = psc_mlp_train_opts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                           int(shuffle_seed))
+    losses = np.zeros(int(epochs), np.float32)
+    _check(_lib.psc_mlp_train(m, x.ctypes.data, t.ctypes.data, x.shape[0], C.byref(o), losses.ctypes.data))
+    return losses
+
+
+def psc_kernel_features(dag, kernel, in_flight=0):
+    import numpy as np
+    f = np.zeros(PSC_FEATURES, np.float32)
+    _check(_lib.psc_kernel_features(dag, int(kernel), int(in_flight), f.ctypes.data))
+    return f
+
+
+def psc_cost_predict(x, m=None):
+    """Predicted microseconds of feature rows under the MLP ``m`` or, with m None, the heuristic."""
+    import numpy as np
+    x = _f32(x, (-1, PSC_FEATURES))
+    us = np.zeros(x.shape[0], np.float32)
+    _check(_lib.psc_cost_predict(m, x.ctypes.data, x.shape[0], us.ctypes.data))
+    return us
+
+
+# flat parameter layout of the cost model
+MLP_LAYOUT = (("W1", (64, PSC_FEATURES)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)),
+              ("b3", (1,)))
+
+
+def mlp_flatten(params):
+    import numpy as np
+    return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k, _ in MLP_LAYOUT])
+
+
+def mlp_unflatten(flat):
+    import numpy as np
+    out, off = {}, 0
+    for k, shp in MLP_LAYOUT:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(flat[off:off + n]).reshape(shp)
+        off += n
+    return out
+
+
 def psc_sched_device_ptr(sched, name):
     p, ld = _P(), _I64()
     _check(_lib.psc_sched_device_ptr(sched, _b(name), C.byref(p), C.byref(ld)))
@@ -293,6 +436,65 @@ def psc_sched_dispatch_trace(sched, host_threads=0, jitter_us=0, seed=0):
     _check(_lib.psc_sched_dispatch_trace(sched, int(host_threads), int(jitter_us), int(seed), buf, cap,
                                          C.byref(n)))
     return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n.value)]
+
+
+def _dt(x):
+    return DTYPES[x] if isinstance(x, str) else int(x)
+
+
+def psc_gemm_tile_count():
+    n = _I()
+    _check(_lib.psc_gemm_tile_count(C.byref(n)))
+    return n.value
+
+
+def psc_tile_cache_set(M, N, K, ab, c, tile):
+    _check(_lib.psc_tile_cache_set(int(M), int(N), int(K), _dt(ab), _dt(c), int(tile)))
+
+
+def psc_tile_cache_get(M, N, K, ab, c):
+    t = _I()
+    _check(_lib.psc_tile_cache_get(int(M), int(N), int(K), _dt(ab), _dt(c), C.byref(t)))
+    return t.value
+
+
+def psc_tile_cache_clear():
+    n = _I()
+    _check(_lib.psc_tile_cache_clear(C.byref(n)))
+    return n.value
+
+
+def psc_autotune_gemm(M, N, K, ab="f32", c="f32", iters=50, device=0):
+    """Returns (best tile, best microseconds, {tile: microseconds})."""
+    nt = psc_gemm_tile_count()
+    best, us = _I(), C.c_float()
+    arr = (C.c_float * nt)()
+    _check(_lib.psc_autotune_gemm(int(device), int(M), int(N), int(K), _dt(ab), _dt(c), int(iters),
+                                  C.byref(best), C.byref(us), arr, nt))
+    return best.value, us.value, {t: arr[t] for t in range(1, nt)}
+
+
+def psc_autotune_dag(dag, iters=50, device=0):
+    n = _I()
+    _check(_lib.psc_autotune_dag(dag, int(device), int(iters), C.byref(n)))
+    return n.value
+
+
+def psc_autotune_schedule(dag, policy, candidates, iters=20):
+    """candidates: list of make_opts() keyword dicts.  Returns (best index, [ms per run])."""
+    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+           if isinstance(policy, str) else int(policy))
+    arr = (psc_sched_opts * len(candidates))(*[make_opts(**c) for c in candidates])
+    best = _I()
+    ms = (C.c_float * len(candidates))()
+    _check(_lib.psc_autotune_schedule(dag, pol, arr, len(candidates), int(iters), C.byref(best), ms))
+    return best.value, list(ms)
+
+
+def psc_sched_kernel_tile(sched, kernel):
+    t = _I()
+    _check(_lib.psc_sched_kernel_tile(sched, int(kernel), C.byref(t)))
+    return t.value
 
 
 def psc_sched_destroy(sched):
@@ -432,6 +634,9 @@ class SpecRunner:
 
     def export(self):
         return export_schedule(self.spec, self.sched)
+
+    def samples(self):
+        return psc_sched_samples(self.sched)
 
     def close(self):
         if self.sched is not None:

@@ -1,7 +1,10 @@
 // extern "C" entry points declared in include/psc.h.  Each call converts internal errors into a
 // psc_status and a thread-local message; no exception crosses the boundary.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <memory>
 #include <new>
 #include <string>
@@ -12,16 +15,26 @@
 
 #include "core.hpp"
 #include "dispatch.hpp"
+#include "mlp.hpp"
 
 namespace psc {
 void prepare(psc_sched &s);
 void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats);
 void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n);
+void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_t *n);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
 float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
 void host_free(void *p);
 void device_sync(int device);
+int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, float *best_us, float *us_per_tile,
+                  int cap);
+int sched_kernel_tile(const psc_sched &s, int32_t kernel);
+void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
+int tile_cache_get(int M, int N, int K, int ab, int c);
+void tile_cache_clear();
+size_t tile_cache_size();
+int gemm_num_tiles();
 }  // namespace psc
 
 namespace {
@@ -303,6 +316,100 @@ psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t 
   });
 }
 
+psc_status psc_sched_samples(const psc_sched *sched, float *features, float *log_us, int32_t cap, int32_t *n) {
+  return guard([&] {
+    need(sched && n, PSC_ERR_ARG, "NULL argument");
+    psc::samples(*sched, features, log_us, cap, n);
+  });
+}
+
+psc_status psc_mlp_create(int32_t device, psc_mlp **out) {
+  return guard([&] {
+    need(out != nullptr, PSC_ERR_ARG, "NULL out");
+    *out = psc::mlp_create(device);
+  });
+}
+
+psc_status psc_mlp_destroy(psc_mlp *m) {
+  return guard([&] { delete m; });
+}
+
+psc_status psc_mlp_set_params(psc_mlp *m, const float *params, int64_t n) {
+  return guard([&] {
+    need(m && params, PSC_ERR_ARG, "NULL argument");
+    need(n == psc::kMlpP, PSC_ERR_ARG, "parameter count must be PSC_MLP_PARAMS");
+    psc::mlp_set_params(*m, params);
+  });
+}
+
+psc_status psc_mlp_get_params(psc_mlp *m, float *params, int64_t n) {
+  return guard([&] {
+    need(m && params, PSC_ERR_ARG, "NULL argument");
+    need(n == psc::kMlpP, PSC_ERR_ARG, "parameter count must be PSC_MLP_PARAMS");
+    psc::mlp_get_params(*m, params);
+  });
+}
+
+psc_status psc_mlp_set_norm(psc_mlp *m, const float *mean, const float *std_dev) {
+  return guard([&] {
+    need(m && mean && std_dev, PSC_ERR_ARG, "NULL argument");
+    psc::mlp_set_norm(*m, mean, std_dev);
+  });
+}
+
+psc_status psc_mlp_predict(psc_mlp *m, const float *x, int64_t n, float *y) {
+  return guard([&] {
+    need(m && x && y, PSC_ERR_ARG, "NULL argument");
+    psc::mlp_predict(*m, x, n, y);
+  });
+}
+
+psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss) {
+  return guard([&] {
+    need(m && x && t, PSC_ERR_ARG, "NULL argument");
+    const double l = psc::mlp_grad(*m, x, t, n, grads);
+    if (loss) *loss = l;
+  });
+}
+
+psc_status psc_mlp_train(psc_mlp *m, const float *x, const float *t, int64_t n, const psc_mlp_train_opts *opts,
+                         float *epoch_loss) {
+  return guard([&] {
+    need(m && x && t && opts, PSC_ERR_ARG, "NULL argument");
+    psc::MlpTrainOpts o;
+    o.epochs = opts->epochs;
+    o.batch = opts->batch;
+    o.lr = opts->lr;
+    o.beta1 = opts->beta1;
+    o.beta2 = opts->beta2;
+    o.eps = opts->eps;
+    o.shuffle_seed = opts->shuffle_seed;
+    psc::mlp_train(*m, x, t, n, o, epoch_loss);
+  });
+}
+
+psc_status psc_kernel_features(const psc_dag *dag, int32_t kernel, int32_t in_flight, float *f) {
+  return guard([&] {
+    need(dag && f, PSC_ERR_ARG, "NULL argument");
+    need(dag->g.validated, PSC_ERR_STATE, "DAG not validated (schedule it first)");
+    need(kernel >= 0 && kernel < int32_t(dag->g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
+    need(in_flight >= 0, PSC_ERR_ARG, "negative in_flight");
+    psc::kernel_features(dag->g, kernel, in_flight, f);
+  });
+}
+
+psc_status psc_cost_predict(psc_mlp *m, const float *x, int64_t n, float *us) {
+  return guard([&] {
+    need(x && us, PSC_ERR_ARG, "NULL argument");
+    need(n >= 0, PSC_ERR_ARG, "negative row count");
+    if (n == 0) return;
+    auto cost = m ? psc::mlp_cost_model(m) : psc::make_heuristic_cost();
+    std::vector<double> d(n);
+    cost->predict_us(x, n, d.data());
+    for (int64_t i = 0; i < n; ++i) us[i] = float(d[i]);
+  });
+}
+
 psc_status psc_sched_device_ptr(const psc_sched *sched, const char *name, void **dptr, int64_t *ld) {
   return guard([&] {
     need(sched && name, PSC_ERR_ARG, "NULL argument");
@@ -379,6 +486,112 @@ psc_status psc_sched_dispatch_trace(const psc_sched *sched, int32_t host_threads
       need(cap >= int32_t(tb.ev.size()), PSC_ERR_ARG, "capacity too small");
       std::copy(tb.ev.begin(), tb.ev.end(), out);
     }
+  });
+}
+
+psc_status psc_gemm_tile_count(int32_t *n) {
+  return guard([&] {
+    need(n != nullptr, PSC_ERR_ARG, "NULL n");
+    *n = psc::gemm_num_tiles();
+  });
+}
+
+psc_status psc_tile_cache_set(int32_t M, int32_t N, int32_t K, int32_t ab_dtype, int32_t c_dtype, int32_t tile) {
+  return guard([&] {
+    need(M >= 0 && N >= 0 && K >= 0, PSC_ERR_ARG, "negative size");
+    need(tile >= 0 && tile < psc::gemm_num_tiles(), PSC_ERR_ARG, "tile out of range");
+    need((ab_dtype == PSC_F32 || ab_dtype == PSC_BF16) && (c_dtype == PSC_F32 || c_dtype == PSC_BF16), PSC_ERR_ARG,
+         "bad dtype");
+    psc::tile_cache_set(M, N, K, ab_dtype, c_dtype, tile);
+  });
+}
+
+psc_status psc_tile_cache_get(int32_t M, int32_t N, int32_t K, int32_t ab_dtype, int32_t c_dtype, int32_t *tile) {
+  return guard([&] {
+    need(tile != nullptr, PSC_ERR_ARG, "NULL tile");
+    *tile = psc::tile_cache_get(M, N, K, ab_dtype, c_dtype);
+  });
+}
+
+psc_status psc_tile_cache_clear(int32_t *n_removed) {
+  return guard([&] {
+    if (n_removed) *n_removed = int32_t(psc::tile_cache_size());
+    psc::tile_cache_clear();
+  });
+}
+
+psc_status psc_autotune_gemm(int32_t device, int32_t M, int32_t N, int32_t K, int32_t ab_dtype, int32_t c_dtype,
+                             int32_t iters, int32_t *best_tile, float *best_us, float *us_per_tile, int32_t cap) {
+  return guard([&] {
+    need(M > 0 && N > 0 && K >= 0, PSC_ERR_ARG, "M and N must be positive, K >= 0");
+    need(iters >= 1, PSC_ERR_ARG, "iters must be >= 1");
+    need((ab_dtype == PSC_F32 || ab_dtype == PSC_BF16) && (c_dtype == PSC_F32 || c_dtype == PSC_BF16), PSC_ERR_ARG,
+         "bad dtype");
+    const int t = psc::autotune_gemm(device, M, N, K, ab_dtype, c_dtype, iters, best_us, us_per_tile, cap);
+    if (best_tile) *best_tile = t;
+  });
+}
+
+psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t *n_tuned) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    need(iters >= 1, PSC_ERR_ARG, "iters must be >= 1");
+    const psc::Dag &g = dag->g;
+    std::map<std::tuple<int, int, int, int, int>, int> seen;
+    for (const psc::Kernel &k : g.kers) {
+      if (k.kind != PSC_GEMM || k.tile > 0) continue;
+      const psc::Buffer &a = g.bufs[k.ins[0]], &b = g.bufs[k.ins[1]], &c = g.bufs[k.outs[0]];
+      if (a.rows == 0 || b.cols == 0) continue;
+      seen[{int(a.rows), int(b.cols), int(a.cols), a.dtype, c.dtype}] = 1;
+    }
+    for (const auto &kv : seen) {
+      const auto &[M, N, K, ab, c] = kv.first;
+      psc::autotune_gemm(device, M, N, K, ab, c, iters, nullptr, nullptr, 0);
+    }
+    if (n_tuned) *n_tuned = int32_t(seen.size());
+  });
+}
+
+psc_status psc_autotune_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *candidates, int32_t n,
+                                 int32_t iters, int32_t *best, float *ms_per_run) {
+  return guard([&] {
+    need(dag && candidates && best, PSC_ERR_ARG, "NULL argument");
+    need(n >= 1 && iters >= 1, PSC_ERR_ARG, "need at least one candidate and one iteration");
+    int32_t bi = -1;
+    double bt = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      psc_sched *s = nullptr;
+      double ms = -1;
+      if (psc_schedule(dag, policy, &candidates[i], &s) == PSC_OK) {
+        try {
+          psc::run(*s, nullptr, 0, nullptr);
+          psc::run(*s, nullptr, 0, nullptr);
+          const auto t0 = std::chrono::steady_clock::now();
+          for (int32_t it = 0; it < iters; ++it) psc::run(*s, nullptr, 0, nullptr);
+          ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / iters;
+        } catch (...) {
+          psc_sched_destroy(s);
+          throw;
+        }
+        psc_sched_destroy(s);
+      }
+      if (ms_per_run) ms_per_run[i] = float(ms);
+      if (ms >= 0 && (bi < 0 || ms < bt)) {
+        bi = i;
+        bt = ms;
+      }
+    }
+    need(bi >= 0, PSC_ERR_ARG, "no candidate schedule could be built");
+    *best = bi;
+  });
+}
+
+psc_status psc_sched_kernel_tile(const psc_sched *sched, int32_t kernel, int32_t *tile) {
+  return guard([&] {
+    need(sched && tile, PSC_ERR_ARG, "NULL argument");
+    need(kernel >= 0 && kernel < int32_t(sched->dag->g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
+    need(sched->dag->g.kers[kernel].kind == PSC_GEMM, PSC_ERR_ARG, "not a GEMM kernel");
+    *tile = psc::sched_kernel_tile(*sched, kernel);
   });
 }
 

@@ -101,14 +101,25 @@ struct SchedPlan {
   std::vector<int32_t> kernel_op;  // kernel id -> op id
 };
 
-// Cost model interface used by the EFT mapper and the makespan simulator.
+// Feature vector of one op, the input of every cost model (all float32):
+//   [0..5]  one-hot kind: GEMM, transpose, softmax, add, H2D, D2H
+//   [6]     log2 M  (output rows; the copied buffer's rows for a copy)
+//   [7]     log2 N  (output columns)
+//   [8]     log2 K  (GEMM inner dimension; 0 otherwise)
+//   [9]     log2 of the algorithmic bytes (every input and the output once)
+//   [10]    1 if the first operand (or the copied buffer) is BF16, else 0
+//   [11]    other streams with an op in flight when this op starts
+constexpr int kFeatures = 12;
+void kernel_features(const Dag &g, int32_t kernel, int32_t in_flight, float *f);
+void copy_features(const Dag &g, int32_t buffer, bool h2d, int32_t in_flight, float *f);
+
+// Cost model interface used by the EFT mapper: predicted microseconds of each feature row.
 struct CostModel {
   virtual ~CostModel() = default;
-  // Predicted duration (microseconds) of each kernel when `in_flight` kernels share the GPU.
-  virtual std::vector<double> kernel_us(const Dag &g, const std::vector<int32_t> &in_flight) = 0;
-  virtual double copy_us(const Dag &g, int32_t buffer, bool h2d) = 0;
+  virtual void predict_us(const float *feat, int64_t n, double *us) = 0;
 };
 std::unique_ptr<CostModel> make_heuristic_cost();
+std::unique_ptr<CostModel> mlp_cost_model(const psc_mlp *m);  // mlp.hip
 
 SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o);
 

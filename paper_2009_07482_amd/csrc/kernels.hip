@@ -1,9 +1,42 @@
 // Standalone gfx950 kernels of the DAG (one tile function call per block; the tile functions live
 // in tiles.hpp) and the launch factories that pick a kernel instance for a problem and fill a
 // Launch record that the runtime passes to hipLaunchKernel.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "tiles.hpp"
 
 namespace psc {
+
+// Tile choices measured by the autotuner, keyed by (M, N, K, operand dtype, output dtype); the
+// automatic choice of make_gemm consults it first.
+namespace {
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_tile_cache;
+}  // namespace
+
+void tile_cache_set(int M, int N, int K, int ab, int c, int tile) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  if (tile <= 0) g_tile_cache.erase({M, N, K, ab, c});
+  else g_tile_cache[{M, N, K, ab, c}] = tile;
+}
+
+int tile_cache_get(int M, int N, int K, int ab, int c) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tile_cache.find({M, N, K, ab, c});
+  return it == g_tile_cache.end() ? 0 : it->second;
+}
+
+void tile_cache_clear() {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_cache.clear();
+}
+
+size_t tile_cache_size() {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  return g_tile_cache.size();
+}
 
 // ---------------------------------------------------------------------------------------------
 // Standalone kernels: one tile function call per 256-thread block.
@@ -136,6 +169,7 @@ int gemm_auto_tile(int M, int N, int K, int dtype) {
 }
 
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
+  if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
   const int bm = kTiles[tile].bm, bn = kTiles[tile].bn;
   a.tiles_n = (a.N + bn - 1) / bn;

@@ -56,6 +56,10 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype);
 bool make_transpose(Launch &L, TransArgs a, int dtype);
 bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype);
 int gemm_num_tiles();
+void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
+int tile_cache_get(int M, int N, int K, int ab, int c);
+void tile_cache_clear();
+size_t tile_cache_size();
 int gemm_auto_tile(int M, int N, int K, int dtype);
 
 }  // namespace psc

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -50,6 +51,7 @@ struct Device {
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> graph_key;
   std::vector<psc_op_time> times;
+  std::vector<char> active;        // per op in the recorded run: it did work
   bool have_times = false;
   std::unique_ptr<Dispatcher> disp;
   // PSC_DEVICE executor
@@ -463,10 +465,12 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     PSC_HIP(hipMemcpy(tl.data(), d.ea.t_last, 8 * nk, hipMemcpyDeviceToHost));
     PSC_HIP(hipMemcpy(&t0, d.ea.t_start, 8, hipMemcpyDeviceToHost));
     d.times.assign(s.plan.ops.size(), psc_op_time{0, 0, 0.f, 0.f});
+    d.active.assign(s.plan.ops.size(), 0);
     for (size_t o = 0; o < s.plan.ops.size(); ++o) {
       const Op &op = s.plan.ops[o];
       d.times[o].op = int32_t(o);
       d.times[o].stream = op.stream;
+      d.active[o] = op.type == PSC_OP_KERNEL && !d.launch[op.kernel].empty;
       if (op.type == PSC_OP_KERNEL) {
         d.times[o].start_us = float(double(int64_t(tf[op.kernel] - t0)) / d.clock_mhz);
         d.times[o].end_us = float(double(int64_t(tl[op.kernel] - t0)) / d.clock_mhz);
@@ -475,11 +479,14 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     d.have_times = true;
   } else if (timed) {
     d.times.resize(s.plan.ops.size());
+    d.active.assign(s.plan.ops.size(), 0);
     for (size_t o = 0; o < s.plan.ops.size(); ++o) {
       float a = 0, b = 0;
       PSC_HIP(hipEventElapsedTime(&a, d.start, d.t0[o]));
       PSC_HIP(hipEventElapsedTime(&b, d.start, d.t1[o]));
       d.times[o] = psc_op_time{int32_t(o), s.plan.ops[o].stream, a * 1000.f, b * 1000.f};
+      const Op &op = s.plan.ops[o];
+      d.active[o] = op.type == PSC_OP_KERNEL ? !d.launch[op.kernel].empty : cd[o].active;
     }
     d.have_times = true;
   }
@@ -509,6 +516,49 @@ void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n) {
   }
 }
 
+// Cost-model samples of the recorded run.  Ops on one stream run one after another, so for each
+// other stream a binary search over its ops' start times finds the op (if any) whose interval
+// contains this op's start.
+void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_t *n) {
+  if (!s.dev || !s.dev->have_times) fail(PSC_ERR_STATE, "no recorded run (set record_ops and call psc_run)");
+  const Device &d = *s.dev;
+  const Dag &g = s.dag->g;
+  const auto &t = d.times;
+  const int32_t S = s.plan.total_streams;
+  std::vector<std::vector<int32_t>> on(S);  // active ops per stream by start time
+  for (size_t o = 0; o < t.size(); ++o)
+    if (d.active[o] && t[o].end_us > t[o].start_us) on[s.plan.ops[o].stream].push_back(int32_t(o));
+  for (auto &v : on)
+    std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return t[a].start_us < t[b].start_us; });
+  int32_t cnt = 0;
+  for (size_t o = 0; o < t.size(); ++o) cnt += d.active[o] && t[o].end_us > t[o].start_us;
+  *n = cnt;
+  if (!feat && !log_us) return;
+  if (cap < cnt) fail(PSC_ERR_ARG, "capacity too small");
+  int32_t i = 0;
+  for (size_t o = 0; o < t.size(); ++o) {
+    if (!(d.active[o] && t[o].end_us > t[o].start_us)) continue;
+    const Op &op = s.plan.ops[o];
+    const float st = t[o].start_us;
+    int32_t busy = 0;
+    for (int32_t q = 0; q < S; ++q) {
+      if (q == op.stream || on[q].empty()) continue;
+      // last op on q starting at or before st
+      auto it = std::upper_bound(on[q].begin(), on[q].end(), st,
+                                 [&](float v, int32_t b) { return v < t[b].start_us; });
+      if (it == on[q].begin()) continue;
+      busy += t[*(it - 1)].end_us > st;
+    }
+    if (feat) {
+      float *f = feat + size_t(i) * kFeatures;
+      if (op.type == PSC_OP_KERNEL) kernel_features(g, op.kernel, busy, f);
+      else copy_features(g, op.buffer, op.type == PSC_OP_H2D, busy, f);
+    }
+    if (log_us) log_us[i] = float(std::log(double(t[o].end_us) - double(t[o].start_us)));
+    ++i;
+  }
+}
+
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) {
   if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
   const Dag &g = s.dag->g;
@@ -516,6 +566,69 @@ void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) 
   if (it == g.buf_by_name.end()) fail(PSC_ERR_NAME, std::string("unknown buffer '") + name + "'");
   if (dptr) *dptr = buffer_ptr(g, *s.dev, it->second);
   if (ld) *ld = buffer_ld(g, it->second);
+}
+
+// Autotuner: times every GEMM tile configuration on device buffers of the given shape (zeros)
+// with back-to-back launches between HIP events, records the fastest in the tile cache and
+// returns it.  us_per_tile[t] (t < cap) receives each configuration's mean time (0 for t = 0).
+int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, float *best_us, float *us_per_tile,
+                  int cap) {
+  PSC_HIP(hipSetDevice(device));
+  const size_t ea = ab == PSC_BF16 ? 2 : 4, ec = c == PSC_BF16 ? 2 : 4;
+  void *A = nullptr, *B = nullptr, *C = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = 0;
+  float best_t = 0;
+  auto cleanup = [&] {
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    if (C) (void)hipFree(C);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  try {
+    PSC_HIP(hipMalloc(&A, std::max<size_t>(16, size_t(M) * K * ea)));
+    PSC_HIP(hipMalloc(&B, std::max<size_t>(16, size_t(K) * N * ea)));
+    PSC_HIP(hipMalloc(&C, std::max<size_t>(16, size_t(M) * N * ec)));
+    PSC_HIP(hipMemset(A, 0, std::max<size_t>(16, size_t(M) * K * ea)));
+    PSC_HIP(hipMemset(B, 0, std::max<size_t>(16, size_t(K) * N * ea)));
+    PSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    PSC_HIP(hipEventCreate(&e0));
+    PSC_HIP(hipEventCreate(&e1));
+    for (int t = 1; t < gemm_num_tiles(); ++t) {
+      GemmArgs g{};
+      g.A = A; g.B = B; g.C = C;
+      g.lda = K; g.ldb = N; g.ldc = N;
+      g.M = M; g.N = N; g.K = K; g.alpha = 1.0f;
+      Launch L;
+      if (!make_gemm(L, g, ab, c, t)) continue;
+      for (int w = 0; w < 3; ++w) launch(L, st);
+      PSC_HIP(hipEventRecord(e0, st));
+      for (int i = 0; i < iters; ++i) launch(L, st);
+      PSC_HIP(hipEventRecord(e1, st));
+      PSC_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      PSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const float us = ms * 1000.f / float(std::max(1, iters));
+      if (us_per_tile && t < cap) us_per_tile[t] = us;
+      if (best == 0 || us < best_t) { best = t; best_t = us; }
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+  if (us_per_tile && cap > 0) us_per_tile[0] = 0.f;
+  if (best) tile_cache_set(M, N, K, ab, c, best);
+  if (best_us) *best_us = best_t;
+  return best;
+}
+
+int sched_kernel_tile(const psc_sched &s, int32_t kernel) {
+  if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
+  return s.dev->launch[kernel].tile;
 }
 
 void *host_alloc(size_t bytes) {

@@ -19,59 +19,63 @@ namespace {
 
 constexpr double kCUs = 256.0;
 
+float lg2(double v) { return v > 1.0 ? float(std::log2(v)) : 0.0f; }
+
 struct HeuristicCost final : CostModel {
-  // Roofline-style estimate: a kernel occupies min(1, workgroups / CUs) of the chip and runs at
-  // that share of the matrix-core or HBM peak, plus a fixed dispatch latency.
-  std::vector<double> kernel_us(const Dag &g, const std::vector<int32_t> &in_flight) override {
-    std::vector<double> out(g.kers.size());
-    for (size_t k = 0; k < g.kers.size(); ++k) {
-      const Kernel &ker = g.kers[k];
-      const Buffer &o = g.bufs[ker.outs[0]];
+  // Roofline-style estimate from the features alone: a kernel occupies min(1, workgroups / CUs)
+  // of the chip and runs at that share of the matrix-core or HBM peak, plus a fixed dispatch
+  // latency; a copy runs at a host-link rate.  Each other stream in flight adds 15%.
+  void predict_us(const float *feat, int64_t n, double *us) override {
+    for (int64_t r = 0; r < n; ++r) {
+      const float *f = feat + r * kFeatures;
+      const double M = std::exp2(double(f[6])), N = std::exp2(double(f[7])), K = std::exp2(double(f[8]));
+      const double bytes = std::exp2(double(f[9]));
+      const bool bf16 = f[10] > 0.5f;
       double t;
-      if (ker.kind == PSC_GEMM) {
-        const Buffer &a = g.bufs[ker.ins[0]], &b = g.bufs[ker.ins[1]];
-        const double M = a.rows, K = a.cols, N = b.cols;
+      if (f[4] > 0.5f || f[5] > 0.5f) {
+        t = 4.0 + bytes / 50.0e9 * 1e6;
+      } else if (f[0] > 0.5f) {
         const double flops = 2.0 * M * N * K;
-        const double peak = a.dtype == PSC_BF16 ? 1.2e15 : 9.0e13;
+        const double peak = bf16 ? 1.2e15 : 9.0e13;
         const double tiles = std::ceil(M / 64.0) * std::ceil(N / 64.0);
         const double share = std::min(1.0, tiles / kCUs);
-        const double bytes = (M * K + K * N) * elem_size(a.dtype) + M * N * elem_size(o.dtype);
-        t = std::max(flops / (peak * share), bytes / 4.0e12) * 1e6;
+        t = 3.0 + std::max(flops / (peak * share), bytes / 4.0e12) * 1e6;
       } else {
-        double bytes = 0;
-        for (int32_t b : ker.ins) bytes += double(g.bufs[b].rows) * g.bufs[b].cols * elem_size(g.bufs[b].dtype);
-        bytes += double(o.rows) * o.cols * elem_size(o.dtype);
-        const double blocks = std::ceil(double(o.rows) * o.cols / 4096.0);
-        t = bytes / (4.0e12 * std::min(1.0, blocks / kCUs)) * 1e6;
+        const double blocks = std::ceil(M * N / 4096.0);
+        t = 3.0 + bytes / (4.0e12 * std::min(1.0, blocks / kCUs)) * 1e6;
       }
-      const double flight = k < in_flight.size() ? std::max(1, in_flight[k]) : 1;
-      out[k] = 3.0 + t * (flight > 1 ? 1.0 + 0.15 * (flight - 1) : 1.0);
+      us[r] = t * (1.0 + 0.15 * std::max(0.0f, f[11]));
     }
-    return out;
-  }
-  double copy_us(const Dag &g, int32_t buffer, bool) override {
-    const Buffer &b = g.bufs[buffer];
-    return 4.0 + double(b.rows) * b.cols * elem_size(b.dtype) / 50.0e9 * 1e6;
   }
 };
 
 // EFT list scheduling: kernels by descending bottom-level rank (ties: lower id), each placed on
-// the stream where it is predicted to finish first.
+// the stream where it is predicted to finish first.  A kernel's duration on a candidate stream is
+// the prediction for the number of other streams still busy at its start, so all predictions are
+// made up front: one batch of feature rows, kernels x (0 .. S-1 streams in flight) plus the
+// uploads of the isolated inputs.
 void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &order,
              std::vector<int32_t> &stream_of) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
-  std::vector<int32_t> flight(nk, std::min<int32_t>(S, 4));
-  const std::vector<double> w = cost.kernel_us(g, flight);
-  std::vector<double> copy_in(nk, 0.0);
+  const int32_t nb = static_cast<int32_t>(g.bufs.size());
+  std::vector<float> feat(size_t(nk * S + nb) * kFeatures, 0.0f);
   for (int32_t k = 0; k < nk; ++k)
-    for (int32_t b : g.iso_in[k]) copy_in[k] += cost.copy_us(g, b, true);
-  // bottom-level rank over a reverse topological order
+    for (int32_t j = 0; j < S; ++j) kernel_features(g, k, j, &feat[size_t(k * S + j) * kFeatures]);
+  std::vector<char> is_h2d(nb, 0);
+  for (int32_t b : g.h2d_bufs) is_h2d[b] = 1;
+  for (int32_t b = 0; b < nb; ++b)
+    if (is_h2d[b]) copy_features(g, b, true, 0, &feat[size_t(nk * S + b) * kFeatures]);
+  std::vector<double> pred(size_t(nk * S + nb), 0.0);
+  cost.predict_us(feat.data(), int64_t(pred.size()), pred.data());
+  auto w = [&](int32_t k, int32_t j) { return pred[size_t(k * S + std::min(j, S - 1))]; };
+  auto up_us = [&](int32_t b) { return pred[size_t(nk * S + b)]; };
+  // bottom-level rank over a reverse topological order, with the uncontended durations
   std::vector<int32_t> topo = g.bfs_order();
   std::vector<double> bl(nk, 0.0);
   for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
     double m = 0;
     for (int32_t s : g.succ[*it]) m = std::max(m, bl[s]);
-    bl[*it] = w[*it] + m;
+    bl[*it] = w(*it, 0) + m;
   }
   using Item = std::pair<double, int32_t>;  // (-rank, id)
   std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
@@ -81,7 +85,7 @@ void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &ord
     if (!indeg[k]) ready.push({-bl[k], k});
   }
   std::vector<double> avail(S, 0.0), finish(nk, 0.0);
-  std::vector<char> uploaded(g.bufs.size(), 0);
+  std::vector<char> uploaded(nb, 0);
   order.clear();
   while (!ready.empty()) {
     const int32_t k = ready.top().second;
@@ -90,11 +94,14 @@ void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &ord
     for (int32_t p : g.pred[k]) dep_ready = std::max(dep_ready, finish[p]);
     double up = 0;
     for (int32_t b : g.iso_in[k])
-      if (!uploaded[b]) up += cost.copy_us(g, b, true);
+      if (!uploaded[b]) up += up_us(b);
     int32_t best = 0;
     double best_f = 1e300;
     for (int32_t s = 0; s < S; ++s) {
-      const double f = std::max(avail[s] + up, dep_ready) + w[k];
+      const double st = std::max(avail[s] + up, dep_ready);
+      int32_t busy = 0;
+      for (int32_t q = 0; q < S; ++q) busy += q != s && avail[q] > st;
+      const double f = st + w(k, busy);
       if (f < best_f - 1e-9) { best_f = f; best = s; }
     }
     for (int32_t b : g.iso_in[k]) uploaded[b] = 1;
@@ -110,7 +117,33 @@ void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &ord
 
 std::unique_ptr<CostModel> make_heuristic_cost() { return std::make_unique<HeuristicCost>(); }
 
-CostModel *mlp_cost_model(const psc_mlp *m);  // mlp.cpp
+void kernel_features(const Dag &g, int32_t kernel, int32_t in_flight, float *f) {
+  const Kernel &ker = g.kers[kernel];
+  const Buffer &o = g.bufs[ker.outs[0]];
+  const Buffer &a = g.bufs[ker.ins[0]];
+  for (int i = 0; i < kFeatures; ++i) f[i] = 0.0f;
+  const int kind = ker.kind == PSC_GEMM ? 0 : ker.kind == PSC_TRANSPOSE ? 1 : ker.kind == PSC_SOFTMAX ? 2 : 3;
+  f[kind] = 1.0f;
+  f[6] = lg2(double(o.rows));
+  f[7] = lg2(double(o.cols));
+  f[8] = ker.kind == PSC_GEMM ? lg2(double(a.cols)) : 0.0f;
+  double bytes = double(o.rows) * o.cols * elem_size(o.dtype);
+  for (int32_t b : ker.ins) bytes += double(g.bufs[b].rows) * g.bufs[b].cols * elem_size(g.bufs[b].dtype);
+  f[9] = lg2(bytes);
+  f[10] = a.dtype == PSC_BF16 ? 1.0f : 0.0f;
+  f[11] = float(in_flight);
+}
+
+void copy_features(const Dag &g, int32_t buffer, bool h2d, int32_t in_flight, float *f) {
+  const Buffer &b = g.bufs[buffer];
+  for (int i = 0; i < kFeatures; ++i) f[i] = 0.0f;
+  f[h2d ? 4 : 5] = 1.0f;
+  f[6] = lg2(double(b.rows));
+  f[7] = lg2(double(b.cols));
+  f[9] = lg2(double(b.rows) * b.cols * elem_size(b.dtype));
+  f[10] = b.dtype == PSC_BF16 ? 1.0f : 0.0f;
+  f[11] = float(in_flight);
+}
 
 namespace {
 
@@ -177,12 +210,8 @@ SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
     order = g.bfs_order();
     for (int32_t k = 0; k < nk; ++k) stream_of[k] = g.kers[k].component % S;
   } else if (o.mapper == PSC_MAP_EFT) {
-    if (o.cost) {
-      map_eft(g, S, *mlp_cost_model(o.cost), order, stream_of);
-    } else {
-      auto h = make_heuristic_cost();
-      map_eft(g, S, *h, order, stream_of);
-    }
+    auto cost = o.cost ? mlp_cost_model(o.cost) : make_heuristic_cost();
+    map_eft(g, S, *cost, order, stream_of);
   } else {
     fail(PSC_ERR_ARG, "unknown mapper");
   }

@@ -249,3 +249,68 @@ def test_classify_default_component_is_whole_dag():
     assert front == {f"L0H{h}_{x}" for h in range(2) for x in "qkv"}
     assert end == {"L0_y"}
     assert not any(inter)
+
+
+def test_tile_cache_roundtrip():
+    n = psc.psc_gemm_tile_count()
+    assert n == 13
+    psc.psc_tile_cache_clear()
+    assert psc.psc_tile_cache_get(512, 64, 512, "f32", "f32") == 0
+    psc.psc_tile_cache_set(512, 64, 512, "f32", "f32", 9)
+    psc.psc_tile_cache_set(512, 64, 512, "bf16", "f32", 12)
+    assert psc.psc_tile_cache_get(512, 64, 512, "f32", "f32") == 9
+    assert psc.psc_tile_cache_get(512, 64, 512, "bf16", "f32") == 12
+    psc.psc_tile_cache_set(512, 64, 512, "f32", "f32", 0)
+    assert psc.psc_tile_cache_get(512, 64, 512, "f32", "f32") == 0
+    assert psc.psc_tile_cache_clear() == 1
+    with pytest.raises(psc.PscError):
+        psc.psc_tile_cache_set(1, 1, 1, "f32", "f32", n)
+
+
+def test_kernel_features_and_heuristic_cost():
+    """Feature rows of the cost model and the roofline heuristic's closed form on them."""
+    import math
+    import numpy as np
+    spec = workloads.mha_spec(512, 512, 8)
+    dag = psc.build_dag(spec)
+    with pytest.raises(psc.PscError) as e:
+        psc.psc_kernel_features(dag, 0)
+    assert e.value.name == "PSC_ERR_STATE"
+    s = psc.psc_schedule(dag, "fine", n_streams=4, mapper="eft")
+    names = [k["name"] for k in spec["kernels"]]
+    q = psc.psc_kernel_features(dag, names.index("L0H0_q"), 2)
+    assert q[:6].tolist() == [1, 0, 0, 0, 0, 0]
+    assert q[6:9].tolist() == [9, 6, 9] and q[10] == 0 and q[11] == 2
+    assert q[9] == pytest.approx(math.log2(4 * (512 * 512 + 512 * 64 + 512 * 64)))
+    kt = psc.psc_kernel_features(dag, names.index("L0H0_kt"), 0)
+    assert kt[:6].tolist() == [0, 1, 0, 0, 0, 0] and kt[6:9].tolist() == [6, 9, 0]
+    p = psc.psc_kernel_features(dag, names.index("L0H0_p"), 0)
+    assert p[:6].tolist() == [0, 0, 1, 0, 0, 0] and p[9] == pytest.approx(math.log2(2 * 4 * 512 * 512))
+    # heuristic: 3 us + 2MNK / (90 TF/s * share of 256 CUs) for this GEMM, +15% per busy stream
+    share = min(1.0, (512 / 64) * (64 / 64) / 256)
+    t0 = 3.0 + max(2 * 512 * 64 * 512 / (9e13 * share), 2 ** q[9] / 4e12) * 1e6
+    us = psc.psc_cost_predict(np.stack([q, q * np.r_[np.ones(11), 0]]))
+    assert us[0] == pytest.approx(t0 * 1.3, rel=1e-5) and us[1] == pytest.approx(t0, rel=1e-5)
+    cp = np.zeros(12, np.float32)
+    cp[4], cp[6], cp[7], cp[9] = 1, 9, 9, math.log2(512 * 512 * 4)
+    assert psc.psc_cost_predict(cp[None])[0] == pytest.approx(4.0 + 512 * 512 * 4 / 50e9 * 1e6, rel=1e-5)
+    with pytest.raises(psc.PscError):
+        psc.psc_sched_samples(s)          # no recorded run
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(dag)
+
+
+def test_eft_spreads_work_over_every_stream():
+    spec = workloads.mha_spec(512, 512, 4)
+    dag = psc.build_dag(spec)
+    s = psc.psc_schedule(dag, "fine", n_streams=4, mapper="eft")
+    exp = psc.export_schedule(spec, s)
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(dag)
+    names = [k["name"] for k in spec["kernels"]]
+    stream_of = {names[o["kernel"]]: o["stream"] for o in exp["ops"] if o["type"] == "kernel"}
+    assert set(stream_of.values()) == {0, 1, 2, 3}
+    # the four heads' first projections start in parallel, one per stream
+    assert len({stream_of[f"L0H{h}_k"] for h in range(4)}) == 4
+    ok, errs, _ = validator.check_schedule(spec, exp)
+    assert ok, errs

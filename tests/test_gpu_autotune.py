@@ -1,0 +1,61 @@
+"""GPU tests of the GEMM tile autotuner: measured choice, cache use by prepared schedules, parity."""
+import numpy as np
+import pytest
+
+import workloads
+import paper_2009_07482_amd as psc
+from gpu_helpers import normwise, oracle_outputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def clean_cache():
+    psc.psc_tile_cache_clear()
+    yield
+    psc.psc_tile_cache_clear()
+
+
+@pytest.mark.parametrize("m,n,k,ab", [(512, 64, 512, "f32"), (1024, 1024, 64, "bf16"), (137, 250, 91, "bf16")])
+def test_autotune_gemm_picks_the_fastest_measured(m, n, k, ab):
+    best, us, table = psc.psc_autotune_gemm(m, n, k, ab, "f32", iters=20)
+    assert 1 <= best < psc.psc_gemm_tile_count()
+    assert us > 0 and all(v > 0 for v in table.values())
+    assert us == pytest.approx(min(table.values()))
+    assert psc.psc_tile_cache_get(m, n, k, ab, "f32") == best
+
+
+def test_tuned_dag_uses_cached_tiles_and_keeps_parity():
+    spec = workloads.mha_spec(512, 512, 8)
+    inp = workloads.mha_inputs(1, 512, 512)
+    dag = psc.build_dag(spec)
+    n = psc.psc_autotune_dag(dag, iters=10)
+    assert n == 3          # 512x64x512, 512x512x64, 512x512x512
+    s = psc.psc_schedule(dag, "fine", n_streams=4, mapper="component")
+    psc.psc_sched_prepare(s)
+    by = {b["name"]: b for b in spec["buffers"]}
+    for ki, k in enumerate(spec["kernels"]):
+        if k["kind"] == "gemm":
+            a, b = by[k["inputs"][0]], by[k["inputs"][1]]
+            want = psc.psc_tile_cache_get(a["rows"], b["cols"], a["cols"], "f32", "f32")
+            assert psc.psc_sched_kernel_tile(s, ki) == want
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(dag)
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=4, mapper="component")
+    assert normwise(out["Y0"], oracle_outputs(spec, inp)["Y0"]) < 1e-4
+
+
+def test_autotune_schedule_returns_the_fastest_candidate_and_keeps_parity():
+    spec = workloads.mha_spec(512, 512, 8)
+    inp = workloads.mha_inputs(1, 512, 512)
+    dag = psc.build_dag(spec)
+    cands = [dict(n_streams=1, mapper="rr", host_threads=1),
+             dict(n_streams=4, mapper="component", host_threads=0),
+             dict(n_streams=4, mapper="rr", host_threads=1)]
+    best, ms = psc.psc_autotune_schedule(dag, "fine", cands, iters=10)
+    psc.psc_dag_destroy(dag)
+    assert 0 <= best < len(cands)
+    assert all(m > 0 for m in ms)
+    assert ms[best] == pytest.approx(min(ms))
+    out, _ = psc.run_spec(spec, inp, "fine", **cands[best])
+    assert normwise(out["Y0"], oracle_outputs(spec, inp)["Y0"]) < 1e-4

@@ -206,3 +206,23 @@ def test_device_executor_node_times_respect_dependencies():
     t = {o["kernel"]: (tt[2], tt[3]) for tt, o in zip(times, exp["ops"]) if o["type"] == "kernel"}
     for (s_, _, d_, _) in spec["edges"]:
         assert t[s_][1] <= t[d_][0] + 1e-3, (s_, d_, t[s_], t[d_])
+
+
+@pytest.mark.timeout(900)
+def test_mha_12_layers_bf16_full_size():
+    # 12 stacked layers, 16 heads, d_model = n = 1024, BF16 GEMM operands with FP32 accumulation,
+    # FP32 softmax; fine schedule with a copy stream overlapping the weight uploads.  Every
+    # layer's output is compared with the exact FP64 oracle (normwise relative error < 2e-2).
+    n, d, h, L = 1024, 1024, 16, 12
+    spec = workloads.mha_spec(n, d, h, L, gemm_dtype="bf16")
+    inp = workloads.mha_inputs(0, n, d, L)
+    r = psc.SpecRunner(spec, "fine", n_streams=4, mapper="component", copy_stream=True)
+    r.set_inputs(inp)
+    st = r.run()
+    got = r.result(f"Y{L - 1}")
+    r.close()
+    print(f"makespan with copies {st['makespan_ms']:.3f} ms", flush=True)
+    ref = dag_outputs = odag.run_dag(spec, inp)
+    err = normwise(got, odag.read_buffer(spec, ref, f"Y{L - 1}"))
+    print(f"Y{L - 1}: normwise relative error vs FP64 oracle {err:.3e}", flush=True)
+    assert err < 2e-2
