@@ -12,7 +12,10 @@ of Sec. V (each head's kernels one task component, components on 4 HIP streams, 
 enqueued by its own host thread).  GEMM tiles are chosen by the autotuner first (--no-tune: size
 heuristic).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha512|mha1024x12|forkjoin]
+--config batch64: 64 instances of log-uniform length, 6 layers, BF16 (21,888 kernels), inferences/s
+and per-instance latency p50/p99, eager streams vs one hipGraph, untuned vs autotuned.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha512|mha1024x12|batch64|forkjoin]
 """
 import argparse
 import json
@@ -42,11 +45,11 @@ def parse():
     p.add_argument("--variants", action="store_true", help="also time other fine-grained variants")
     p.add_argument("--kernel-iters", type=int, default=200)
     a = p.parse_args()
-    big = a.config == "mha1024x12"
+    big = a.config in ("mha1024x12", "batch64")
     if a.steps is None:
-        a.steps = 20 if big else 300
+        a.steps = {"mha1024x12": 20, "batch64": 5}.get(a.config, 300)
     if a.warmup is None:
-        a.warmup = 3 if big else 30
+        a.warmup = 2 if a.config == "batch64" else (3 if big else 30)
     return a
 
 
@@ -136,6 +139,149 @@ def overlap(times):
     return sum(e - s for s, e in ivals) / busy if busy > 0 else 0.0
 
 
+def dominant_roofline(spec, r, kernel_iters):
+    """Dominant kernel: per kernel class, the mean duration of back-to-back launches on the
+    class's own stream (HIP events around the launches, on that stream) times its launches per
+    step; the class with the largest product dominates the step."""
+    import paper_2009_07482_amd as psc
+    kers = {}
+    for k in range(len(spec["kernels"])):
+        key, work, bound, dt = kernel_class(spec, k)
+        kers.setdefault(key, {"work": work, "bound": bound, "dtype": dt, "ids": []})["ids"].append(k)
+    for key, c in kers.items():
+        psc.psc_kernel_time(r.sched, c["ids"][0], 10)
+        c["avg_us"] = psc.psc_kernel_time(r.sched, c["ids"][0], kernel_iters)
+        c["total_us"] = c["avg_us"] * len(c["ids"])
+        if c["bound"] == "mfma":
+            c["tile"] = psc.psc_sched_kernel_tile(r.sched, c["ids"][0])
+    print("# kernel classes (isolated mean us per launch x launches per step), top 12:", file=sys.stderr)
+    for key, c in sorted(kers.items(), key=lambda kv: -kv[1]["total_us"])[:12]:
+        print(f"#   {key}: {c['avg_us']:.2f} us x {len(c['ids'])}" + (f" (tile {c['tile']})" if "tile" in c else ""),
+              file=sys.stderr)
+    dom_key = max(kers, key=lambda k: kers[k]["total_us"])
+    dom = kers[dom_key]
+    avg_us = dom["avg_us"]
+    achieved = dom["work"] / (avg_us * 1e-6)
+    if dom["bound"] == "mfma":
+        peak = PEAK["mfma_bf16"] if dom["dtype"] == "bf16" else PEAK["mfma_f32"]
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None}
+    roof.update({"kernel": dom_key, "avg_us": avg_us, "launches_per_step": len(dom["ids"]),
+                 "work_per_launch": dom["work"],
+                 "timing": f"{kernel_iters} back-to-back launches, HIP events on its stream"})
+    return roof
+
+
+def batch_main(a):
+    """64 attention instances of log-uniform length in [64, 2048] (d = 512, 8 heads, 6 layers,
+    BF16 GEMMs), one task component each, in one DAG of 21,888 kernels.  A step is one batch.
+    Reports inferences/s = 64 / batch time and per-instance completion latency (device-clock
+    marks after each instance's last kernel), untuned vs autotuned, eager vs one hipGraph."""
+    import paper_2009_07482_amd as psc
+    import workloads
+    lengths = workloads.batch_lengths(0)
+    d, h, L = 512, 8, 6
+    spec = workloads.batch_spec(lengths, d, h, L, gemm_dtype="bf16")
+    inp = workloads.batch_inputs(0, lengths, d, L)
+    print(f"# batch: {len(lengths)} instances, n in [{min(lengths)}, {max(lengths)}], "
+          f"{len(spec['kernels'])} kernels", file=sys.stderr, flush=True)
+    res, keep = {}, {}
+
+    def measure(name, policy, keep_runner=False, **kw):
+        t0 = time.perf_counter()
+        r = psc.SpecRunner(spec, policy, mark_components=(policy != "device"), **kw)
+        r.set_inputs(inp)
+        st_io = r.run()
+        setup = time.perf_counter() - t0
+        wall, mk, st = timed(r, a.steps, a.warmup)
+        done = psc.psc_sched_component_times(r.sched) / 1000.0
+        res[name] = {"ms_per_batch": wall / a.steps * 1e3, "makespan_ms_median": float(np.median(mk)),
+                     "latency_ms_p50": float(np.percentile(done, 50)),
+                     "latency_ms_p99": float(np.percentile(done, 99)),
+                     "makespan_with_copies_ms": st_io["makespan_ms"], "host_enqueue_ms": st["host_enqueue_ms"],
+                     "first_run_s": setup, "opts": {"policy": policy, **kw}}
+        print(f"# {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
+        if keep_runner:
+            keep[name] = r
+        else:
+            r.close()
+
+    measure("coarse_default", "coarse")
+    measure("fine_default", "fine", n_streams=4, mapper="component")
+    measure("graph_default", "fine", n_streams=4, mapper="component", use_graph=True)
+    tuned = 0
+    if not a.no_tune:
+        d0 = psc.build_dag(spec)
+        t0 = time.perf_counter()
+        tuned = psc.psc_autotune_dag(d0, iters=10)
+        psc.psc_dag_destroy(d0)
+        print(f"# tile autotuner: {tuned} GEMM shapes in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    cands = [dict(n_streams=s_, mapper="component", use_graph=g_) for s_ in (4, 8, 16) for g_ in (False, True)]
+    d1 = psc.build_dag(spec)
+    bi, cms = psc.psc_autotune_schedule(d1, "fine", cands, iters=3)
+    psc.psc_dag_destroy(d1)
+    best = cands[bi]
+    print("# schedule autotuner: " + ", ".join(
+        f"{c['n_streams']}{'g' if c['use_graph'] else 'e'}={m:.2f}" for c, m in zip(cands, cms)) + f" -> {best}",
+        file=sys.stderr, flush=True)
+    measure("coarse", "coarse")
+    measure("tuned", "fine", keep_runner=True, **best)
+    other = dict(best, use_graph=not best["use_graph"])
+    measure("tuned_" + ("eager" if best["use_graph"] else "graph"), "fine", **other)
+    roof = dominant_roofline(spec, keep["tuned"], a.kernel_iters)
+    keep["tuned"].close()
+    t = res["tuned"]
+    line = {
+        "metric": "batched inference: inferences/s and per-instance latency p50/p99",
+        "value": len(lengths) / (t["ms_per_batch"] / 1e3), "unit": "inferences/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": t["ms_per_batch"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded N(0,1) inputs, N(0,1/d) weights, log-uniform lengths)",
+        "config": {"workload": f"batch of {len(lengths)} attention instances, n log-uniform in [64, 2048], "
+                               f"d_model={d}, {h} heads, {L} layers, GEMM BF16 (FP32 accumulation)",
+                   "kernels": len(spec["kernels"]), "schedule": best, "inputs": "device-resident",
+                   "gemm_tiles": "autotuned" if tuned else "size heuristic"},
+        "latency_ms": {"p50": t["latency_ms_p50"], "p99": t["latency_ms_p99"]},
+        "by_schedule": res,
+        "roofline": roof,
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = batch_cpu_baseline(lengths, d, h, L, inp, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def batch_cpu_baseline(lengths, d, h, L, inp, seconds):
+    """The oracle on instances taken shortest first until the time is used, scaled to the whole
+    batch by floating-point work (the oracle's time is dominated by its matrix products)."""
+    import workloads
+    from oracle import dag as odag
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    order = sorted(range(len(lengths)), key=lambda i: lengths[i])
+    total = sum(workloads.spec_flops(workloads.mha_spec(n, d, h, L, "bf16")) for n in lengths)
+    done, el, t0 = 0.0, 0.0, time.perf_counter()
+    count = 0
+    for i in order[::max(1, len(order) // 16)]:
+        sub = workloads.mha_spec(lengths[i], d, h, L, "bf16", prefix=f"i{i}_", weight_prefix="")
+        odag.run_dag(sub, {k: inp[k] for k in workloads.host_inputs_of(sub)})
+        done += workloads.spec_flops(sub)
+        count += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    batch_s = el * total / done
+    return {"value": len(lengths) / batch_s, "unit": "inferences/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{count} instance(s) spread over the length range in FP64 (numpy), {el:.1f} s, "
+                      f"scaled to the batch by FLOPs"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -143,6 +289,9 @@ def main():
         sys.exit(2)
     import paper_2009_07482_amd as psc
 
+    if a.config == "batch64":
+        batch_main(a)
+        return
     spec, inp, desc = workload(a.config)
     tuned = 0
     if not a.no_tune:
@@ -189,38 +338,7 @@ def main():
                      "n_waits": st["n_waits"], "n_streams": st["n_streams"]}
         print(f"# {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
 
-    # Dominant kernel: per kernel class, the mean duration of back-to-back launches on the
-    # class's own stream (HIP events around the launches, on that stream) times its launches per
-    # step; the class with the largest product dominates the step.
-    r = runners["fine"]
-    kers = {}
-    for k in range(len(spec["kernels"])):
-        key, work, bound, dt = kernel_class(spec, k)
-        kers.setdefault(key, {"work": work, "bound": bound, "dtype": dt, "ids": []})["ids"].append(k)
-    for key, c in kers.items():
-        psc.psc_kernel_time(r.sched, c["ids"][0], 10)
-        c["avg_us"] = psc.psc_kernel_time(r.sched, c["ids"][0], a.kernel_iters)
-        c["total_us"] = c["avg_us"] * len(c["ids"])
-        if c["bound"] == "mfma":
-            c["tile"] = psc.psc_sched_kernel_tile(r.sched, c["ids"][0])
-    print("# kernel classes (isolated mean us per launch x launches per step):", file=sys.stderr)
-    for key, c in sorted(kers.items(), key=lambda kv: -kv[1]["total_us"]):
-        print(f"#   {key}: {c['avg_us']:.2f} us x {len(c['ids'])}" + (f" (tile {c['tile']})" if "tile" in c else ""),
-              file=sys.stderr)
-    dom_key = max(kers, key=lambda k: kers[k]["total_us"])
-    dom = kers[dom_key]
-    avg_us = dom["avg_us"]
-    achieved = dom["work"] / (avg_us * 1e-6)
-    if dom["bound"] == "mfma":
-        peak = PEAK["mfma_bf16"] if dom["dtype"] == "bf16" else PEAK["mfma_f32"]
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
-    else:
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None}
-    roof.update({"kernel": dom_key, "avg_us": avg_us, "launches_per_step": len(dom["ids"]),
-                 "work_per_launch": dom["work"],
-                 "timing": f"{a.kernel_iters} back-to-back launches, HIP events on its stream"})
+    roof = dominant_roofline(spec, runners["fine"], a.kernel_iters)
 
     # concurrency of the fine schedule from a per-op timeline (start/end events around every op)
     rec = psc.SpecRunner(spec, "fine", record_ops=True, **fine_opts)

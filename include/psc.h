@@ -119,7 +119,12 @@ typedef struct psc_sched_opts {
   const psc_mlp *cost;  /* learned cost model for PSC_MAP_EFT; NULL = heuristic model */
   int32_t host_threads; /* host threads that enqueue in psc_run (stream s is enqueued by thread
                            s mod host_threads); 0 = one per stream, 1 = the caller only */
-  int32_t reserved[7];
+  int32_t mark_components; /* 1: psc_run stamps the device clock before the first op and after
+                              every END kernel of each task component (a one-thread marker
+                              kernel, also inside the graph), so psc_sched_component_times can
+                              report when each component finished -- per-instance latency of a
+                              batch.  PSC_DEVICE always keeps per-kernel clocks instead. */
+  int32_t reserved[6];
 } psc_sched_opts;
 
 /* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..
@@ -260,6 +265,13 @@ psc_status psc_run(psc_sched *sched, const psc_host_io *io, int32_t n_io, psc_ru
 
 /* Per-op timeline of the last psc_run made with record_ops = 1: out[0..cap), *n = op count. */
 psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t cap, int32_t *n);
+
+/* [GPU] Completion of each task component in the last psc_run: done_us[c] = microseconds from
+ * the run's start mark to the end of component c's last END kernel (a kernel with no successor
+ * in its component, Def. 2), or -1 for a component with no kernel.  *n = number of components
+ * (largest component id + 1).  Needs mark_components (or PSC_DEVICE).  PSC_ERR_STATE without
+ * such a run; PSC_ERR_ARG if cap < *n (done_us may be NULL to query *n). */
+psc_status psc_sched_component_times(const psc_sched *sched, float *done_us, int32_t cap, int32_t *n);
 
 /* [GPU after prepare] Device address of buffer `name` (a view's address is inside its root's
  * storage) and its leading dimension in elements.  PSC_ERR_STATE before psc_sched_prepare. */

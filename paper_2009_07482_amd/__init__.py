@@ -60,7 +60,8 @@ class psc_kernel_params(C.Structure):
 class psc_sched_opts(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("mapper", C.c_int32), ("copy_stream", C.c_int32),
                 ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
-                ("cost", C.c_void_p), ("host_threads", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("cost", C.c_void_p), ("host_threads", C.c_int32), ("mark_components", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class psc_op(C.Structure):
@@ -140,6 +141,7 @@ _SIGS = {
     "psc_mlp_train": [_P, C.c_void_p, C.c_void_p, _I64, C.POINTER(psc_mlp_train_opts), C.c_void_p],
     "psc_cost_predict": [_P, C.c_void_p, _I64, C.c_void_p],
     "psc_kernel_features": [_P, _I, _I, C.c_void_p],
+    "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
     "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
                               C.POINTER(C.c_float)],
@@ -234,7 +236,7 @@ def psc_dag_classify(dag, component):
 
 
 def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
-              device=0, cost=None, host_threads=0):
+              device=0, cost=None, host_threads=0, mark_components=False):
     o = psc_sched_opts()
     o.n_streams = int(n_streams)
     o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
@@ -244,6 +246,7 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
     o.device = int(device)
     o.cost = None if cost is None else C.c_void_p(int(cost.value if hasattr(cost, "value") else cost))
     o.host_threads = int(host_threads)
+    o.mark_components = int(bool(mark_components))
     return o
 
 
@@ -301,6 +304,16 @@ def psc_sched_op_times(sched):
     buf = (psc_op_time * max(1, n.value))()
     _check(_lib.psc_sched_op_times(sched, buf, n.value, C.byref(n)))
     return [(t.op, t.stream, t.start_us, t.end_us) for t in buf[:n.value]]
+
+
+def psc_sched_component_times(sched):
+    """Microseconds from the run's start mark to the end of each task component (-1: empty)."""
+    import numpy as np
+    n = _I()
+    _check(_lib.psc_sched_component_times(sched, None, 0, C.byref(n)))
+    out = np.zeros(max(1, n.value), np.float32)
+    _check(_lib.psc_sched_component_times(sched, out.ctypes.data, n.value, C.byref(n)))
+    return out[:n.value]
 
 
 def psc_sched_samples(sched):

@@ -22,6 +22,7 @@ void prepare(psc_sched &s);
 void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats);
 void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n);
 void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_t *n);
+void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
 float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
@@ -252,6 +253,7 @@ psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts
     need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
     need(!(o.use_graph && o.record_ops), PSC_ERR_ARG, "record_ops cannot be combined with use_graph");
     need(o.device >= 0, PSC_ERR_ARG, "negative device");
+    need(o.mark_components == 0 || o.mark_components == 1, PSC_ERR_ARG, "mark_components must be 0 or 1");
     psc::Dag &g = dag->g;
     if (!g.validated || !g.frozen) g.validate();
     g.frozen = true;
@@ -313,6 +315,13 @@ psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t 
   return guard([&] {
     need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
     psc::op_times(*sched, out, cap, n);
+  });
+}
+
+psc_status psc_sched_component_times(const psc_sched *sched, float *done_us, int32_t cap, int32_t *n) {
+  return guard([&] {
+    need(sched && n, PSC_ERR_ARG, "NULL argument");
+    psc::component_times(*sched, done_us, cap, n);
   });
 }
 

@@ -155,6 +155,20 @@ int64_t tiles_of(int t, int M, int N) {
 
 int gemm_num_tiles() { return kNumTiles; }
 
+namespace {
+__global__ __launch_bounds__(64) void mark_kernel(uint64_t *slot) {
+  if (threadIdx.x == 0) *slot = wall_clock64();
+}
+}  // namespace
+
+void make_mark(Launch &L, uint64_t *slot) {
+  L = Launch{};
+  L.func = reinterpret_cast<const void *>(&mark_kernel);
+  L.grid = dim3(1, 1, 1);
+  L.block = dim3(64, 1, 1);
+  std::memcpy(L.args, &slot, sizeof(slot));
+}
+
 int gemm_auto_tile(int M, int N, int K, int dtype) {
   (void)dtype;
   // Enough output tiles to fill the chip: the large-tile kernels.  Otherwise the split-K kernels,

@@ -56,6 +56,8 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype);
 bool make_transpose(Launch &L, TransArgs a, int dtype);
 bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype);
 int gemm_num_tiles();
+// One-thread kernel that stores the device wall clock (wall_clock64) to *slot.
+void make_mark(Launch &L, uint64_t *slot);
 void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
 int tile_cache_get(int M, int N, int K, int ab, int c);
 void tile_cache_clear();

@@ -53,6 +53,11 @@ struct Device {
   std::vector<psc_op_time> times;
   std::vector<char> active;        // per op in the recorded run: it did work
   bool have_times = false;
+  // component completion marks (mark_components): slot k = after END kernel k, slot nk = start
+  uint64_t *marks = nullptr;
+  Launch mark_start;
+  std::vector<Launch> mark_after;  // per kernel; .func == nullptr unless an END kernel
+  bool have_marks = false;
   std::unique_ptr<Dispatcher> disp;
   // PSC_DEVICE executor
   void *exec_mem = nullptr;
@@ -64,6 +69,7 @@ struct Device {
   ~Device() {
     disp.reset();
     if (exec_mem) (void)hipFree(exec_mem);
+    if (marks) (void)hipFree(marks);
     if (h_err) (void)hipHostFree(h_err);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -256,6 +262,20 @@ void prepare(psc_sched &s) {
   }
   d->launch.assign(g.kers.size(), Launch{});
   for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, *d, int32_t(k), d->launch[k]);
+  if (s.opts.mark_components && !dev_mode) {
+    const size_t nk = g.kers.size();
+    PSC_HIP(hipMalloc(&d->marks, 8 * (nk + 1)));
+    make_mark(d->mark_start, d->marks + nk);
+    d->mark_after.assign(nk, Launch{});
+    for (size_t k = 0; k < nk; ++k) {
+      bool end = true;
+      for (int32_t q : g.succ[k]) end = end && g.kers[q].component != g.kers[k].component;
+      if (end) make_mark(d->mark_after[k], d->marks + k);
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d->device) == hipSuccess && khz > 0)
+      d->clock_mhz = khz / 1000.0;
+  }
   if (dev_mode) {
     prepare_executor(g, *d);
   } else {
@@ -339,6 +359,7 @@ struct HipBackend final : Backend {
     if (op.type == PSC_OP_KERNEL) launch(d.launch[op.kernel], st(o));
     else do_copy(cd[o], st(o));
     if (timed) PSC_HIP(hipEventRecord(d.t1[o], st(o)));
+    if (op.type == PSC_OP_KERNEL && d.marks && d.mark_after[op.kernel].func) launch(d.mark_after[op.kernel], st(o));
   }
   void record(int32_t o) override { PSC_HIP(hipEventRecord(d.op_ev[o], st(o))); }
   void stream_done(int32_t stream) override {
@@ -366,24 +387,29 @@ void build_graph(psc_sched &s, const std::vector<CopyDesc> &cd) {
   const size_t n = s.plan.ops.size();
   std::vector<hipGraphNode_t> node(n, nullptr), last(s.plan.total_streams, nullptr);
   std::vector<hipGraphNode_t> deps;
+  auto kernel_node = [&](const Launch &L, const hipGraphNode_t *dp, size_t nd) {
+    hipKernelNodeParams kp{};
+    void *args[] = {const_cast<unsigned char *>(L.args)};
+    kp.func = const_cast<void *>(L.func);
+    kp.gridDim = L.grid;
+    kp.blockDim = L.block;
+    kp.sharedMemBytes = L.shmem;
+    kp.kernelParams = args;
+    hipGraphNode_t x = nullptr;
+    PSC_HIP(hipGraphAddKernelNode(&x, d.graph, dp, nd, &kp));
+    return x;
+  };
+  hipGraphNode_t start_mark = d.marks ? kernel_node(d.mark_start, nullptr, 0) : nullptr;
   for (size_t o = 0; o < n; ++o) {
     const Op &op = s.plan.ops[o];
     deps.clear();
     if (last[op.stream]) deps.push_back(last[op.stream]);
     for (int32_t w : op.waits) deps.push_back(node[w]);
+    if (deps.empty() && start_mark) deps.push_back(start_mark);
     hipGraphNode_t nd = nullptr;
     const hipGraphNode_t *dp = deps.empty() ? nullptr : deps.data();
     if (op.type == PSC_OP_KERNEL && !d.launch[op.kernel].empty) {
-      const Launch &L = d.launch[op.kernel];
-      void *args[] = {const_cast<unsigned char *>(L.args)};
-      hipKernelNodeParams kp{};
-      kp.func = const_cast<void *>(L.func);
-      kp.gridDim = L.grid;
-      kp.blockDim = L.block;
-      kp.sharedMemBytes = L.shmem;
-      kp.kernelParams = args;
-      kp.extra = nullptr;
-      PSC_HIP(hipGraphAddKernelNode(&nd, d.graph, dp, deps.size(), &kp));
+      nd = kernel_node(d.launch[op.kernel], dp, deps.size());
     } else if (op.type != PSC_OP_KERNEL && cd[o].active) {
       const CopyDesc &c = cd[o];
       if (c.dpitch == c.width && c.spitch == c.width) {
@@ -401,6 +427,7 @@ void build_graph(psc_sched &s, const std::vector<CopyDesc> &cd) {
     }
     node[o] = nd;
     last[op.stream] = nd;
+    if (op.type == PSC_OP_KERNEL && d.marks && d.mark_after[op.kernel].func) kernel_node(d.mark_after[op.kernel], &nd, 1);
   }
   PSC_HIP(hipGraphInstantiate(&d.exec, d.graph, nullptr, nullptr, 0));
 }
@@ -443,6 +470,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   } else {
     const auto h0 = std::chrono::steady_clock::now();
+    if (d.marks) launch(d.mark_start, s0);
     PSC_HIP(hipEventRecord(d.start, s0));
     fork_streams(d, d.start);
     HipBackend backend(s, cd, timed);
@@ -454,6 +482,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   PSC_HIP(hipEventSynchronize(d.end));
   float ms = 0;
   PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
+  d.have_marks = d.marks != nullptr || s.plan.device;
   if (s.plan.device && *d.h_err)
     fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) +
                           "): a queue wait or a worker loop exceeded its bound");
@@ -557,6 +586,40 @@ void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_
     if (log_us) log_us[i] = float(std::log(double(t[o].end_us) - double(t[o].start_us)));
     ++i;
   }
+}
+
+void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n) {
+  const Dag &g = s.dag->g;
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  int32_t nc = 0;
+  for (const Kernel &k : g.kers) nc = std::max(nc, k.component + 1);
+  *n = nc;
+  if (!done_us) return;
+  if (cap < nc) fail(PSC_ERR_ARG, "capacity too small");
+  if (!s.dev || !s.dev->have_marks)
+    fail(PSC_ERR_STATE, "no marked run (set mark_components, or use PSC_DEVICE, and call psc_run)");
+  const Device &d = *s.dev;
+  PSC_HIP(hipSetDevice(d.device));
+  std::vector<uint64_t> at(nk + 1, 0);  // completion clock per END kernel, start at [nk]
+  std::vector<char> end(nk, 0);
+  for (int32_t k = 0; k < nk; ++k) {
+    end[k] = 1;
+    for (int32_t q : g.succ[k]) end[k] = end[k] && g.kers[q].component != g.kers[k].component;
+  }
+  if (s.plan.device) {
+    PSC_HIP(hipMemcpy(at.data(), d.ea.t_last, 8 * size_t(nk), hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(&at[nk], d.ea.t_start, 8, hipMemcpyDeviceToHost));
+  } else {
+    PSC_HIP(hipMemcpy(at.data(), d.marks, 8 * size_t(nk + 1), hipMemcpyDeviceToHost));
+  }
+  std::vector<double> done(nc, -1.0);
+  for (int32_t k = 0; k < nk; ++k)
+    if (end[k]) {
+      const double us = double(int64_t(at[k] - at[nk])) / d.clock_mhz;
+      double &c = done[g.kers[k].component];
+      c = std::max(c, us);
+    }
+  for (int32_t c = 0; c < nc; ++c) done_us[c] = float(done[c]);
 }
 
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) {
