@@ -372,10 +372,24 @@ psc_status psc_kernel_features(const psc_dag *dag, int32_t kernel, int32_t in_fl
  * *n = number of samples; PSC_ERR_ARG if cap < *n; PSC_ERR_STATE without a recorded run. */
 psc_status psc_sched_samples(const psc_sched *sched, float *features, float *log_us, int32_t cap, int32_t *n);
 
+/* Host-only view of the PSC_DEVICE executor's plan for `workers` workgroups (the run uses one per
+ * resident slot of the GPU): every kernel is cut into tasks (output tiles or row groups), and
+ * the tasks are list-scheduled onto the workgroups.  tasks[3*i .. 3*i+2] = (kernel, tile,
+ * signal) of the i-th task, where the lists of workgroups 0, 1, ... follow each other and
+ * workgroup w's list is tasks [work_off[w], work_off[w+1]); signal > 0 means that after this
+ * task the workgroup publishes that many completed tiles of the kernel (the run of its tiles
+ * ending here).  *n_tasks = total; with tasks and work_off NULL only the total is returned;
+ * work_off holds workers + 1 entries.  Any schedule of the DAG may be passed (its policy is not
+ * used).  PSC_ERR_ARG if cap < *n_tasks. */
+psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32_t *tasks, int32_t cap,
+                                  int32_t *n_tasks, int32_t *work_off);
+
 /* ---------------------------------------------------------------------------------------------
  * GEMM tile autotuner.  Tile configurations are numbered 1 .. n-1 (psc_gemm_tile_count gives n):
  * 1..5 large-tile kernels (128x128, 64x64, 32x32, 128x64, 64x128), 6..12 K-split small-tile
- * kernels (64x64, 32x64, 64x32, 32x32, 16x32, 32x16, 16x16).  A GEMM whose params leave tile at
+ * kernels staging operands through LDS (64x64, 32x64, 64x32, 32x32, 16x32, 32x16, 16x16), 13..15
+ * K-split 16-row kernels reading operands directly into matrix-core registers (16x16, 16x32,
+ * 16x64).  A GEMM whose params leave tile at
  * 0 takes the process-wide cache entry for its (M, N, K, operand dtype, output dtype) when there
  * is one, and a size heuristic otherwise; the choice is made when a schedule is prepared.  The
  * cache is thread safe.  (The paper leaves autotuning to future work, Sec. VII.)

@@ -141,6 +141,7 @@ _SIGS = {
     "psc_mlp_train": [_P, C.c_void_p, C.c_void_p, _I64, C.POINTER(psc_mlp_train_opts), C.c_void_p],
     "psc_cost_predict": [_P, C.c_void_p, _I64, C.c_void_p],
     "psc_kernel_features": [_P, _I, _I, C.c_void_p],
+    "psc_sched_device_tasks": [_P, _I, C.c_void_p, _I, C.POINTER(_I), C.c_void_p],
     "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
     "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
@@ -304,6 +305,17 @@ def psc_sched_op_times(sched):
     buf = (psc_op_time * max(1, n.value))()
     _check(_lib.psc_sched_op_times(sched, buf, n.value, C.byref(n)))
     return [(t.op, t.stream, t.start_us, t.end_us) for t in buf[:n.value]]
+
+
+def psc_sched_device_tasks(sched, workers):
+    """Host-only plan of the device executor: ([(kernel, tile, signal)] per workgroup)."""
+    import numpy as np
+    n = _I()
+    _check(_lib.psc_sched_device_tasks(sched, int(workers), None, 0, C.byref(n), None))
+    t = np.zeros((max(1, n.value), 3), np.int32)
+    off = np.zeros(int(workers) + 1, np.int32)
+    _check(_lib.psc_sched_device_tasks(sched, int(workers), t.ctypes.data, n.value, C.byref(n), off.ctypes.data))
+    return [[tuple(int(v) for v in t[i]) for i in range(off[w], off[w + 1])] for w in range(int(workers))]
 
 
 def psc_sched_component_times(sched):

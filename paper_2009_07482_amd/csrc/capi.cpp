@@ -23,6 +23,8 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
 void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n);
 void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_t *n);
 void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n);
+void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t cap, int32_t *n_tasks,
+                  int32_t *work_off);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
 float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
@@ -315,6 +317,15 @@ psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t 
   return guard([&] {
     need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
     psc::op_times(*sched, out, cap, n);
+  });
+}
+
+psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32_t *tasks, int32_t cap,
+                                  int32_t *n_tasks, int32_t *work_off) {
+  return guard([&] {
+    need(sched && n_tasks, PSC_ERR_ARG, "NULL argument");
+    need(workers >= 1, PSC_ERR_ARG, "workers must be >= 1");
+    psc::device_tasks(*sched, workers, tasks, cap, n_tasks, work_off);
   });
 }
 

@@ -65,6 +65,18 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
   gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 
+template <int FN, bool VEC, bool OUT_BF16>
+__global__ __launch_bounds__(256) void gemm_f32_direct_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN>()];
+  gemm_direct_tile<FN, false, VEC, OUT_BF16>(p, blockIdx.x, smem);
+}
+
+template <int FN, bool VEC, bool OUT_BF16>
+__global__ __launch_bounds__(256) void gemm_bf16_direct_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN>()];
+  gemm_direct_tile<FN, true, VEC, OUT_BF16>(p, blockIdx.x, smem);
+}
+
 template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16>
 __global__ __launch_bounds__(256) void softmax_kernel(SoftmaxArgs p) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -99,12 +111,14 @@ struct TileCfg {
   int bm, bn;
   bool splitk;  // K split across the block's four wavefronts
 };
+// 1..5: large tiles; 6..12: K split over the wavefronts, operands through LDS; 13..15: K split
+// over the wavefronts, operands read directly into matrix-core registers (16-row tiles).
 
 // GEMM tile configurations (index = psc_kernel_params.tile; 0 = automatic)
 constexpr TileCfg kTiles[] = {{0, 0, false},     {128, 128, false}, {64, 64, false},  {32, 32, false},
                               {128, 64, false},  {64, 128, false},  {64, 64, true},   {32, 64, true},
                               {64, 32, true},    {32, 32, true},    {16, 32, true},   {32, 16, true},
-                              {16, 16, true}};
+                              {16, 16, true},    {16, 16, true},    {16, 32, true},   {16, 64, true}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 #define PSC_VO(KERNEL, ...)                                                                     \
@@ -126,6 +140,9 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 10: return PSC_VO(gemm_f32_splitk_kernel, 16, 32);
       case 11: return PSC_VO(gemm_f32_splitk_kernel, 32, 16);
       case 12: return PSC_VO(gemm_f32_splitk_kernel, 16, 16);
+      case 13: return PSC_VO(gemm_f32_direct_kernel, 1);
+      case 14: return PSC_VO(gemm_f32_direct_kernel, 2);
+      case 15: return PSC_VO(gemm_f32_direct_kernel, 4);
     }
   } else {
     switch (tile) {
@@ -141,6 +158,9 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 10: return PSC_VO(gemm_bf16_splitk_kernel, 16, 32);
       case 11: return PSC_VO(gemm_bf16_splitk_kernel, 32, 16);
       case 12: return PSC_VO(gemm_bf16_splitk_kernel, 16, 16);
+      case 13: return PSC_VO(gemm_bf16_direct_kernel, 1);
+      case 14: return PSC_VO(gemm_bf16_direct_kernel, 2);
+      case 15: return PSC_VO(gemm_bf16_direct_kernel, 4);
     }
   }
   return nullptr;

@@ -3,22 +3,23 @@
 // The fine-grained schedules of Sec. IV-B enforce a kernel's precedences with events between host
 // queues; here the same precedences are enforced on the GPU, at tile granularity, by one
 // persistent kernel.  Every DAG kernel is split into tasks (GEMM output tiles, groups of 16
-// softmax rows, 64 x 64 transpose tiles, groups of 8 added rows).  A work queue in device memory
-// holds one slot per task; the reset kernel fills it with the tasks of the kernels that have no
-// predecessor.  Each workgroup of the executor repeatedly claims the next slot (an atomic head),
-// waits until that slot has been published, runs the task's tile function, and counts the task
-// as done; the workgroup that completes a kernel's last task decrements the pending-predecessor
-// count of each successor, and publishes all tasks of every successor that reaches zero (an
-// atomic tail reserves their slots).  Task results are published with agent-scope release
-// (fence before the completion count) and read after an agent-scope acquire (the slot load and a
-// fence), so tiles written on one XCD are visible to consumers on another.
+// softmax rows, 64 x 64 transpose tiles, groups of 8 added rows).  As setup_cq maps kernels to
+// command queues ahead of dispatch (Algorithm 1), the host maps tasks to the executor's
+// workgroups ahead of the run: a list schedule in a topological order of the kernels, each task
+// on the workgroup predicted to be free first.  A workgroup walks its list; before the first
+// task of a kernel it waits until every predecessor kernel's completion counter reaches that
+// kernel's tile count, and after its last consecutive task of a kernel it adds their number to
+// the kernel's counter.  Tiles are published with an agent-scope release (fence, then the
+// counter add) and read after an agent-scope acquire (counter loads, then a fence), so data
+// written on one XCD is visible to consumers on another.
 //
-// Progress: a claimed slot is published eventually because, while any task is unfinished, some
-// published task has all its predecessors done (the DAG is acyclic) and only executing
-// workgroups publish.  Every wait is bounded by max_spin polls: past it (or once another
-// workgroup has flagged an error) the workgroup records ctl[2] = 1 and exits, so every wave of
-// the grid reaches its exit even if a description were wrong; a workgroup whose loop runs more
-// iterations than there are tasks also stops and flags an error.  Claims past the last task exit.
+// Progress: every list is a subsequence of one global topological order of the tasks, and the
+// grid is no larger than the number of workgroups the GPU holds at once, so once all workgroups
+// are resident the earliest unfinished task always has its predecessors done and its workgroup
+// at it (a workgroup not yet resident only has to wait for a CU that other work frees).  Every
+// wait is also bounded in device-clock time: past the bound (or once another workgroup has
+// flagged an error) the workgroup records the error in ctl[0] and leaves its loop, so every wave
+// reaches its exit even if a description were wrong.
 #include "persistent.hpp"
 
 #include "tiles.hpp"
@@ -81,18 +82,26 @@ __device__ __forceinline__ void run_task(const ExecNode *ndp, int tile, unsigned
     case 149: gemm_f32_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 150: gemm_f32_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 151: gemm_f32_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 160: gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 161: gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 164: gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 165: gemm_bf16_tile<32, 32, 64, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 188: gemm_bf16_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 189: gemm_bf16_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 192: gemm_bf16_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 193: gemm_bf16_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 198: gemm_bf16_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 199: gemm_bf16_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 200: gemm_bf16_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 201: gemm_bf16_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 152: gemm_direct_tile<1, false, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 153: gemm_direct_tile<1, false, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 154: gemm_direct_tile<1, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 155: gemm_direct_tile<1, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 158: gemm_direct_tile<2, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 159: gemm_direct_tile<2, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 162: gemm_direct_tile<4, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 163: gemm_direct_tile<4, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 210: gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 211: gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 214: gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 215: gemm_bf16_tile<32, 32, 64, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 238: gemm_bf16_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 239: gemm_bf16_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 242: gemm_bf16_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 243: gemm_bf16_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 248: gemm_bf16_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 249: gemm_bf16_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 250: gemm_bf16_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 251: gemm_bf16_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 300: softmax_task<0, false, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
     case 301: softmax_task<0, false, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
     case 302: softmax_task<0, false, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
@@ -127,97 +136,96 @@ constexpr int kExecSmem = 49152;  // the largest tile function's LDS (FP32 K-spl
 
 __global__ __launch_bounds__(256) void exec_reset_kernel(ExecArgs a) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i < a.total_tasks) a.slots[i] = i < uint32_t(a.n_roots) ? a.roots[i] : 0;
   if (i < uint32_t(a.n_nodes)) {
-    a.pending[i] = uint32_t(a.nodes[i].n_pred);
     a.done[i] = 0;
     a.t_first[i] = kExit;
     a.t_last[i] = 0;
   }
   if (i == 0) {
     a.ctl[0] = 0;
-    a.ctl[1] = uint32_t(a.n_roots);
-    a.ctl[2] = 0;
-    a.ctl[3] = 0;
     *a.t_start = wall_clock64();
   }
 }
 
-// Completion of one task by thread 0: count it; the task that completes its kernel releases
-// the successors whose last predecessor this was and publishes all their tasks.
-__device__ __forceinline__ void complete_task(const ExecArgs &a, int32_t node) {
-  const ExecNode &nd = a.nodes[node];
-  const uint32_t d = __hip_atomic_fetch_add(&a.done[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  if (d + 1 != uint32_t(nd.n_tiles)) return;
-  __hip_atomic_store(&a.t_last[node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int32_t j = 0; j < nd.n_succ; ++j) {
-    const int32_t s = a.succ[nd.succ_off + j];
-    const uint32_t left = __hip_atomic_fetch_sub(&a.pending[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (left != 1) continue;
-    const uint32_t nt = uint32_t(a.nodes[s].n_tiles);
-    const uint32_t base = __hip_atomic_fetch_add(&a.ctl[1], nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (uint32_t t = 0; t < nt && base + t < a.total_tasks; ++t)
-      __hip_atomic_store(&a.slots[base + t], (uint64_t(s + 1) << 32) | t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Claim by thread 0: the next queue slot's task once published, or kExit (queue exhausted, an
-// error flagged elsewhere, or this wait exceeded its bound -- then flag the error).
-__device__ __forceinline__ uint64_t claim_task(const ExecArgs &a) {
-  const uint32_t i = __hip_atomic_fetch_add(&a.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (i >= a.total_tasks) return kExit;
-  for (uint32_t spin = 0;; ++spin) {
-    const uint64_t x = __hip_atomic_load(&a.slots[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (x) return x;
-    if (__hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return kExit;
-    if (spin >= a.max_spin) {
-      __hip_atomic_fetch_or(&a.ctl[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return kExit;
+// Thread 0: wait until every predecessor of `node` has all its tiles done.  Returns false (and
+// flags the error) if a wait exceeds a.max_wait ticks, or if another workgroup flagged one.
+__device__ __forceinline__ bool wait_preds(const ExecArgs &a, const ExecNode &nd) {
+  for (int32_t j = 0; j < nd.n_pred; ++j) {
+    const int32_t p = a.pred[nd.pred_off + j];
+    const uint32_t need = uint32_t(a.nodes[p].n_tiles);
+    if (__hip_atomic_load(&a.done[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) continue;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(&a.done[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (__hip_atomic_load(&a.ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (wall_clock64() - t0 > a.max_wait) {
+        __hip_atomic_fetch_or(&a.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_s_sleep(2);
   }
+  return true;
 }
 
-// Every branch that encloses a barrier depends only on wavefront-uniform values: the task word is
-// broadcast through LDS and read with readfirstlane, so the exit test, the kernel index and the
-// tile arguments live in scalar registers and all 256 threads take the same path each iteration.
+// Every branch that encloses a barrier depends only on wavefront-uniform values: list bounds and
+// task entries are read with readfirstlane, and the wait's verdict is broadcast through LDS and
+// read the same way, so all 256 threads take the same path each iteration.
 __global__ __launch_bounds__(256) void exec_kernel(ExecArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kExecSmem];
-  __shared__ uint64_t s_task;
-  int32_t prev = -1;  // kernel of the task finished in the previous iteration (uniform)
-  for (uint32_t iter = 0;; ++iter) {
-    if (threadIdx.x == 0) {
-      if (prev >= 0) complete_task(a, prev);
-      // no workgroup can run more tasks than exist: a longer loop means the run is broken
-      if (iter > a.total_tasks) {
-        __hip_atomic_fetch_or(&a.ctl[2], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_task = kExit;
-      } else {
-        s_task = claim_task(a);
+  __shared__ uint32_t s_ok;
+  const int32_t w = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x));
+  const int32_t lo = __builtin_amdgcn_readfirstlane(a.work_off[w]);
+  const int32_t hi = __builtin_amdgcn_readfirstlane(a.work_off[w + 1]);
+  int32_t checked = -1;  // node whose predecessors this workgroup has seen complete (uniform)
+  for (int32_t i = lo; i < hi; ++i) {
+    const ExecTask t = uniform_load<ExecTask>(reinterpret_cast<const unsigned char *>(a.tasks + i));
+    const ExecNode *nd = a.nodes + t.node;
+    if (t.node != checked) {
+      if (__builtin_amdgcn_readfirstlane(nd->n_pred) > 0) {
+        // One acquire for the workgroup: thread 0 observes the counters, then invalidates this
+        // CU's L1 and the XCD's L2 (cache-wide operations) before the barrier releases the
+        // other wavefronts to read the predecessors' outputs.
+        if (threadIdx.x == 0) {
+          const bool ok = wait_preds(a, *nd);
+          if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+          }
+          s_ok = ok ? 1u : 0u;
+        }
+        __syncthreads();
+        const uint32_t ok = __builtin_amdgcn_readfirstlane(s_ok);
+        if (!ok) break;
       }
+      checked = t.node;
     }
-    __syncthreads();
-    const uint64_t raw = s_task;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(raw));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(raw >> 32));
-    __syncthreads();
-    if ((lo == 0xffffffffu && hi == 0xffffffffu) || iter > a.total_tasks) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int32_t node = int32_t(hi) - 1;
-    const int32_t tile = int32_t(lo);
     if (threadIdx.x == 0)
-      __hip_atomic_fetch_min(&a.t_first[node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    run_task(a.nodes + node, tile, smem);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    prev = node;
+      __hip_atomic_fetch_min(&a.t_first[t.node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    run_task(nd, t.tile, smem);
+    if (t.signal > 0) {
+      // One release for the workgroup: every wavefront waits until its stores have reached the
+      // L2, the barrier orders that before thread 0's release fence (a write-back of the whole
+      // L2) and its counter update.
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t before =
+            __hip_atomic_fetch_add(&a.done[t.node], uint32_t(t.signal), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + uint32_t(t.signal) == uint32_t(nd->n_tiles))
+          __hip_atomic_store(&a.t_last[t.node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      __syncthreads();  // the next task reuses the LDS
+    }
   }
 }
 
 struct PCfg {
   int cfg, bm, bn;
 };
-constexpr PCfg kPersistentGemm[] = {{2, 64, 64}, {3, 32, 32}, {9, 32, 32}, {10, 16, 32}, {12, 16, 16}};
+constexpr PCfg kPersistentGemm[] = {{2, 64, 64},  {3, 32, 32},  {9, 32, 32}, {10, 16, 32},
+                                    {12, 16, 16}, {13, 16, 16}, {14, 16, 32}, {15, 16, 64}};
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -239,15 +247,20 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
         case 3: cfg = 3; break;
         case 6: case 7: case 8: case 9: cfg = 9; break;
         case 10: case 11: cfg = 10; break;
+        case 13: cfg = in_dtype == 0 ? 13 : 12; break;
+        case 14: cfg = in_dtype == 0 ? 14 : 10; break;
+        case 15: cfg = in_dtype == 0 ? 15 : 10; break;
         default: cfg = 12; break;
       }
-      if (!vec) cfg = 12;
+      if (!vec) cfg = (in_dtype == 0 && cfg == 13) ? 13 : 12;
       int bm = 16, bn = 16;
       for (const PCfg &c : kPersistentGemm)
         if (c.cfg == cfg) { bm = c.bm; bn = c.bn; }
       g.tiles_n = (g.N + bn - 1) / bn;
-      n.variant = 100 + in_dtype * 50 + cfg * 4 + (vec ? 2 : 0) + (out_dtype == 1 ? 1 : 0);
+      n.variant = 100 + in_dtype * 100 + cfg * 4 + (vec ? 2 : 0) + (out_dtype == 1 ? 1 : 0);
       n.n_tiles = ((g.M + bm - 1) / bm) * g.tiles_n;
+      n.tile_m = bm;
+      n.tile_n = bn;
       memcpy(n.args, &g, sizeof(g));
       return n;
     }
@@ -262,6 +275,8 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       if (vec) code = sa.C <= 256 ? 1 : sa.C <= 512 ? 2 : sa.C <= 1024 ? 3 : sa.C <= 2048 ? 4 : 0;
       n.variant = 300 + code * 8 + (code ? 4 : 0) + in_dtype * 2 + out_dtype;
       n.n_tiles = (sa.R + 15) / 16;
+      n.tile_m = 16;
+      n.tile_n = sa.C;
       memcpy(n.args, &sa, sizeof(sa));
       return n;
     }
@@ -271,6 +286,8 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       if (ta.R == 0 || ta.C == 0) break;
       n.variant = 400 + in_dtype;
       n.n_tiles = ((ta.R + 63) / 64) * ((ta.C + 63) / 64);
+      n.tile_m = 64;
+      n.tile_n = 64;
       memcpy(n.args, &ta, sizeof(ta));
       return n;
     }
@@ -280,6 +297,8 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       if (aa.R == 0 || aa.C == 0) break;
       n.variant = 410 + in_dtype * 2 + out_dtype;
       n.n_tiles = (aa.R + 7) / 8;
+      n.tile_m = 8;
+      n.tile_n = aa.C;
       memcpy(n.args, &aa, sizeof(aa));
       return n;
     }
@@ -290,15 +309,15 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
 }
 
 hipError_t launch_exec_reset(const ExecArgs &a, hipStream_t stream) {
-  const uint32_t n = a.total_tasks > uint32_t(a.n_nodes) ? a.total_tasks : uint32_t(a.n_nodes);
+  const uint32_t n = uint32_t(a.n_nodes > 1 ? a.n_nodes : 1);
   void *args[] = {const_cast<ExecArgs *>(&a)};
-  return hipLaunchKernel((const void *)&exec_reset_kernel, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1),
-                         dim3(256), args, 0, stream);
+  return hipLaunchKernel((const void *)&exec_reset_kernel, dim3((n + 255) / 256), dim3(256), args, 0, stream);
 }
 
-hipError_t launch_exec(const ExecArgs &a, int workers, hipStream_t stream) {
+hipError_t launch_exec(const ExecArgs &a, hipStream_t stream) {
   void *args[] = {const_cast<ExecArgs *>(&a)};
-  return hipLaunchKernel((const void *)&exec_kernel, dim3(workers > 0 ? workers : 1), dim3(256), args, 0, stream);
+  return hipLaunchKernel((const void *)&exec_kernel, dim3(a.n_workers > 0 ? a.n_workers : 1), dim3(256), args, 0,
+                         stream);
 }
 
 int exec_max_workers(int device) {

@@ -1,6 +1,7 @@
 // Device-side DAG executor (policy PSC_DEVICE): one persistent kernel runs every kernel of the DAG
-// as tiles pulled from a device work queue, releasing a kernel's tiles when all its predecessors
-// have completed.  Host-side interface used by the runtime.
+// as tiles.  The host list-schedules the tiles onto the executor's workgroups (one ordered task
+// list per workgroup); a workgroup waits for a task's predecessor kernels through per-kernel
+// completion counters.  Host-side interface used by the runtime.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,37 +17,46 @@ namespace psc {
 struct alignas(16) ExecNode {
   int32_t variant;   // which tile function (see persistent.hip)
   int32_t n_tiles;   // tasks of this kernel (>= 1; an empty kernel has one no-op task)
-  int32_t n_succ;    // successors: succ[succ_off .. succ_off + n_succ)
-  int32_t succ_off;
-  int32_t n_pred;    // number of distinct predecessor kernels
-  int32_t pad[3];
+  int32_t n_pred;    // predecessor kernels: pred[pred_off .. pred_off + n_pred)
+  int32_t pred_off;
+  int32_t tile_m;    // output rows / columns covered by one task (cost estimates)
+  int32_t tile_n;
+  int32_t pad[2];
   unsigned char args[96];  // GemmArgs / SoftmaxArgs / TransArgs / AddArgs
+};
+
+// One entry of a workgroup's task list.  signal > 0: after this task, publish `signal`
+// completed tiles of `node` (the task and the ones of the same node right before it).
+struct alignas(16) ExecTask {
+  int32_t node;
+  int32_t tile;
+  int32_t signal;
+  int32_t pad;
 };
 
 struct ExecArgs {
   const ExecNode *nodes;
-  const int32_t *succ;
-  const uint64_t *roots;   // initial queue content: the tasks of every kernel with no predecessor
-  uint32_t *ctl;           // [0] head, [1] tail, [2] error, [3] unused
-  uint32_t *pending;       // per kernel: predecessors not yet complete
+  const int32_t *pred;
+  const ExecTask *tasks;   // every workgroup's list, back to back
+  const int32_t *work_off; // workgroup w runs tasks[work_off[w] .. work_off[w + 1])
   uint32_t *done;          // per kernel: tiles completed
-  uint64_t *slots;         // work queue, one slot per task: ((kernel + 1) << 32) | tile, 0 = empty
+  uint32_t *ctl;           // [0] error flags: 1 = a wait exceeded its bound
   uint64_t *t_first;       // per kernel: device clock when its first tile started
   uint64_t *t_last;        // per kernel: device clock when its last tile finished
-  uint64_t *t_start;       // device clock at queue reset
+  uint64_t *t_start;       // device clock at reset
   int32_t n_nodes;
-  int32_t n_roots;
-  uint32_t total_tasks;
-  uint32_t max_spin;       // bound on every wait: beyond it the run stops with ctl[2] = 1
+  int32_t n_workers;
+  uint64_t max_wait;       // device-clock ticks one wait may last before the run stops with an error
 };
 
 // Builds the executor's description of a kernel from the launch it would use standalone.
 // kind: psc_kind; dtypes: 0 = f32, 1 = bf16.
 ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile);
 
-// Launch helpers (enqueue on `stream`).
+// Launch helpers (enqueue on `stream`).  The executor runs a.n_workers workgroups, at most as
+// many as the GPU holds resident at once (a task may wait for any other workgroup's earlier task).
 hipError_t launch_exec_reset(const ExecArgs &a, hipStream_t stream);
-hipError_t launch_exec(const ExecArgs &a, int workers, hipStream_t stream);
+hipError_t launch_exec(const ExecArgs &a, hipStream_t stream);
 int exec_max_workers(int device);
 
 }  // namespace psc

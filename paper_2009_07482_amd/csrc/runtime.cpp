@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <queue>
 #include <string>
 
 #include "core.hpp"
@@ -62,7 +63,6 @@ struct Device {
   // PSC_DEVICE executor
   void *exec_mem = nullptr;
   ExecArgs ea{};
-  int exec_workers = 0;
   uint32_t *h_err = nullptr;  // page-locked word receiving the executor's error flag
   double clock_mhz = 100.0;   // device wall clock rate
 
@@ -155,35 +155,115 @@ namespace {
 
 int in_dtype_of(const Dag &g, const Kernel &k) { return g.bufs[k.ins[0]].dtype; }
 
-// Device-side executor state: node descriptions, successor lists, root tasks, counters, queue.
-void prepare_executor(const Dag &g, Device &d) {
+// Predicted duration of one executor task (microseconds) for the host's list schedule: a CU's
+// share of the matrix-core peak (at half efficiency) or of the memory bandwidth, plus a fixed
+// per-task overhead.
+double exec_task_us(const Dag &g, const Kernel &ker, const ExecNode &nd) {
+  constexpr double kOverhead = 0.6, kCuBw = 40e9;
+  if (nd.variant == 0) return 0.1;
+  const Buffer &a = g.bufs[ker.ins[0]], &o = g.bufs[ker.outs[0]];
+  const double ea = double(elem_size(a.dtype)), eo = double(elem_size(o.dtype));
+  if (ker.kind == PSC_GEMM) {
+    const double K = double(a.cols), bm = nd.tile_m, bn = nd.tile_n;
+    const double flops = 2.0 * bm * bn * K;
+    const double cu_flops = (a.dtype == PSC_BF16 ? 2.5e15 : 157.3e12) / 256.0 * 0.5;
+    const double bytes = (bm * K + K * bn) * ea + bm * bn * eo;
+    return kOverhead + std::max(flops / cu_flops, bytes / kCuBw) * 1e6;
+  }
+  const double elems = double(nd.tile_m) * double(nd.tile_n);
+  const double per = ker.kind == PSC_ADD ? 2.0 * ea + eo : ea + eo;
+  return kOverhead + elems * per / kCuBw * 1e6;
+}
+
+// The executor's plan: node descriptions, predecessor lists and the per-workgroup task lists (a
+// list schedule: kernels in descending bottom-level order among those whose predecessors are
+// placed, each task on the workgroup predicted to be free first).  Host only.
+struct ExecPlan {
+  std::vector<ExecNode> nodes;
+  std::vector<int32_t> pred;
+  std::vector<ExecTask> tasks;
+  std::vector<int32_t> work_off;
+};
+
+ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
-  std::vector<ExecNode> nodes(nk);
-  std::vector<int32_t> succ;
-  std::vector<uint64_t> roots;
+  ExecPlan ep;
+  ep.nodes.resize(nk);
   uint64_t total = 0;
   for (int32_t k = 0; k < nk; ++k) {
     const Kernel &ker = g.kers[k];
-    nodes[k] = make_exec_node(ker.kind, d.launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
-                              d.launch[k].tile);
-    nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
-    nodes[k].succ_off = static_cast<int32_t>(succ.size());
-    nodes[k].n_succ = static_cast<int32_t>(g.succ[k].size());
-    succ.insert(succ.end(), g.succ[k].begin(), g.succ[k].end());
-    total += uint64_t(nodes[k].n_tiles);
+    ep.nodes[k] = make_exec_node(ker.kind, launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
+                                 launch[k].tile);
+    ep.nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
+    ep.nodes[k].pred_off = static_cast<int32_t>(ep.pred.size());
+    ep.pred.insert(ep.pred.end(), g.pred[k].begin(), g.pred[k].end());
+    total += uint64_t(ep.nodes[k].n_tiles);
   }
   if (total >= (uint64_t(1) << 31)) fail(PSC_ERR_UNSUPPORTED, "too many executor tasks");
+  const int32_t W = static_cast<int32_t>(std::max<uint64_t>(1, std::min<uint64_t>(total, uint64_t(std::max(1, max_workers)))));
+  std::vector<double> cost(nk), bl(nk, 0.0), finish(nk, 0.0);
+  for (int32_t k = 0; k < nk; ++k) cost[k] = exec_task_us(g, g.kers[k], ep.nodes[k]);
+  const std::vector<int32_t> topo = g.bfs_order();
+  for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
+    double m = 0;
+    for (int32_t q : g.succ[*it]) m = std::max(m, bl[q]);
+    bl[*it] = cost[*it] * std::ceil(double(ep.nodes[*it].n_tiles) / W) + m;
+  }
+  using Item = std::pair<double, int32_t>;  // (-rank, kernel)
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
+  std::vector<int32_t> indeg(nk);
   for (int32_t k = 0; k < nk; ++k)
-    if (!nodes[k].n_pred)
-      for (int32_t t = 0; t < nodes[k].n_tiles; ++t) roots.push_back((uint64_t(k + 1) << 32) | uint32_t(t));
+    if (!(indeg[k] = static_cast<int32_t>(g.pred[k].size()))) ready.push({-bl[k], k});
+  using Free = std::pair<double, int32_t>;  // (time the workgroup is free, workgroup)
+  std::priority_queue<Free, std::vector<Free>, std::greater<Free>> free_at;
+  for (int32_t w = 0; w < W; ++w) free_at.push({0.0, w});
+  std::vector<std::vector<ExecTask>> lists(W);
+  while (!ready.empty()) {
+    const int32_t k = ready.top().second;
+    ready.pop();
+    double rt = 0;
+    for (int32_t p : g.pred[k]) rt = std::max(rt, finish[p]);
+    for (int32_t t = 0; t < ep.nodes[k].n_tiles; ++t) {
+      const Free f = free_at.top();
+      free_at.pop();
+      const double end = std::max(f.first, rt) + cost[k];
+      finish[k] = std::max(finish[k], end);
+      free_at.push({end, f.second});
+      lists[f.second].push_back(ExecTask{k, t, 0, 0});
+    }
+    for (int32_t q : g.succ[k])
+      if (--indeg[q] == 0) ready.push({-bl[q], q});
+  }
+  ep.work_off.assign(W + 1, 0);
+  ep.tasks.reserve(total);
+  for (int32_t w = 0; w < W; ++w) {
+    auto &L = lists[w];
+    int32_t run = 0;
+    for (size_t i = 0; i < L.size(); ++i) {  // publish at the end of each run of one kernel's tiles
+      run = (i > 0 && L[i - 1].node == L[i].node) ? run + 1 : 1;
+      if (i + 1 == L.size() || L[i + 1].node != L[i].node) L[i].signal = run;
+    }
+    ep.tasks.insert(ep.tasks.end(), L.begin(), L.end());
+    ep.work_off[w + 1] = static_cast<int32_t>(ep.tasks.size());
+  }
+  return ep;
+}
+
+void prepare_executor(const Dag &g, Device &d) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  ExecPlan ep = plan_executor(g, d.launch, exec_max_workers(d.device));
+  const std::vector<ExecNode> &nodes = ep.nodes;
+  const std::vector<int32_t> &pred = ep.pred;
+  const std::vector<ExecTask> &tasks = ep.tasks;
+  const std::vector<int32_t> &work_off = ep.work_off;
+  const int32_t W = static_cast<int32_t>(work_off.size()) - 1;
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t o_nodes = 0, o_succ = o_nodes + up(sizeof(ExecNode) * std::max(1, nk));
-  const size_t o_roots = o_succ + up(4 * std::max<size_t>(1, succ.size()));
-  const size_t o_ctl = o_roots + up(8 * std::max<size_t>(1, roots.size()));
-  const size_t o_pending = o_ctl + 256;
-  const size_t o_done = o_pending + up(4 * std::max(1, nk));
-  const size_t o_slots = o_done + up(4 * std::max(1, nk));
-  const size_t o_tf = o_slots + up(8 * std::max<uint64_t>(1, total));
+  const size_t o_nodes = 0, o_pred = o_nodes + up(sizeof(ExecNode) * std::max(1, nk));
+  const size_t o_tasks = o_pred + up(4 * std::max<size_t>(1, pred.size()));
+  const size_t o_off = o_tasks + up(sizeof(ExecTask) * std::max<size_t>(1, tasks.size()));
+  const size_t o_done = o_off + up(4 * size_t(W + 1));
+  const size_t o_ctl = o_done + up(4 * std::max(1, nk));
+  const size_t o_tf = o_ctl + 256;
   const size_t o_tl = o_tf + up(8 * std::max(1, nk));
   const size_t o_ts = o_tl + up(8 * std::max(1, nk));
   const size_t bytes = o_ts + 256;
@@ -191,29 +271,28 @@ void prepare_executor(const Dag &g, Device &d) {
   if (e != hipSuccess) fail(PSC_ERR_OOM, std::string("hipMalloc (executor state): ") + hipGetErrorString(e));
   char *base = static_cast<char *>(d.exec_mem);
   PSC_HIP(hipMemcpy(base + o_nodes, nodes.data(), sizeof(ExecNode) * nk, hipMemcpyHostToDevice));
-  if (!succ.empty()) PSC_HIP(hipMemcpy(base + o_succ, succ.data(), 4 * succ.size(), hipMemcpyHostToDevice));
-  if (!roots.empty()) PSC_HIP(hipMemcpy(base + o_roots, roots.data(), 8 * roots.size(), hipMemcpyHostToDevice));
+  if (!pred.empty()) PSC_HIP(hipMemcpy(base + o_pred, pred.data(), 4 * pred.size(), hipMemcpyHostToDevice));
+  PSC_HIP(hipMemcpy(base + o_tasks, tasks.data(), sizeof(ExecTask) * tasks.size(), hipMemcpyHostToDevice));
+  PSC_HIP(hipMemcpy(base + o_off, work_off.data(), 4 * work_off.size(), hipMemcpyHostToDevice));
   ExecArgs &a = d.ea;
   a.nodes = reinterpret_cast<const ExecNode *>(base + o_nodes);
-  a.succ = reinterpret_cast<const int32_t *>(base + o_succ);
-  a.roots = reinterpret_cast<const uint64_t *>(base + o_roots);
-  a.ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
-  a.pending = reinterpret_cast<uint32_t *>(base + o_pending);
+  a.pred = reinterpret_cast<const int32_t *>(base + o_pred);
+  a.tasks = reinterpret_cast<const ExecTask *>(base + o_tasks);
+  a.work_off = reinterpret_cast<const int32_t *>(base + o_off);
   a.done = reinterpret_cast<uint32_t *>(base + o_done);
-  a.slots = reinterpret_cast<uint64_t *>(base + o_slots);
+  a.ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
   a.t_first = reinterpret_cast<uint64_t *>(base + o_tf);
   a.t_last = reinterpret_cast<uint64_t *>(base + o_tl);
   a.t_start = reinterpret_cast<uint64_t *>(base + o_ts);
   a.n_nodes = nk;
-  a.n_roots = static_cast<int32_t>(roots.size());
-  a.total_tasks = static_cast<uint32_t>(total);
-  a.max_spin = 200000u;
-  d.exec_workers = static_cast<int>(std::min<uint64_t>(total, uint64_t(exec_max_workers(d.device))));
+  a.n_workers = W;
   PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
   *d.h_err = 0;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
     d.clock_mhz = khz / 1000.0;
+  // one wait may last 5 s of device time (the clock runs at clock_mhz)
+  a.max_wait = uint64_t(5.0e6 * d.clock_mhz);
 }
 
 }  // namespace
@@ -448,8 +527,8 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_H2D) do_copy(cd[o], s0);
     PSC_HIP(launch_exec_reset(d.ea, s0));
-    PSC_HIP(launch_exec(d.ea, d.exec_workers, s0));
-    PSC_HIP(hipMemcpyAsync(d.h_err, d.ea.ctl + 2, 4, hipMemcpyDeviceToHost, s0));
+    PSC_HIP(launch_exec(d.ea, s0));
+    PSC_HIP(hipMemcpyAsync(d.h_err, d.ea.ctl, 4, hipMemcpyDeviceToHost, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
     PSC_HIP(hipEventRecord(d.end, s0));
@@ -485,7 +564,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   d.have_marks = d.marks != nullptr || s.plan.device;
   if (s.plan.device && *d.h_err)
     fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) +
-                          "): a queue wait or a worker loop exceeded its bound");
+                          "): a wait for a predecessor kernel exceeded its bound");
   if (timed && s.plan.device) {
     const int32_t nk = d.ea.n_nodes;
     std::vector<uint64_t> tf(nk), tl(nk);
@@ -586,6 +665,36 @@ void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_
     if (log_us) log_us[i] = float(std::log(double(t[o].end_us) - double(t[o].start_us)));
     ++i;
   }
+}
+
+// Host-only: the device executor's task lists for `workers` workgroups, from launches built on a
+// stand-in arena address (never dereferenced).
+void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t cap, int32_t *n_tasks,
+                  int32_t *work_off) {
+  const Dag &g = s.dag->g;
+  Device d;
+  d.base.assign(g.bufs.size(), nullptr);
+  uintptr_t at = uintptr_t(1) << 32;
+  for (size_t b = 0; b < g.bufs.size(); ++b) {
+    const Buffer &x = g.bufs[b];
+    if (x.parent >= 0) continue;
+    d.base[b] = reinterpret_cast<char *>(at);
+    at += (size_t(x.rows) * x.cols * elem_size(x.dtype) + 255) & ~size_t(255);
+  }
+  std::vector<Launch> launch(g.kers.size());
+  for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, d, int32_t(k), launch[k]);
+  const ExecPlan ep = plan_executor(g, launch, workers);
+  *n_tasks = static_cast<int32_t>(ep.tasks.size());
+  if (!tasks && !work_off) return;
+  if (cap < *n_tasks) fail(PSC_ERR_ARG, "capacity too small");
+  if (tasks)
+    for (size_t i = 0; i < ep.tasks.size(); ++i) {
+      tasks[3 * i] = ep.tasks[i].node;
+      tasks[3 * i + 1] = ep.tasks[i].tile;
+      tasks[3 * i + 2] = ep.tasks[i].signal;
+    }
+  if (work_off)  // workgroups beyond the task count get empty lists
+    for (int32_t w = 0; w <= workers; ++w) work_off[w] = ep.work_off[std::min<size_t>(w, ep.work_off.size() - 1)];
 }
 
 void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n) {

@@ -12,6 +12,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -520,6 +521,104 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
     const float v = ((red[e] + red[TM * TN + e]) + red[2 * TM * TN + e]) + red[3 * TM * TN + e];
     if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * v);
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Skinny GEMM tile for few output tiles and a long K: a 16 x TN output tile (TN = 16 * FN), K cut
+// into four contiguous ranges, one per wavefront.  Operands go straight from global memory into
+// matrix-core registers: per k step each lane reads one vector of its A row (E consecutive k: 4
+// FP32 or 8 BF16) and, for each 16-column block, the same k of its B column (coalesced across the
+// 16 lanes that share those k).  The sum over k is order-free, so in FP32 the 16 k of a step are
+// assigned k = 4 * (l / 16) + e over the four products e, identically for A and B.  G steps of
+// loads are issued together before their products (one memory latency per group instead of one
+// per step); there is no LDS traffic and no barrier inside the K loop.  The four partial tiles are
+// added through LDS in a fixed order.
+// ---------------------------------------------------------------------------------------------
+template <int FN>
+constexpr int gemm_direct_smem() {
+  return 4 * 16 * 16 * FN * 4;
+}
+
+template <int FN, bool BF16, bool VEC, bool OUT_BF16>
+__device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, unsigned char *smem) {
+  constexpr int TN = 16 * FN;
+  constexpr int E = BF16 ? 8 : 4;     // consecutive k per lane per step
+  constexpr int STEP = 4 * E;         // k per step
+  constexpr int G = 8 / FN;           // steps per load group
+  using T = typename std::conditional<BF16, uint16_t, float>::type;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
+  const int m0 = tm * 16, n0 = tn * TN;
+  const int row = m0 + (lane & 15);
+  const int kl = E * (lane >> 4);
+  const int kq = ((p.K + 3) / 4 + STEP - 1) / STEP * STEP;
+  const int kb = min(p.K, w * kq), ke = min(p.K, kb + kq);
+  const int steps = (ke - kb + STEP - 1) / STEP;
+  const T *A = static_cast<const T *>(p.A);
+  const T *B = static_cast<const T *>(p.B);
+  const bool row_ok = row < p.M;
+  const T *arow = A + int64_t(row_ok ? row : 0) * p.lda;
+
+  floatx4 acc[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  T ra[G][E], rb[G][FN][E];
+  for (int s0 = 0; s0 < steps; s0 += G) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k = kb + (s0 + g) * STEP + kl;
+      if (VEC && row_ok && k + E <= ke) {
+        if constexpr (BF16) {
+          const uint4 v = *reinterpret_cast<const uint4 *>(arow + k);
+          memcpy(ra[g], &v, 16);
+        } else {
+          const float4 v = *reinterpret_cast<const float4 *>(arow + k);
+          memcpy(ra[g], &v, 16);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) ra[g][e] = (row_ok && k + e < ke) ? arow[k + e] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = n0 + 16 * j + (lane & 15);
+        const bool col_ok = col < p.N;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          rb[g][j][e] = (col_ok && k + e < ke) ? B[int64_t(k + e) * p.ldb + col] : T(0);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if constexpr (BF16) {
+        bf16x8 a, b;
+        memcpy(&a, ra[g], 16);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          memcpy(&b, rb[g][j], 16);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[g][e], rb[g][j][e], acc[j], 0, 0, 0);
+      }
+    }
+  }
+  float *red = reinterpret_cast<float *>(smem);
+#pragma unroll
+  for (int j = 0; j < FN; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w * 16 * TN + ((lane >> 4) * 4 + r) * TN + j * 16 + (lane & 15)] = acc[j][r];
+  __syncthreads();
+  for (int e = tid; e < 16 * TN; e += 256) {
+    const int orow = m0 + e / TN, col = n0 + e % TN;
+    const float v = ((red[e] + red[16 * TN + e]) + red[2 * 16 * TN + e]) + red[3 * 16 * TN + e];
+    if (orow < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(orow) * p.ldc + col, p.alpha * v);
+  }
+  __syncthreads();  // the LDS may be reused by the caller's next tile
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -253,7 +253,7 @@ def test_classify_default_component_is_whole_dag():
 
 def test_tile_cache_roundtrip():
     n = psc.psc_gemm_tile_count()
-    assert n == 13
+    assert n == 16   # automatic (0) + 5 large + 7 LDS K-split + 3 direct K-split
     psc.psc_tile_cache_clear()
     assert psc.psc_tile_cache_get(512, 64, 512, "f32", "f32") == 0
     psc.psc_tile_cache_set(512, 64, 512, "f32", "f32", 9)
@@ -314,3 +314,76 @@ def test_eft_spreads_work_over_every_stream():
     assert len({stream_of[f"L0H{h}_k"] for h in range(4)}) == 4
     ok, errs, _ = validator.check_schedule(spec, exp)
     assert ok, errs
+
+
+@pytest.mark.parametrize("name,spec,workers", [
+    ("mha512", workloads.mha_spec(512, 512, 8), 256),
+    ("mha_bf16_2x", workloads.mha_spec(200, 128, 4, layers=2, gemm_dtype="bf16"), 37),
+    ("batch", workloads.batch_spec([5, 130, 64, 1], d=64, heads=2, layers=2), 256),
+    ("random", workloads.random_dag_spec(5, n_nodes=(30, 60), dim=(8, 300)), 16),
+    ("forkjoin", workloads.forkjoin_spec(256), 3),
+])
+def test_device_executor_plan_cannot_deadlock(name, spec, workers):
+    """The PSC_DEVICE task lists: every tile of every kernel exactly once, published exactly once
+    (signals of a kernel add up to its tile count, each at the end of a run of its tiles), and the
+    wait-for relation -- list order within a workgroup plus 'a kernel's tasks wait for all tasks of
+    its predecessors' -- is acyclic, which with all workgroups resident means every wait ends."""
+    import numpy as np
+    dag = psc.build_dag(spec)
+    s = psc.psc_schedule(dag, "device")
+    lists = psc.psc_sched_device_tasks(s, workers)
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(dag)
+    nk = len(spec["kernels"])
+    tiles = {}
+    for L in lists:
+        for (k, t, _) in L:
+            tiles.setdefault(k, []).append(t)
+    assert sorted(tiles) == list(range(nk))
+    ntiles = {k: len(v) for k, v in tiles.items()}
+    for k, v in tiles.items():
+        assert sorted(v) == list(range(len(v))), k
+    signalled = {k: 0 for k in range(nk)}
+    for L in lists:
+        for i, (k, t, sig) in enumerate(L):
+            last_of_run = i + 1 == len(L) or L[i + 1][0] != k
+            assert (sig > 0) == last_of_run
+            if sig:
+                run = 1
+                while i - run >= 0 and L[i - run][0] == k:
+                    run += 1
+                assert sig == run
+                signalled[k] += sig
+    assert signalled == ntiles
+    # wait-for graph on kernel "stages": a task of kernel k at list position i waits for every task
+    # of k's predecessors and for the task before it in its list.  Acyclic iff a topological order
+    # of all tasks exists; check with Kahn's algorithm over tasks.
+    by = {b["name"]: b for b in spec["buffers"]}
+    preds = {k: set() for k in range(nk)}
+    for (src, _, dst, _) in spec["edges"]:
+        preds[dst].add(src)
+    ids = {}
+    for w, L in enumerate(lists):
+        for i, (k, t, _) in enumerate(L):
+            ids[(k, t)] = (w, i)
+    indeg = {}
+    succ = {}
+    for w, L in enumerate(lists):
+        for i, (k, t, _) in enumerate(L):
+            deps = [(L[i - 1][0], L[i - 1][1])] if i else []
+            for p in preds[k]:
+                deps += [(p, tt) for tt in range(ntiles[p])]
+            indeg[(k, t)] = len(deps)
+            for d in deps:
+                succ.setdefault(d, []).append((k, t))
+    queue = [x for x, d in indeg.items() if d == 0]
+    seen = 0
+    while queue:
+        x = queue.pop()
+        seen += 1
+        for y in succ.get(x, []):
+            indeg[y] -= 1
+            if indeg[y] == 0:
+                queue.append(y)
+    assert seen == len(indeg), "wait-for cycle"
+    assert len([L for L in lists if L]) == min(workers, len(indeg))

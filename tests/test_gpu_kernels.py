@@ -19,7 +19,7 @@ def _run(spec, inputs, **kw):
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
-@pytest.mark.parametrize("tile", list(range(13)))
+@pytest.mark.parametrize("tile", list(range(psc.psc_gemm_tile_count())))
 def test_gemm_f32(m, n, k, tile):
     print(f"gemm f32 {m}x{n}x{k} tile {tile}", flush=True)
     spec = one_kernel_spec("gemm", [(m, k), (k, n), (m, n)], ["f32"] * 3, alpha=0.5, tile=tile)
@@ -32,7 +32,7 @@ def test_gemm_f32(m, n, k, tile):
 
 
 @pytest.mark.parametrize("m,n,k", [(64, 64, 64), (130, 250, 97), (512, 512, 512)])
-@pytest.mark.parametrize("tile", [0, 1, 3, 6, 9, 12])
+@pytest.mark.parametrize("tile", [0, 1, 3, 6, 9, 12, 13, 14, 15])
 def test_gemm_f32_ternary_exact(m, n, k, tile):
     g = np.random.default_rng(3)
     spec = one_kernel_spec("gemm", [(m, k), (k, n), (m, n)], ["f32"] * 3, tile=tile)
@@ -42,7 +42,7 @@ def test_gemm_f32_ternary_exact(m, n, k, tile):
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES + [(1024, 64, 1024), (1024, 1024, 64)])
-@pytest.mark.parametrize("tile", list(range(13)))
+@pytest.mark.parametrize("tile", list(range(psc.psc_gemm_tile_count())))
 @pytest.mark.parametrize("cdt", ["f32", "bf16"])
 def test_gemm_bf16(m, n, k, tile, cdt):
     print(f"gemm bf16 {m}x{n}x{k} tile {tile} out {cdt}", flush=True)
