@@ -67,13 +67,13 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
 
 template <int FN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_f32_direct_kernel(GemmArgs p) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN, false>()];
   gemm_direct_tile<FN, false, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_bf16_direct_kernel(GemmArgs p) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN, true>()];
   gemm_direct_tile<FN, true, VEC, OUT_BF16>(p, blockIdx.x, smem);
 }
 

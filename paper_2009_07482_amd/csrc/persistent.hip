@@ -159,6 +159,7 @@ __device__ __forceinline__ bool wait_preds(const ExecArgs &a, const ExecNode &nd
       if (__hip_atomic_load(&a.ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
       if (wall_clock64() - t0 > a.max_wait) {
         __hip_atomic_fetch_or(&a.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.host_err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return false;
       }
       __builtin_amdgcn_s_sleep(1);

@@ -41,6 +41,7 @@ struct ExecArgs {
   const int32_t *work_off; // workgroup w runs tasks[work_off[w] .. work_off[w + 1])
   uint32_t *done;          // per kernel: tiles completed
   uint32_t *ctl;           // [0] error flags: 1 = a wait exceeded its bound
+  uint32_t *host_err;      // page-locked host word: set to 1 by any workgroup that stops early
   uint64_t *t_first;       // per kernel: device clock when its first tile started
   uint64_t *t_last;        // per kernel: device clock when its last tile finished
   uint64_t *t_start;       // device clock at reset

@@ -288,6 +288,7 @@ void prepare_executor(const Dag &g, Device &d) {
   a.n_workers = W;
   PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
   *d.h_err = 0;
+  a.host_err = d.h_err;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
     d.clock_mhz = khz / 1000.0;
@@ -526,9 +527,9 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     PSC_HIP(hipEventRecord(d.start, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_H2D) do_copy(cd[o], s0);
+    *d.h_err = 0;  // the previous run has completed: psc_run waits for its end
     PSC_HIP(launch_exec_reset(d.ea, s0));
     PSC_HIP(launch_exec(d.ea, s0));
-    PSC_HIP(hipMemcpyAsync(d.h_err, d.ea.ctl, 4, hipMemcpyDeviceToHost, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
     PSC_HIP(hipEventRecord(d.end, s0));

@@ -525,18 +525,41 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
 
 // ---------------------------------------------------------------------------------------------
 // Skinny GEMM tile for few output tiles and a long K: a 16 x TN output tile (TN = 16 * FN), K cut
-// into four contiguous ranges, one per wavefront.  Operands go straight from global memory into
-// matrix-core registers: per k step each lane reads one vector of its A row (E consecutive k: 4
-// FP32 or 8 BF16) and, for each 16-column block, the same k of its B column (coalesced across the
-// 16 lanes that share those k).  The sum over k is order-free, so in FP32 the 16 k of a step are
-// assigned k = 4 * (l / 16) + e over the four products e, identically for A and B.  G steps of
-// loads are issued together before their products (one memory latency per group instead of one
-// per step); there is no LDS traffic and no barrier inside the K loop.  The four partial tiles are
-// added through LDS in a fixed order.
+// into four contiguous ranges, one per wavefront; no barrier inside the K loop.  Per k step each
+// lane reads one vector of its A row (E consecutive k: 4 FP32 or 8 BF16) straight into its
+// matrix-core register.  B (row-major, k-major rows) must reach each lane as E consecutive k of
+// one column:
+//   FP32: each lane reads the 4 k of its column directly (coalesced across the 16 lanes that
+//         share those k); the sum over k is order-free, so the 16 k of a step are assigned
+//         k = 4 * (l / 16) + e over the four products e, identically for A and B.
+//   BF16: lanes read 16-byte runs of two consecutive B rows (k, k + 1) and write them, paired,
+//         into a k-contiguous copy in the wavefront's own LDS region, from which each lane reads
+//         its 8 k with one 16-byte LDS read.
+// G steps of loads are issued together before their products (one memory latency per group
+// instead of one per step).  The four partial tiles are added through LDS in a fixed order.
 // ---------------------------------------------------------------------------------------------
 template <int FN>
+constexpr int gemm_direct_bkp() {  // BF16: LDS pitch (bf16 elements) of one k-contiguous column
+  return 32 + 8;
+}
+template <int FN, bool BF16>
 constexpr int gemm_direct_smem() {
-  return 4 * 16 * 16 * FN * 4;
+  constexpr int red = 4 * 16 * 16 * FN * 4;
+  constexpr int stage = BF16 ? 4 * (8 / FN) * 16 * FN * gemm_direct_bkp<FN>() * 2 : 0;  // 4 waves x G x TN x pitch
+  return red > stage ? red : stage;
+}
+
+// Eight consecutive bf16 at p[0..8), element e only if ok_e(e), packed into one uint4.
+template <typename F>
+__device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = ok_e(2 * q) ? uint32_t(p[2 * q]) : 0u;
+    const uint32_t hi = ok_e(2 * q + 1) ? uint32_t(p[2 * q + 1]) : 0u;
+    w[q] = lo | (hi << 16);
+  }
+  return uint4{w[0], w[1], w[2], w[3]};
 }
 
 template <int FN, bool BF16, bool VEC, bool OUT_BF16>
@@ -545,6 +568,8 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
   constexpr int E = BF16 ? 8 : 4;     // consecutive k per lane per step
   constexpr int STEP = 4 * E;         // k per step
   constexpr int G = 8 / FN;           // steps per load group
+  constexpr int KP = gemm_direct_bkp<FN>();
+  constexpr int UB = (16 * (TN / 8) + 63) / 64;  // BF16: (k-pair, 8-column) units per lane per step
   using T = typename std::conditional<BF16, uint16_t, float>::type;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
@@ -558,55 +583,102 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
   const T *B = static_cast<const T *>(p.B);
   const bool row_ok = row < p.M;
   const T *arow = A + int64_t(row_ok ? row : 0) * p.lda;
+  uint16_t *Bt = reinterpret_cast<uint16_t *>(smem) + w * G * TN * KP;  // BF16: this wave's staging
 
   floatx4 acc[FN];
 #pragma unroll
   for (int j = 0; j < FN; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  T ra[G][E], rb[G][FN][E];
+  uint4 ra[G];                                           // A: E consecutive k (16 bytes)
+  float rbf[BF16 ? 1 : G][BF16 ? 1 : FN][E];             // FP32 B: the lane's column, E k
+  uint4 rb0[BF16 ? G : 1][UB], rb1[BF16 ? G : 1][UB];    // BF16 B: rows k and k + 1, 8 columns
   for (int s0 = 0; s0 < steps; s0 += G) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int k = kb + (s0 + g) * STEP + kl;
       if (VEC && row_ok && k + E <= ke) {
-        if constexpr (BF16) {
-          const uint4 v = *reinterpret_cast<const uint4 *>(arow + k);
-          memcpy(ra[g], &v, 16);
-        } else {
-          const float4 v = *reinterpret_cast<const float4 *>(arow + k);
-          memcpy(ra[g], &v, 16);
+        ra[g] = *reinterpret_cast<const uint4 *>(arow + k);
+      } else if constexpr (BF16) {
+        ra[g] = pack8_guarded(reinterpret_cast<const uint16_t *>(arow) + k, [&](int e) { return row_ok && k + e < ke; });
+      } else {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (row_ok && k + e < ke) ? reinterpret_cast<const float *>(arow)[k + e] : 0.f;
+        memcpy(&ra[g], v, 16);
+      }
+      if constexpr (BF16) {
+        const int ks = kb + (s0 + g) * STEP;
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int unit = lane + 64 * u, kp = unit / (TN / 8), c = n0 + (unit % (TN / 8)) * 8;
+          const int k0 = ks + 2 * kp;
+          const bool uok = unit < 16 * (TN / 8);
+          const uint16_t *b0 = reinterpret_cast<const uint16_t *>(B) + int64_t(k0) * p.ldb + c;
+          if (uok && VEC && k0 + 1 < ke && c + 7 < p.N) {
+            rb0[g][u] = *reinterpret_cast<const uint4 *>(b0);
+            rb1[g][u] = *reinterpret_cast<const uint4 *>(b0 + p.ldb);
+          } else {
+            rb0[g][u] = pack8_guarded(b0, [&](int e) { return uok && k0 < ke && c + e < p.N; });
+            rb1[g][u] = pack8_guarded(b0 + p.ldb, [&](int e) { return uok && k0 + 1 < ke && c + e < p.N; });
+          }
         }
       } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) ra[g][e] = (row_ok && k + e < ke) ? arow[k + e] : T(0);
-      }
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int col = n0 + 16 * j + (lane & 15);
-        const bool col_ok = col < p.N;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          rb[g][j][e] = (col_ok && k + e < ke) ? B[int64_t(k + e) * p.ldb + col] : T(0);
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if constexpr (BF16) {
-        bf16x8 a, b;
-        memcpy(&a, ra[g], 16);
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-          memcpy(&b, rb[g][j], 16);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+          const int col = n0 + 16 * j + (lane & 15);
+          const bool col_ok = col < p.N;
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            rbf[g][j][e] = (col_ok && k + e < ke) ? reinterpret_cast<const float *>(B)[int64_t(k + e) * p.ldb + col] : 0.f;
         }
-      } else {
+      }
+    }
+    if constexpr (BF16) {
+      // stage the group's B into this wave's LDS as k-contiguous columns, (k, k+1) per 32-bit write
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int unit = lane + 64 * u, kp = unit / (TN / 8), c = (unit % (TN / 8)) * 8;
+          if (unit < 16 * (TN / 8)) {
+            const uint32_t lo[4] = {rb0[g][u].x, rb0[g][u].y, rb0[g][u].z, rb0[g][u].w};
+            const uint32_t hi[4] = {rb1[g][u].x, rb1[g][u].y, rb1[g][u].z, rb1[g][u].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {  // columns c + 2q (low halves) and c + 2q + 1 (high halves)
+              *reinterpret_cast<uint32_t *>(&Bt[(g * TN + c + 2 * q) * KP + 2 * kp]) =
+                  (lo[q] & 0xffffu) | (hi[q] << 16);
+              *reinterpret_cast<uint32_t *>(&Bt[(g * TN + c + 2 * q + 1) * KP + 2 * kp]) =
+                  (lo[q] >> 16) | (hi[q] & 0xffff0000u);
+            }
+          }
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        bf16x8 av, bv;
+        memcpy(&av, &ra[g], 16);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          bv = *reinterpret_cast<const bf16x8 *>(&Bt[(g * TN + j * 16 + (lane & 15)) * KP + kl]);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int e = 0; e < E; ++e)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[g][e], rb[g][j][e], acc[j], 0, 0, 0);
-      }
+          for (int j = 0; j < FN; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float((&ra[g].x)[e]), rbf[g][j][e], acc[j], 0, 0, 0);
     }
   }
+  __syncthreads();  // all waves done with their staging before the LDS holds partial sums
   float *red = reinterpret_cast<float *>(smem);
 #pragma unroll
   for (int j = 0; j < FN; ++j)
