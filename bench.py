@@ -12,6 +12,8 @@ of Sec. V (each head's kernels one task component, components on 4 HIP streams, 
 enqueued by its own host thread).  GEMM tiles are chosen by the autotuner first (--no-tune: size
 heuristic).
 
+--config kernels: standalone softmax / transpose / add against HBM bandwidth and GEMMs against the
+matrix-core peak, at large sizes.
 --config batch64: 64 instances of log-uniform length, 6 layers, BF16 (21,888 kernels), inferences/s
 and per-instance latency p50/p99, eager streams vs one hipGraph, untuned vs autotuned.
 
@@ -47,6 +49,11 @@ def parse():
     p.add_argument("--kernel-profile", choices=["dominant", "executor"], default=None,
                    help="launch sequence for rocprofv3 counter runs (no timing line): the dominant "
                         "kernel of the stream schedule, or the device executor, then a calibration copy")
+    p.add_argument("--schedule", choices=["auto", "streams", "device"], default="auto",
+                   help="fine-grained schedule reported: the faster of the two (auto) or a fixed one")
+    p.add_argument("--profile-tile", type=int, default=0,
+                   help="with --kernel-profile: GEMM tile of the shape --profile-shape (0 = autotune)")
+    p.add_argument("--profile-shape", default="512x64x512", help="MxNxK pinned by --profile-tile")
     a = p.parse_args()
     big = a.config in ("mha1024x12", "batch64")
     if a.steps is None:
@@ -203,6 +210,15 @@ def kernel_profile(a):
         psc.psc_autotune_dag(d0, iters=20)
         psc.psc_dag_destroy(d0)
     info = {"config": a.config, "target": a.kernel_profile, "source_digest": source_digest()}
+    if a.profile_tile:
+        # every counter pass must profile the same kernel instance: pin the tile of every GEMM
+        # shape whose autotuned choice would otherwise vary from run to run
+        by = {b["name"]: b for b in spec["buffers"]}
+        for k in spec["kernels"]:
+            if k["kind"] == "gemm":
+                A_, B_, C_ = by[k["inputs"][0]], by[k["inputs"][1]], by[k["outputs"][0]]
+                if (A_["rows"], B_["cols"], A_["cols"]) == tuple(int(v) for v in a.profile_shape.split("x")):
+                    psc.psc_tile_cache_set(A_["rows"], B_["cols"], A_["cols"], A_["dtype"], C_["dtype"], a.profile_tile)
     if a.kernel_profile == "executor":
         r = psc.SpecRunner(spec, "device")
         r.set_inputs(inp)
@@ -238,7 +254,7 @@ def kernel_profile(a):
     c.run()
     psc.psc_kernel_time(c.sched, 0, 20)
     c.close()
-    info["calibration"] = {"kernel": f"transpose {CAL_N}x{CAL_N} f32", "match": "transpose_kernel",
+    info["calibration"] = {"kernel": f"transpose {CAL_N}x{CAL_N} f32", "match": "transpose",
                            "grid": (CAL_N // 64) * (CAL_N // 64), "read_bytes": CAL_N * CAL_N * 4,
                            "write_bytes": CAL_N * CAL_N * 4, "launches": 20}
     print(json.dumps(info), flush=True)
@@ -279,6 +295,101 @@ def executor_roofline(spec, r):
             "timing": "median of the timed steps, HIP events around the executor's reset and main kernels",
             "traffic_note": "bytes of the whole DAG's data movement inside the one kernel"} | \
         {"traffic": stored_traffic("exec_kernel (whole DAG, one launch)", None)}
+
+
+def environment():
+    import paper_2009_07482_amd as psc
+    env = {"device": psc.psc_device_info(0)}
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            env["rocm"] = fh.read().strip()
+    except OSError:
+        pass
+    return env
+
+
+def dag_bound_us(spec):
+    """Whole-DAG lower bound with every kernel at its roofline and no overlap lost: GEMM FLOPs at
+    the matrix-core peak of their operand type plus the other kernels' bytes at HBM bandwidth."""
+    t = 0.0
+    for k in range(len(spec["kernels"])):
+        _, work, bound, dt = kernel_class(spec, k)
+        t += work / (PEAK["mfma_bf16"] if dt == "bf16" else PEAK["mfma_f32"]) if bound == "mfma" else work / PEAK["hbm"]
+    return t * 1e6
+
+
+def one_kernel(kind, shapes, dtypes, tile=0, alpha=1.0):
+    names = ["A", "B"][: len(shapes) - 1] + ["C"]
+    bufs = [{"name": n, "dtype": d, "rows": r, "cols": c, "view_of": None, "row_off": 0, "col_off": 0}
+            for n, (r, c), d in zip(names, shapes, dtypes)]
+    ker = {"name": "k", "kind": kind, "inputs": names[:-1], "outputs": ["C"], "alpha": alpha, "tile": tile}
+    return {"buffers": bufs, "kernels": [ker], "edges": [], "component": [0]}
+
+
+def kernels_main(a):
+    """Standalone kernel rates at sizes large enough to reach the hardware's asymptotes: row
+    softmax and transpose against HBM bandwidth (algorithmic bytes: input and output once), GEMMs
+    against the matrix-core peak (2MNK).  Each kernel: device-resident operands, the mean of
+    back-to-back launches timed with HIP events on its stream; GEMM tiles autotuned."""
+    import paper_2009_07482_amd as psc
+    es = {"f32": 4, "bf16": 2}
+    cases = [("softmax", (65536, 1024), "f32", "f32"), ("softmax", (32768, 2048), "f32", "bf16"),
+             ("softmax", (65536, 1024), "bf16", "bf16"), ("transpose", (16384, 16384), "f32", "f32"),
+             ("transpose", (16384, 16384), "bf16", "bf16"), ("add", (16384, 16384), "f32", "f32"),
+             ("gemm", (4096, 4096, 4096), "bf16", "f32"), ("gemm", (8192, 8192, 8192), "bf16", "bf16"),
+             ("gemm", (4096, 4096, 4096), "f32", "f32"), ("gemm", (1024, 64, 1024), "bf16", "bf16"),
+             ("gemm", (512, 64, 512), "f32", "f32")]
+    out = []
+    for kind, shp, idt, odt in cases:
+        if kind == "gemm":
+            m, n, k = shp
+            tile = 0
+            if not a.no_tune and m * n * k <= 1e10:
+                tile, _, _ = psc.psc_autotune_gemm(m, n, k, idt, odt, iters=20)
+            elif not a.no_tune:
+                # large shapes: only the large-tile kernels are candidates (the K-split ones are
+                # for few output tiles and would take seconds each here)
+                best = None
+                for t in (1, 2, 4, 5, 16):
+                    rr = psc.SpecRunner(one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt], tile=t), "coarse")
+                    psc.psc_sched_prepare(rr.sched)
+                    psc.psc_kernel_time(rr.sched, 0, 1)
+                    u = psc.psc_kernel_time(rr.sched, 0, 3)
+                    rr.close()
+                    print(f"#   tile {t}: {u:.1f} us", file=sys.stderr, flush=True)
+                    if best is None or u < best[1]:
+                        best = (t, u)
+                tile = best[0]
+            spec = one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt], tile=tile)
+            work, unit, peak = 2.0 * m * n * k, "TFLOP/s", PEAK["mfma_bf16"] if idt == "bf16" else PEAK["mfma_f32"]
+            label = f"gemm {m}x{n}x{k} {idt}->{odt}"
+        else:
+            r_, c_ = shp
+            if kind == "transpose":
+                spec = one_kernel(kind, [(r_, c_), (c_, r_)], [idt, odt])
+                work = r_ * c_ * (es[idt] + es[odt])
+            elif kind == "add":
+                spec = one_kernel(kind, [(r_, c_), (r_, c_), (r_, c_)], [idt, idt, odt])
+                work = r_ * c_ * (2 * es[idt] + es[odt])
+            else:
+                spec = one_kernel(kind, [(r_, c_), (r_, c_)], [idt, odt])
+                work = r_ * c_ * (es[idt] + es[odt])
+            unit, peak = "GB/s", PEAK["hbm"]
+            label = f"{kind} {r_}x{c_} {idt}->{odt}"
+        r = psc.SpecRunner(spec, "coarse")
+        psc.psc_sched_prepare(r.sched)
+        big = work > 1e11
+        psc.psc_kernel_time(r.sched, 0, 3)
+        us = psc.psc_kernel_time(r.sched, 0, 10 if big else 100)
+        rate = work / (us * 1e-6)
+        row = {"kernel": label, "avg_us": us, "achieved": rate / (1e12 if unit == "TFLOP/s" else 1e9),
+               "unit": unit, "peak": peak / (1e12 if unit == "TFLOP/s" else 1e9), "frac": rate / peak}
+        if kind == "gemm":
+            row["tile"] = psc.psc_sched_kernel_tile(r.sched, 0)
+        r.close()
+        out.append(row)
+        print(f"# {json.dumps(row)}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "standalone kernel rates vs roofline", "kernels": out}), flush=True)
 
 
 def batch_main(a):
@@ -398,6 +509,9 @@ def main():
     if a.config == "batch64":
         batch_main(a)
         return
+    if a.config == "kernels":
+        kernels_main(a)
+        return
     if a.kernel_profile:
         kernel_profile(a)
         return
@@ -448,7 +562,10 @@ def main():
         print(f"# {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
 
     # the fine-grained schedule: the faster of the best stream schedule and the device executor
-    best_fine = min(("fine_streams", "device"), key=lambda k: res[k]["ms_per_step"])
+    if a.schedule == "auto":
+        best_fine = min(("fine_streams", "device"), key=lambda k: res[k]["ms_per_step"])
+    else:
+        best_fine = "fine_streams" if a.schedule == "streams" else "device"
     res["fine"] = res[best_fine]
     if best_fine == "device":
         roof = executor_roofline(spec, res["device"])
@@ -486,7 +603,10 @@ def main():
         "makespan_with_copies_ms": {k: v["makespan_with_copies_ms"] for k, v in res.items()},
         "fine_vs_coarse_speedup": res["coarse"]["ms_per_step"] / fine["ms_per_step"],
         "fine_streams_mean_ops_in_flight": concurrency,
+        "dag_bound_us": dag_bound_us(spec),
+        "makespan_over_dag_bound": fine["makespan_ms_median"] * 1e3 / dag_bound_us(spec),
         "roofline": roof,
+        "environment": environment(),
     }
     for r in runners.values():
         r.close()

@@ -291,6 +291,12 @@ psc_status psc_host_alloc(size_t bytes, void **out);
 /* [GPU] Frees memory from psc_host_alloc.  NULL is ignored. */
 psc_status psc_host_free(void *ptr);
 
+/* [GPU] Properties of `device` for reports: its name and architecture (NUL-terminated, truncated
+ * to cap bytes each; either may be NULL), compute units, peak engine clock in MHz and device
+ * memory in bytes (any output may be NULL). */
+psc_status psc_device_info(int32_t device, char *name, int32_t name_cap, char *arch, int32_t arch_cap,
+                           int32_t *compute_units, int32_t *clock_mhz, int64_t *memory_bytes);
+
 /* [GPU] Waits until all work the library enqueued on `device` has finished (hipDeviceSynchronize). */
 psc_status psc_device_sync(int32_t device);
 

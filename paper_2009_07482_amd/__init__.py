@@ -141,6 +141,7 @@ _SIGS = {
     "psc_mlp_train": [_P, C.c_void_p, C.c_void_p, _I64, C.POINTER(psc_mlp_train_opts), C.c_void_p],
     "psc_cost_predict": [_P, C.c_void_p, _I64, C.c_void_p],
     "psc_kernel_features": [_P, _I, _I, C.c_void_p],
+    "psc_device_info": [_I, C.c_char_p, _I, C.c_char_p, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I64)],
     "psc_sched_device_tasks": [_P, _I, C.c_void_p, _I, C.POINTER(_I), C.c_void_p],
     "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
@@ -305,6 +306,14 @@ def psc_sched_op_times(sched):
     buf = (psc_op_time * max(1, n.value))()
     _check(_lib.psc_sched_op_times(sched, buf, n.value, C.byref(n)))
     return [(t.op, t.stream, t.start_us, t.end_us) for t in buf[:n.value]]
+
+
+def psc_device_info(device=0):
+    name, arch = C.create_string_buffer(256), C.create_string_buffer(64)
+    cus, clk, mem = _I(), _I(), _I64()
+    _check(_lib.psc_device_info(int(device), name, 256, arch, 64, C.byref(cus), C.byref(clk), C.byref(mem)))
+    return {"name": name.value.decode(), "arch": arch.value.decode(), "compute_units": cus.value,
+            "clock_mhz": clk.value, "memory_gib": mem.value / 2 ** 30}
 
 
 def psc_sched_device_tasks(sched, workers):

@@ -30,6 +30,8 @@ float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
 void host_free(void *p);
 void device_sync(int device);
+void device_info(int device, char *name, int name_cap, char *arch, int arch_cap, int *cus, int *clock_mhz,
+                 int64_t *mem);
 int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, float *best_us, float *us_per_tile,
                   int cap);
 int sched_kernel_tile(const psc_sched &s, int32_t kernel);
@@ -317,6 +319,14 @@ psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t 
   return guard([&] {
     need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
     psc::op_times(*sched, out, cap, n);
+  });
+}
+
+psc_status psc_device_info(int32_t device, char *name, int32_t name_cap, char *arch, int32_t arch_cap,
+                           int32_t *compute_units, int32_t *clock_mhz, int64_t *memory_bytes) {
+  return guard([&] {
+    need(device >= 0, PSC_ERR_ARG, "negative device");
+    psc::device_info(device, name, name_cap, arch, arch_cap, compute_units, clock_mhz, memory_bytes);
   });
 }
 

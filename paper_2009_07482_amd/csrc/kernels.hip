@@ -44,37 +44,43 @@ size_t tile_cache_size() {
 template <int BM, int BN, int BK, int WM, int WN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_f32_smem<BM, BN, BK>()];
-  gemm_f32_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_f32_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_smem<BM, BN, BK>()];
-  gemm_bf16_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_bf16_tile<BM, BN, BK, WM, WN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int TM, int TN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_f32_splitk_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_f32_splitk_smem<TM, TN>()];
-  gemm_f32_splitk_tile<TM, TN, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_f32_splitk_tile<TM, TN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int TM, int TN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_splitk_smem<TM, TN>()];
-  gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
+}
+
+template <bool VEC, bool OUT_BF16>
+__global__ __launch_bounds__(256) void gemm_bf16_big_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_big_smem()];
+  gemm_bf16_big_tile<VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_f32_direct_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN, false>()];
-  gemm_direct_tile<FN, false, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_direct_tile<FN, false, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
 __global__ __launch_bounds__(256) void gemm_bf16_direct_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_direct_smem<FN, true>()];
-  gemm_direct_tile<FN, true, VEC, OUT_BF16>(p, blockIdx.x, smem);
+  gemm_direct_tile<FN, true, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16>
@@ -89,9 +95,20 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransArgs p) {
   transpose_tile<T>(p, blockIdx.x, smem);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_vec_kernel(TransArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[64 * 65 * sizeof(T)];
+  transpose_tile_vec<T>(p, blockIdx.x, smem);
+}
+
 template <bool IN_BF16, bool OUT_BF16>
 __global__ __launch_bounds__(256) void add_kernel(AddArgs p) {
   add_block<IN_BF16, OUT_BF16>(p, blockIdx.x);
+}
+
+template <bool IN_BF16, bool OUT_BF16>
+__global__ __launch_bounds__(256) void add_vec_kernel(AddArgs p) {
+  add_block_vec<IN_BF16, OUT_BF16>(p, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -112,13 +129,15 @@ struct TileCfg {
   bool splitk;  // K split across the block's four wavefronts
 };
 // 1..5: large tiles; 6..12: K split over the wavefronts, operands through LDS; 13..15: K split
-// over the wavefronts, operands read directly into matrix-core registers (16-row tiles).
+// over the wavefronts, operands read directly into matrix-core registers (16-row tiles);
+// 16: 256 x 256 BF16 tile with double-buffered LDS (for FP32 operands it means tile 1).
 
 // GEMM tile configurations (index = psc_kernel_params.tile; 0 = automatic)
 constexpr TileCfg kTiles[] = {{0, 0, false},     {128, 128, false}, {64, 64, false},  {32, 32, false},
                               {128, 64, false},  {64, 128, false},  {64, 64, true},   {32, 64, true},
                               {64, 32, true},    {32, 32, true},    {16, 32, true},   {32, 16, true},
-                              {16, 16, true},    {16, 16, true},    {16, 32, true},   {16, 64, true}};
+                              {16, 16, true},    {16, 16, true},    {16, 32, true},   {16, 64, true},
+                              {256, 256, false}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 #define PSC_VO(KERNEL, ...)                                                                     \
@@ -161,6 +180,8 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 13: return PSC_VO(gemm_bf16_direct_kernel, 1);
       case 14: return PSC_VO(gemm_bf16_direct_kernel, 2);
       case 15: return PSC_VO(gemm_bf16_direct_kernel, 4);
+      case 16: return (vec ? (obf ? (const void *)&gemm_bf16_big_kernel<true, true> : (const void *)&gemm_bf16_big_kernel<true, false>)
+                           : (obf ? (const void *)&gemm_bf16_big_kernel<false, true> : (const void *)&gemm_bf16_big_kernel<false, false>));
     }
   }
   return nullptr;
@@ -205,6 +226,7 @@ int gemm_auto_tile(int M, int N, int K, int dtype) {
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
+  if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 256 tile exists for BF16 operands only
   const int bm = kTiles[tile].bm, bn = kTiles[tile].bn;
   a.tiles_n = (a.N + bn - 1) / bn;
   const int tiles_m = (a.M + bm - 1) / bm;
@@ -256,7 +278,12 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype) {
 }
 
 bool make_transpose(Launch &L, TransArgs a, int dtype) {
-  L.func = dtype == 1 ? (const void *)&transpose_kernel<uint16_t> : (const void *)&transpose_kernel<float>;
+  const int64_t v = dtype == 1 ? 8 : 4;  // elements per 16-byte vector
+  const bool vec = aligned16(a.A) && aligned16(a.B) && a.lda % v == 0 && a.ldb % v == 0;
+  if (vec)
+    L.func = dtype == 1 ? (const void *)&transpose_vec_kernel<uint16_t> : (const void *)&transpose_vec_kernel<float>;
+  else
+    L.func = dtype == 1 ? (const void *)&transpose_kernel<uint16_t> : (const void *)&transpose_kernel<float>;
   L.grid = dim3(unsigned(int64_t((a.R + 63) / 64) * ((a.C + 63) / 64)), 1, 1);
   L.block = dim3(256, 1, 1);
   L.shmem = 0;
@@ -267,9 +294,17 @@ bool make_transpose(Launch &L, TransArgs a, int dtype) {
 
 bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype) {
   const bool ib = in_dtype == 1, ob = out_dtype == 1;
-  L.func = ib ? (ob ? (const void *)&add_kernel<true, true> : (const void *)&add_kernel<true, false>)
-              : (ob ? (const void *)&add_kernel<false, true> : (const void *)&add_kernel<false, false>);
-  L.grid = dim3(unsigned(int64_t((a.C + 255) / 256) * a.R), 1, 1);
+  const bool vec = aligned16(a.A) && aligned16(a.B) && aligned16(a.Cp) && a.lda % 8 == 0 && a.ldb % 8 == 0 &&
+                   a.ldc % 8 == 0;
+  if (vec) {
+    L.func = ib ? (ob ? (const void *)&add_vec_kernel<true, true> : (const void *)&add_vec_kernel<true, false>)
+                : (ob ? (const void *)&add_vec_kernel<false, true> : (const void *)&add_vec_kernel<false, false>);
+    L.grid = dim3(unsigned(int64_t((a.C + 2047) / 2048) * a.R), 1, 1);
+  } else {
+    L.func = ib ? (ob ? (const void *)&add_kernel<true, true> : (const void *)&add_kernel<true, false>)
+                : (ob ? (const void *)&add_kernel<false, true> : (const void *)&add_kernel<false, false>);
+    L.grid = dim3(unsigned(int64_t((a.C + 255) / 256) * a.R), 1, 1);
+  }
   L.block = dim3(256, 1, 1);
   L.shmem = 0;
   L.empty = a.R == 0 || a.C == 0;

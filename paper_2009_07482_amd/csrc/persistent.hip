@@ -244,7 +244,7 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       // nearest executor tile configuration to the standalone choice
       int cfg;
       switch (tile) {
-        case 1: case 2: case 4: case 5: cfg = 2; break;
+        case 1: case 2: case 4: case 5: case 16: cfg = 2; break;
         case 3: cfg = 3; break;
         case 6: case 7: case 8: case 9: cfg = 9; break;
         case 10: case 11: cfg = 10; break;

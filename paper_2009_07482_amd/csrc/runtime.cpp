@@ -732,6 +732,22 @@ void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n
   for (int32_t c = 0; c < nc; ++c) done_us[c] = float(done[c]);
 }
 
+void device_info(int device, char *name, int name_cap, char *arch, int arch_cap, int *cus, int *clock_mhz,
+                 int64_t *mem) {
+  hipDeviceProp_t pr{};
+  PSC_HIP(hipGetDeviceProperties(&pr, device));
+  auto put = [](char *dst, int cap, const char *src) {
+    if (!dst || cap <= 0) return;
+    std::strncpy(dst, src, size_t(cap - 1));
+    dst[cap - 1] = 0;
+  };
+  put(name, name_cap, pr.name);
+  put(arch, arch_cap, pr.gcnArchName);
+  if (cus) *cus = pr.multiProcessorCount;
+  if (clock_mhz) *clock_mhz = pr.clockRate / 1000;
+  if (mem) *mem = int64_t(pr.totalGlobalMem);
+}
+
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) {
   if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
   const Dag &g = s.dag->g;

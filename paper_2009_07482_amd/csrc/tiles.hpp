@@ -46,6 +46,20 @@ __device__ __forceinline__ void store_elem(void *p, int64_t i, float v) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// XCD-aware tile order.  The GPU deals workgroups round robin over its 8 XCDs (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  Giving every XCD a contiguous range of the row-major
+// tile order keeps the tiles that share an A row panel (consecutive tile indices) on one XCD, so
+// the panel is fetched from HBM once instead of once per XCD.  A bijection of [0, n): correct for
+// any XCD count; only the locality assumes 8.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int X = 8;
+  const int per = n / X, rem = n % X;
+  const int x = b % X, i = b / X;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------------------------------------
 // GEMM, C = alpha * A * B.  Block tile BM x BN, K step BK, each wavefront a WM x WN sub-tile made
 // of 16 x 16 matrix-core blocks.  Operand tiles are staged through LDS with padded pitches so that
 // the per-lane fragment reads hit distinct banks.
@@ -523,6 +537,137 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
   }
 }
 
+// Eight consecutive bf16 at p[0..8), element e only if ok_e(e), packed into one uint4.
+template <typename F>
+__device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = ok_e(2 * q) ? uint32_t(p[2 * q]) : 0u;
+    const uint32_t hi = ok_e(2 * q + 1) ? uint32_t(p[2 * q + 1]) : 0u;
+    w[q] = lo | (hi << 16);
+  }
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// ---------------------------------------------------------------------------------------------
+// Large BF16 GEMM tile: 256 x 256 outputs per block, K step 64, four wavefronts each owning a
+// 128 x 128 sub-tile (8 x 8 blocks of v_mfma_f32_16x16x32_bf16, 256 accumulators per lane).  The
+// larger wavefront tile halves the LDS bytes read per product against a 64 x 64 one, which keeps
+// the kernel matrix-core bound rather than LDS bound.  Two LDS buffers alternate: while the
+// products of step s read one, step s+1's operands (already in registers, loaded from global
+// memory during step s's products) are written to the other, so each step needs one barrier.
+// A is staged as As[m][k], B transposed as Bt[n][k] with (k, k+1) pairs in 32-bit writes, both
+// with a padded pitch (KP = 72 bf16) so the 16-byte fragment reads spread over the banks.
+// ---------------------------------------------------------------------------------------------
+constexpr int gemm_bf16_big_smem() { return 2 * (256 + 256) * 72 * 2; }
+
+template <bool VEC, bool OUT_BF16>
+__device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, unsigned char *smem) {
+  constexpr int BM = 256, BN = 256, BK = 64, KP = 72, FM = 8, FN = 8, NT = 256;
+  constexpr int NA = BM * (BK / 8) / NT;          // 8 uint4 of A per thread
+  constexpr int NB = (BK / 2) * (BN / 8) / NT;    // 4 (k, k+1) x 8-column units of B per thread
+  uint16_t *const buf0 = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *const buf1 = buf0 + (BM + BN) * KP;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const uint16_t *A = static_cast<const uint16_t *>(p.A);
+  const uint16_t *B = static_cast<const uint16_t *>(p.B);
+
+  uint4 ra[NA], rb0[NB], rb1[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
+      const int gr = m0 + r, gc = k0 + c;
+      if (VEC && gr < p.M && gc + 7 < p.K) {
+        ra[j] = *reinterpret_cast<const uint4 *>(A + int64_t(gr) * p.lda + gc);
+      } else {
+        ra[j] = pack8_guarded(A + int64_t(gr < p.M ? gr : 0) * p.lda + gc,
+                              [&](int e) { return gr < p.M && gc + e < p.K; });
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
+      const int gk = k0 + 2 * kp, gc = n0 + c;
+      const uint16_t *b0 = B + int64_t(gk < p.K ? gk : 0) * p.ldb + gc;
+      if (VEC && gk + 1 < p.K && gc + 7 < p.N) {
+        rb0[j] = *reinterpret_cast<const uint4 *>(b0);
+        rb1[j] = *reinterpret_cast<const uint4 *>(b0 + p.ldb);
+      } else {
+        rb0[j] = pack8_guarded(b0, [&](int e) { return gk < p.K && gc + e < p.N; });
+        const uint16_t *b1 = B + int64_t(gk + 1 < p.K ? gk + 1 : 0) * p.ldb + gc;
+        rb1[j] = pack8_guarded(b1, [&](int e) { return gk + 1 < p.K && gc + e < p.N; });
+      }
+    }
+  };
+  auto store = [&](uint16_t *buf) {
+    uint16_t *As = buf, *Bt = buf + BM * KP;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
+      *reinterpret_cast<uint4 *>(&As[r * KP + c]) = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
+      const uint32_t lo[4] = {rb0[j].x, rb0[j].y, rb0[j].z, rb0[j].w};
+      const uint32_t hi[4] = {rb1[j].x, rb1[j].y, rb1[j].z, rb1[j].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        *reinterpret_cast<uint32_t *>(&Bt[(c + 2 * q) * KP + 2 * kp]) = (lo[q] & 0xffffu) | (hi[q] << 16);
+        *reinterpret_cast<uint32_t *>(&Bt[(c + 2 * q + 1) * KP + 2 * kp]) = (lo[q] >> 16) | (hi[q] & 0xffff0000u);
+      }
+    }
+  };
+
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int steps = (p.K + BK - 1) / BK;
+  load(0);
+  store(buf0);
+  __syncthreads();
+  for (int s = 0; s < steps; ++s) {
+    const uint16_t *As = (s & 1) ? buf1 : buf0;
+    const uint16_t *Bt = As + BM * KP;
+    if (s + 1 < steps) load((s + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      const int kq = kk + 8 * (lane >> 4);
+      bf16x8 b[FN];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bt[(wn * 128 + j * 16 + (lane & 15)) * KP + kq]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {  // one A fragment at a time: fewer live registers
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(wm * 128 + i * 16 + (lane & 15)) * KP + kq]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (s + 1 < steps) store((s & 1) ? buf0 : buf1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * 128 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 128 + i * 16 + (lane >> 4) * 4 + r;
+        if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Skinny GEMM tile for few output tiles and a long K: a 16 x TN output tile (TN = 16 * FN), K cut
 // into four contiguous ranges, one per wavefront; no barrier inside the K loop.  Per k step each
@@ -549,18 +694,6 @@ constexpr int gemm_direct_smem() {
   return red > stage ? red : stage;
 }
 
-// Eight consecutive bf16 at p[0..8), element e only if ok_e(e), packed into one uint4.
-template <typename F>
-__device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
-  uint32_t w[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t lo = ok_e(2 * q) ? uint32_t(p[2 * q]) : 0u;
-    const uint32_t hi = ok_e(2 * q + 1) ? uint32_t(p[2 * q + 1]) : 0u;
-    w[q] = lo | (hi << 16);
-  }
-  return uint4{w[0], w[1], w[2], w[3]};
-}
 
 template <int FN, bool BF16, bool VEC, bool OUT_BF16>
 __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, unsigned char *smem) {
@@ -810,6 +943,65 @@ __device__ __forceinline__ void transpose_tile(const TransArgs &p, int bid, unsi
   }
 }
 
+// Vector variant for aligned operands (base addresses 16-byte aligned, leading dimensions
+// multiples of V = 16 / sizeof(T)): 16-byte global reads along A's rows and 16-byte global writes
+// along B's rows; elements move through the padded LDS tile one by one.  Vectors that cross the
+// matrix edge fall back to element accesses.
+template <typename T>
+__device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, unsigned char *smem) {
+  constexpr int V = 16 / int(sizeof(T));   // elements per vector
+  constexpr int VPR = 64 / V;              // vectors per 64-element row
+  constexpr int RPP = 256 / VPR;           // rows per pass
+  constexpr int PASSES = 64 / RPP;
+  T(*tile)[65] = reinterpret_cast<T(*)[65]>(smem);
+  const int tiles_c = (p.C + 63) / 64, tiles_r = (p.R + 63) / 64;
+  // diagonal order: consecutive workgroups take different tile rows as well as different tile
+  // columns, so the ones in flight together write different column ranges of B (with a
+  // power-of-two leading dimension, equal column ranges of many rows share HBM channels)
+  const int tc = bid % tiles_c, tr = (bid / tiles_c + tc) % tiles_r;
+  const int vx = threadIdx.x % VPR, vy = threadIdx.x / VPR;
+  const T *A = static_cast<const T *>(p.A);
+  T *B = static_cast<T *>(p.B);
+  uint4 v[PASSES];
+#pragma unroll
+  for (int i = 0; i < PASSES; ++i) {
+    const int r = tr * 64 + vy + RPP * i, c = tc * 64 + vx * V;
+    if (r < p.R && c + V <= p.C) {
+      v[i] = *reinterpret_cast<const uint4 *>(A + int64_t(r) * p.lda + c);
+    } else {
+      T e[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) e[j] = (r < p.R && c + j < p.C) ? A[int64_t(r) * p.lda + c + j] : T(0);
+      memcpy(&v[i], e, 16);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PASSES; ++i) {
+    T e[V];
+    memcpy(e, &v[i], 16);
+#pragma unroll
+    for (int j = 0; j < V; ++j) tile[vy + RPP * i][vx * V + j] = e[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PASSES; ++i) {
+    // output row orow = input column; V consecutive output columns = V consecutive input rows
+    const int oc = vy + RPP * i, orow = tc * 64 + oc, ocol = tr * 64 + vx * V;
+    T e[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) e[j] = tile[vx * V + j][oc];
+    if (orow < p.C && ocol + V <= p.R) {
+      uint4 w;
+      memcpy(&w, e, 16);
+      *reinterpret_cast<uint4 *>(B + int64_t(orow) * p.ldb + ocol) = w;
+    } else if (orow < p.C) {
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (ocol + j < p.R) B[int64_t(orow) * p.ldb + ocol + j] = e[j];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Element-wise add in FP32: grid (ceil(C/256), R), one element per thread.
 // ---------------------------------------------------------------------------------------------
@@ -822,6 +1014,56 @@ __device__ __forceinline__ void add_block(const AddArgs &p, int bid) {
   const float a = load_elem<IN_BF16>(p.A, int64_t(r) * p.lda + c);
   const float b = load_elem<IN_BF16>(p.B, int64_t(r) * p.ldb + c);
   store_elem<OUT_BF16>(p.Cp, int64_t(r) * p.ldc + c, a + b);
+}
+
+// Vector variant (operands 16-byte aligned, leading dimensions multiples of 8): each thread adds
+// 8 consecutive elements per row of a 2048-column chunk; a workgroup covers one chunk of one row.
+// The FP32 sum of two values is rounded once to the output type, as in add_block.
+template <bool IN_BF16, bool OUT_BF16>
+__device__ __forceinline__ void add_block_vec(const AddArgs &p, int bid) {
+  const int nbx = (p.C + 2047) / 2048;
+  const int c = (bid % nbx) * 2048 + threadIdx.x * 8;
+  const int r = bid / nbx;
+  if (c >= p.C || r >= p.R) return;
+  const int64_t ia = int64_t(r) * p.lda + c, ib = int64_t(r) * p.ldb + c, ic = int64_t(r) * p.ldc + c;
+  float a[8], b[8];
+  if (c + 8 <= p.C) {
+    if constexpr (IN_BF16) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p.A) + ia);
+      const uint4 y = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p.B) + ib);
+      const uint32_t xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[2 * q] = __uint_as_float(xs[q] << 16);
+        a[2 * q + 1] = __uint_as_float(xs[q] & 0xffff0000u);
+        b[2 * q] = __uint_as_float(ys[q] << 16);
+        b[2 * q + 1] = __uint_as_float(ys[q] & 0xffff0000u);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float4 x = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.A) + ia + 4 * h);
+        const float4 y = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.B) + ib + 4 * h);
+        a[4 * h] = x.x; a[4 * h + 1] = x.y; a[4 * h + 2] = x.z; a[4 * h + 3] = x.w;
+        b[4 * h] = y.x; b[4 * h + 1] = y.y; b[4 * h + 2] = y.z; b[4 * h + 3] = y.w;
+      }
+    }
+    if constexpr (OUT_BF16) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        w[q] = uint32_t(f32_to_bf16(a[2 * q] + b[2 * q])) | (uint32_t(f32_to_bf16(a[2 * q + 1] + b[2 * q + 1])) << 16);
+      *reinterpret_cast<uint4 *>(static_cast<uint16_t *>(p.Cp) + ic) = uint4{w[0], w[1], w[2], w[3]};
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        *reinterpret_cast<float4 *>(static_cast<float *>(p.Cp) + ic + 4 * h) =
+            make_float4(a[4 * h] + b[4 * h], a[4 * h + 1] + b[4 * h + 1], a[4 * h + 2] + b[4 * h + 2], a[4 * h + 3] + b[4 * h + 3]);
+    }
+  } else {
+    for (int e = 0; c + e < p.C; ++e)
+      store_elem<OUT_BF16>(p.Cp, ic + e, load_elem<IN_BF16>(p.A, ia + e) + load_elem<IN_BF16>(p.B, ib + e));
+  }
 }
 
 }  // namespace psc

@@ -67,7 +67,8 @@ def test_gemm_bf16_ternary_exact():
     np.testing.assert_array_equal(_run(spec, inp), oracle_outputs(spec, inp)["C"])
 
 
-@pytest.mark.parametrize("r,c", [(1, 1), (64, 64), (512, 64), (64, 512), (130, 257), (1024, 64), (0, 5)])
+@pytest.mark.parametrize("r,c", [(1, 1), (64, 64), (512, 64), (64, 512), (130, 257), (1024, 64), (0, 5),
+                                 (136, 264), (72, 200), (8, 4104)])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_transpose_exact(r, c, dt):
     spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt])
@@ -106,8 +107,8 @@ def test_softmax_shift_invariance_and_constant_rows():
     np.testing.assert_array_equal(_run(spec, {"A": x}), want)
 
 
-@pytest.mark.parametrize("r,c", [(1, 1), (256, 256), (129, 1000), (0, 3)])
-@pytest.mark.parametrize("idt,odt", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "f32")])
+@pytest.mark.parametrize("r,c", [(1, 1), (256, 256), (129, 1000), (0, 3), (3, 2056), (7, 4104)])
+@pytest.mark.parametrize("idt,odt", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "f32"), ("f32", "bf16")])
 def test_add_exact(r, c, idt, odt):
     spec = one_kernel_spec("add", [(r, c), (r, c), (r, c)], [idt, idt, odt])
     a, b = uniform(10, (r, c)), uniform(11, (r, c))
@@ -117,3 +118,27 @@ def test_add_exact(r, c, idt, odt):
     s = a.astype(np.float64) + b.astype(np.float64)
     want = round_bf16(round_f32(s)) if odt == "bf16" else round_f32(s)
     np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_add_and_transpose_on_column_windows(dt):
+    """Kernels on views: aligned leading dimension, ragged width (the vector kernels' tail path)."""
+    R, W, C = 5, 1008, 1001
+    bufs = [{"name": "A", "dtype": dt, "rows": R, "cols": W, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "B", "dtype": dt, "rows": R, "cols": W, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "Cr", "dtype": dt, "rows": R, "cols": W, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "Av", "dtype": dt, "rows": R, "cols": C, "view_of": "A", "row_off": 0, "col_off": 0},
+            {"name": "Bv", "dtype": dt, "rows": R, "cols": C, "view_of": "B", "row_off": 0, "col_off": 0},
+            {"name": "Cv", "dtype": dt, "rows": R, "cols": C, "view_of": "Cr", "row_off": 0, "col_off": 0},
+            {"name": "T", "dtype": dt, "rows": C, "cols": R, "view_of": None, "row_off": 0, "col_off": 0}]
+    kers = [{"name": "add", "kind": "add", "inputs": ["Av", "Bv"], "outputs": ["Cv"], "alpha": 1.0, "tile": 0},
+            {"name": "tr", "kind": "transpose", "inputs": ["Av"], "outputs": ["T"], "alpha": 1.0, "tile": 0}]
+    spec = {"buffers": bufs, "kernels": kers, "edges": [], "component": [0, 0]}
+    a, b = uniform(12, (R, W)), uniform(13, (R, W))
+    out, _ = psc.run_spec(spec, {"A": a, "B": b})
+    if dt == "bf16":
+        a, b = round_bf16(a), round_bf16(b)
+    s_ = a[:, :C].astype(np.float64) + b[:, :C].astype(np.float64)
+    want = round_bf16(round_f32(s_)) if dt == "bf16" else round_f32(s_)
+    np.testing.assert_array_equal(out["Cv"], want)
+    np.testing.assert_array_equal(out["T"], a[:, :C].T.astype(np.float64))
