@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--graph", action="store_true", help="also time the schedule launched as one hipGraph")
     p.add_argument("--variants", action="store_true", help="also time other fine-grained variants")
     p.add_argument("--kernel-iters", type=int, default=200)
+    p.add_argument("--heldout", type=int, default=20, help="--config costmodel: held-out DAGs")
+    p.add_argument("--epochs", type=int, default=300, help="--config costmodel: training passes")
+    p.add_argument("--dump-samples", default=None, help="--config costmodel: save the samples (.npz)")
     p.add_argument("--kernel-profile", choices=["dominant", "executor"], default=None,
                    help="launch sequence for rocprofv3 counter runs (no timing line): the dominant "
                         "kernel of the stream schedule, or the device executor, then a calibration copy")
@@ -392,6 +395,76 @@ def kernels_main(a):
     print(json.dumps({"metric": "standalone kernel rates vs roofline", "kernels": out}), flush=True)
 
 
+def costmodel_main(a):
+    """Learned cost model at full scale: ~20k op timings recorded by the runtime from random
+    layered DAGs (50-500 nodes, widths 1-16, dims 64-4096, FP32 or BF16), the MLP trained on the
+    GPU, then on held-out DAGs: op-time error of the MLP vs the roofline heuristic, and the
+    measured makespan of EFT schedules (4 streams) under each model, beside round robin."""
+    import paper_2009_07482_amd as psc
+    import workloads
+    from paper_2009_07482_amd import costmodel
+    t0 = time.perf_counter()
+    xs, ts = [], []
+    seed = 0
+    while sum(len(t) for t in ts) < 20000 and seed < 200:
+        spec = workloads.random_dag_spec(seed)
+        es = {"f32": 4, "bf16": 2}
+        nbytes = sum(b["rows"] * b["cols"] * es[b["dtype"]] for b in spec["buffers"] if b["view_of"] is None)
+        # every 8th DAG of moderate size also times its host copies
+        inp = workloads.random_dag_inputs(seed, spec) if seed % 8 == 0 and nbytes < 1.5e9 else None
+        x, t = costmodel.record_samples(spec, inp, n_streams=(1, 2, 4, 8)[seed % 4], runs=1)
+        xs.append(x)
+        ts.append(t)
+        seed += 1
+        if seed % 10 == 0:
+            print(f"# recorded {sum(len(t) for t in ts)} samples from {seed} DAGs "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    X, T = np.concatenate(xs), np.concatenate(ts)
+    if a.dump_samples:
+        np.savez(a.dump_samples, X=X, T=T)
+    t1 = time.perf_counter()
+    cm = costmodel.fit(X, T, epochs=a.epochs, batch=256, lr=2e-3, seed=0)
+    train_s = time.perf_counter() - t1
+    print(f"# trained on {len(T)} samples in {train_s:.1f} s; loss {cm.losses[0]:.3f} -> {cm.losses[-1]:.3f}",
+          file=sys.stderr, flush=True)
+    held = []
+    e_mlp, e_heu = [], []
+    for hs in range(1000, 1000 + a.heldout):
+        spec = workloads.random_dag_spec(hs)
+        x, t = costmodel.record_samples(spec, None, n_streams=4, runs=1)
+        if a.dump_samples:
+            np.savez(a.dump_samples.replace(".npz", f"_heldout{hs}.npz"), X=x, T=t)
+        e_mlp.append(costmodel.mape(cm.predict_us(x), t))
+        e_heu.append(costmodel.mape(psc.psc_cost_predict(x), t))
+        ms = {}
+        for name, kw in (("rr", dict(mapper="rr")), ("eft_heuristic", dict(mapper="eft")),
+                         ("eft_mlp", dict(mapper="eft", cost=cm.handle))):
+            r = psc.SpecRunner(spec, "fine", n_streams=4, host_threads=1, **kw)
+            psc.psc_sched_prepare(r.sched)
+            r.run(with_inputs=False, with_outputs=False)
+            mk = [r.run(with_inputs=False, with_outputs=False)["makespan_ms"] for _ in range(5)]
+            ms[name] = float(np.median(mk))
+            r.close()
+        held.append({"seed": hs, "kernels": len(spec["kernels"]), "dtype": spec["dtype"], "makespan_ms": ms,
+                     "mape_mlp": e_mlp[-1], "mape_heuristic": e_heu[-1]})
+        print(f"# held-out {hs}: {len(spec['kernels'])} kernels {spec['dtype']}: " +
+              ", ".join(f"{k} {v:.2f} ms" for k, v in ms.items()) +
+              f"; op-time MAPE mlp {e_mlp[-1]:.3f} heuristic {e_heu[-1]:.3f}", file=sys.stderr, flush=True)
+    cm.close()
+    ratio = [h["makespan_ms"]["eft_mlp"] / h["makespan_ms"]["eft_heuristic"] for h in held]
+    ratio_rr = [h["makespan_ms"]["eft_mlp"] / h["makespan_ms"]["rr"] for h in held]
+    gm = lambda v: float(np.exp(np.mean(np.log(v))))
+    line = {"metric": "learned cost model: op-time error and EFT makespan vs the roofline heuristic",
+            "training_samples": int(len(T)), "training_dags": seed, "train_seconds": train_s,
+            "loss_first_last": [float(cm.losses[0]), float(cm.losses[-1])],
+            "heldout_dags": len(held), "op_time_mape": {"mlp": float(np.mean(e_mlp)), "heuristic": float(np.mean(e_heu))},
+            "makespan_ratio_mlp_over_heuristic_geomean": gm(ratio),
+            "makespan_ratio_mlp_over_rr_geomean": gm(ratio_rr),
+            "mlp_faster_on": int(sum(r < 1.0 for r in ratio)), "per_dag": held,
+            "data": "synthetic random layered DAGs (seeded), device-resident timings plus copies on every 8th DAG"}
+    print(json.dumps(line), flush=True)
+
+
 def batch_main(a):
     """64 attention instances of log-uniform length in [64, 2048] (d = 512, 8 heads, 6 layers,
     BF16 GEMMs), one task component each, in one DAG of 21,888 kernels.  A step is one batch.
@@ -511,6 +584,9 @@ def main():
         return
     if a.config == "kernels":
         kernels_main(a)
+        return
+    if a.config == "costmodel":
+        costmodel_main(a)
         return
     if a.kernel_profile:
         kernel_profile(a)

@@ -629,6 +629,20 @@ class HostBuffer:
             pass
 
 
+class _LazyOutputs(dict):
+    """Read-back buffers made on first use (page-locked memory is only taken when needed)."""
+
+    def __init__(self, by):
+        super().__init__()
+        self._by = by
+
+    def __missing__(self, name):
+        b = self._by[name]
+        h = HostBuffer(b["rows"], b["cols"], b["dtype"])
+        self[name] = h
+        return h
+
+
 class SpecRunner:
     """A scheduled spec with page-locked host staging for its inputs and outputs."""
 
@@ -640,8 +654,7 @@ class SpecRunner:
         self.sched = psc_schedule(self.dag, policy, **opts)
         self.in_names = workloads.host_inputs_of(spec)
         self.out_names = workloads.host_outputs_of(spec)
-        self.outputs = {n: HostBuffer(self.by[n]["rows"], self.by[n]["cols"], self.by[n]["dtype"])
-                        for n in self.out_names}
+        self.outputs = _LazyOutputs(self.by)
         self.inputs = {}
 
     def set_inputs(self, inputs):
@@ -657,7 +670,7 @@ class SpecRunner:
         if with_inputs:
             out += [(n, h.ptr, h.nbytes) for n, h in self.inputs.items()]
         if with_outputs:
-            out += [(n, h.ptr, h.nbytes) for n, h in self.outputs.items()]
+            out += [(n, self.outputs[n].ptr, self.outputs[n].nbytes) for n in self.out_names]
         return out
 
     def run(self, with_inputs=True, with_outputs=True):

@@ -190,16 +190,24 @@ void check_n(int64_t n) {
 
 // fwd over the first n uploaded samples (rows idx[0..n) if idx, else 0..n)
 void launch_fwd(psc_mlp &m, const int32_t *idx, int64_t n) {
-  hipLaunchKernelGGL(mlp_fwd, dim3(blocks_for(n)), dim3(256), 0, m.stream, m.params, m.norm, m.x, idx,
-                     int32_t(n), m.z1, m.z2, m.y);
-  MLP_HIP(hipGetLastError());
+  const float *P = m.params, *norm = m.norm, *X = m.x;
+  int32_t nn = int32_t(n);
+  float *Z1 = m.z1, *Z2 = m.z2, *Y = m.y;
+  void *args[] = {&P, &norm, &X, &idx, &nn, &Z1, &Z2, &Y};
+  MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_fwd), dim3(blocks_for(n)), dim3(256), args, 0, m.stream));
 }
 
 void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const MlpTrainOpts &o, float *G) {
   launch_fwd(m, idx, n);
-  hipLaunchKernelGGL(mlp_delta, dim3(blocks_for(n)), dim3(256), 0, m.stream, m.params, m.t, idx, int32_t(n),
-                     float(2.0 / double(n)), m.z1, m.z2, m.y, m.dz1, m.dz2, m.dy);
-  MLP_HIP(hipGetLastError());
+  {
+    const float *P = m.params, *T = m.t, *Z1 = m.z1, *Z2 = m.z2, *Y = m.y;
+    int32_t nn = int32_t(n);
+    float scale = float(2.0 / double(n));
+    float *DZ1 = m.dz1, *DZ2 = m.dz2, *DY = m.dy;
+    void *args[] = {&P, &T, &idx, &nn, &scale, &Z1, &Z2, &Y, &DZ1, &DZ2, &DY};
+    MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_delta), dim3(blocks_for(n)), dim3(256), args, 0,
+                            m.stream));
+  }
   UpdateArgs a{};
   a.P = m.params;
   a.M = m.m;
@@ -224,8 +232,9 @@ void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const M
     a.c1 = float(1.0 / (1.0 - std::pow(double(o.beta1), double(m.step))));
     a.c2 = float(1.0 / (1.0 - std::pow(double(o.beta2), double(m.step))));
   }
-  hipLaunchKernelGGL(mlp_update, dim3((kMlpP + 255) / 256), dim3(256), 0, m.stream, a);
-  MLP_HIP(hipGetLastError());
+  void *uargs[] = {&a};
+  MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_update), dim3((kMlpP + 255) / 256), dim3(256), uargs, 0,
+                          m.stream));
 }
 
 double mse_of(const std::vector<float> &y, const float *t, int64_t n) {

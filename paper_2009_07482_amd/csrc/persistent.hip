@@ -323,10 +323,15 @@ hipError_t launch_exec(const ExecArgs &a, hipStream_t stream) {
 
 int exec_max_workers(int device) {
   int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)&exec_kernel, 256, 0) != hipSuccess ||
-      per_cu < 1)
+      per_cu < 1) {
+    (void)hipGetLastError();
     per_cu = 1;
+  }
   return cus * per_cu;
 }
 

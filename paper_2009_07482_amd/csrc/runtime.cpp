@@ -292,6 +292,8 @@ void prepare_executor(const Dag &g, Device &d) {
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
     d.clock_mhz = khz / 1000.0;
+  else
+    (void)hipGetLastError();  // keep the default rate; leave no sticky error behind
   // one wait may last 5 s of device time (the clock runs at clock_mhz)
   a.max_wait = uint64_t(5.0e6 * d.clock_mhz);
 }
@@ -355,6 +357,8 @@ void prepare(psc_sched &s) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d->device) == hipSuccess && khz > 0)
       d->clock_mhz = khz / 1000.0;
+    else
+      (void)hipGetLastError();
   }
   if (dev_mode) {
     prepare_executor(g, *d);
