@@ -65,10 +65,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
   gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
-template <bool VEC, bool OUT_BF16>
-__global__ __launch_bounds__(256) void gemm_bf16_big_kernel(GemmArgs p) {
+template <bool OUT_BF16>
+__global__ __launch_bounds__(512) void gemm_bf16_big_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_big_smem()];
-  gemm_bf16_big_tile<VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
+  gemm_bf16_big_tile<OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
@@ -130,7 +130,7 @@ struct TileCfg {
 };
 // 1..5: large tiles; 6..12: K split over the wavefronts, operands through LDS; 13..15: K split
 // over the wavefronts, operands read directly into matrix-core registers (16-row tiles);
-// 16: 256 x 256 BF16 tile with double-buffered LDS (for FP32 operands it means tile 1).
+// 16: 256 x 256 BF16 tile, eight wavefronts, 512 threads (for FP32 operands it means tile 1).
 
 // GEMM tile configurations (index = psc_kernel_params.tile; 0 = automatic)
 constexpr TileCfg kTiles[] = {{0, 0, false},     {128, 128, false}, {64, 64, false},  {32, 32, false},
@@ -180,8 +180,7 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 13: return PSC_VO(gemm_bf16_direct_kernel, 1);
       case 14: return PSC_VO(gemm_bf16_direct_kernel, 2);
       case 15: return PSC_VO(gemm_bf16_direct_kernel, 4);
-      case 16: return (vec ? (obf ? (const void *)&gemm_bf16_big_kernel<true, true> : (const void *)&gemm_bf16_big_kernel<true, false>)
-                           : (obf ? (const void *)&gemm_bf16_big_kernel<false, true> : (const void *)&gemm_bf16_big_kernel<false, false>));
+      case 16: return obf ? (const void *)&gemm_bf16_big_kernel<true> : (const void *)&gemm_bf16_big_kernel<false>;
     }
   }
   return nullptr;
@@ -226,7 +225,12 @@ int gemm_auto_tile(int M, int N, int K, int dtype) {
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
-  if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 256 tile exists for BF16 operands only
+  if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 128 tile exists for BF16 operands only
+  if (tile == 16) {  // whole tiles, aligned operands only
+    const bool fits = a.M % 256 == 0 && a.N % 256 == 0 && a.K % 64 == 0 && a.K > 0 && aligned16(a.A) &&
+                      aligned16(a.B) && a.lda % 8 == 0 && a.ldb % 8 == 0;
+    if (!fits) tile = 4;
+  }
   const int bm = kTiles[tile].bm, bn = kTiles[tile].bn;
   a.tiles_n = (a.N + bn - 1) / bn;
   const int tiles_m = (a.M + bm - 1) / bm;
@@ -238,7 +242,7 @@ bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (!fn) return false;
   L.func = fn;
   L.grid = dim3(unsigned(int64_t(tiles_m) * a.tiles_n), 1, 1);
-  L.block = dim3(256, 1, 1);  // every GEMM instance runs four wavefronts
+  L.block = dim3(tile == 16 ? 512 : 256, 1, 1);  // four wavefronts, eight for the 256 x 256 tile
   L.shmem = 0;
   L.empty = a.M == 0 || a.N == 0;
   L.tile = tile;

@@ -551,77 +551,67 @@ __device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Large BF16 GEMM tile: 256 x 256 outputs per block, K step 64, four wavefronts each owning a
-// 128 x 128 sub-tile (8 x 8 blocks of v_mfma_f32_16x16x32_bf16, 256 accumulators per lane).  The
-// larger wavefront tile halves the LDS bytes read per product against a 64 x 64 one, which keeps
-// the kernel matrix-core bound rather than LDS bound.  Two LDS buffers alternate: while the
-// products of step s read one, step s+1's operands (already in registers, loaded from global
-// memory during step s's products) are written to the other, so each step needs one barrier.
-// A is staged as As[m][k], B transposed as Bt[n][k] with (k, k+1) pairs in 32-bit writes, both
-// with a padded pitch (KP = 72 bf16) so the 16-byte fragment reads spread over the banks.
+// Large BF16 GEMM tile: 256 x 256 outputs per 512-thread block, K step 64, eight wavefronts
+// (2 along M x 4 along N) each owning a 128 x 64 sub-tile (8 x 4 blocks of
+// v_mfma_f32_16x16x32_bf16, 128 accumulators per lane); two wavefronts per SIMD.  The next K
+// step's operands are loaded into registers while the current step is multiplied out of LDS; two
+// LDS buffers alternate, so each step needs one barrier.  Shapes are whole tiles (no edge guards,
+// no per-load branches), every load an offset from one per-thread base pointer.  A is staged as
+// As[m][k], B transposed as Bt[n][k] with (k, k+1) pairs in 32-bit writes; the unit-to-lane order
+// of the B loads (4 lanes along n, then 16 along k) keeps those writes at most 2-way bank
+// conflicted while each 4-lane group still reads 64 contiguous bytes of a B row.
 // ---------------------------------------------------------------------------------------------
 constexpr int gemm_bf16_big_smem() { return 2 * (256 + 256) * 72 * 2; }
 
-template <bool VEC, bool OUT_BF16>
+// Requires M % 256 == 0, N % 256 == 0, K % 64 == 0, 16-byte aligned operands and leading
+// dimensions that are multiples of 8 (the launch factory checks; other shapes use tile 4).
+template <bool OUT_BF16>
 __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, unsigned char *smem) {
-  constexpr int BM = 256, BN = 256, BK = 64, KP = 72, FM = 8, FN = 8, NT = 256;
-  constexpr int NA = BM * (BK / 8) / NT;          // 8 uint4 of A per thread
-  constexpr int NB = (BK / 2) * (BN / 8) / NT;    // 4 (k, k+1) x 8-column units of B per thread
+  constexpr int BM = 256, BN = 256, BK = 64, KP = 72, FM = 8, FN = 4;
   uint16_t *const buf0 = reinterpret_cast<uint16_t *>(smem);
   uint16_t *const buf1 = buf0 + (BM + BN) * KP;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // 8 wavefronts
+  const int wm = wave >> 2, wn = wave & 3;
   const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
-  const uint16_t *A = static_cast<const uint16_t *>(p.A);
-  const uint16_t *B = static_cast<const uint16_t *>(p.B);
+  // A units: row ar + 64 j (j < 4), 8 k at ac.  B units: k pair bkp + 16 j (j < 2), 8 n at bc.
+  const int ar = tid >> 3, ac = (tid & 7) * 8;
+  const int bc = (wave * 4 + (lane & 3)) * 8, bkp = (lane >> 2) & 15;
+  const uint16_t *pa = static_cast<const uint16_t *>(p.A) + int64_t(m0 + ar) * p.lda + ac;
+  const uint16_t *pb = static_cast<const uint16_t *>(p.B) + int64_t(2 * bkp) * p.ldb + n0 + bc;
+  const int64_t a_step = int64_t(64) * p.lda, b_pair = p.ldb, b_half = int64_t(32) * p.ldb;
 
-  uint4 ra[NA], rb0[NB], rb1[NB];
-  auto load = [&](int k0) {
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // one K step in flight
+#define PSC_BIG_LOAD(k0)                                                                         \
+  do {                                                                                           \
+    const uint16_t *qa_ = pa + (k0);                                                             \
+    ra0 = *reinterpret_cast<const uint4 *>(qa_);                                                 \
+    ra1 = *reinterpret_cast<const uint4 *>(qa_ + a_step);                                        \
+    ra2 = *reinterpret_cast<const uint4 *>(qa_ + 2 * a_step);                                    \
+    ra3 = *reinterpret_cast<const uint4 *>(qa_ + 3 * a_step);                                    \
+    const uint16_t *qb_ = pb + int64_t(k0) * p.ldb;                                              \
+    rb0 = *reinterpret_cast<const uint4 *>(qb_);                                                 \
+    rb1 = *reinterpret_cast<const uint4 *>(qb_ + b_pair);                                        \
+    rb2 = *reinterpret_cast<const uint4 *>(qb_ + b_half);                                        \
+    rb3 = *reinterpret_cast<const uint4 *>(qb_ + b_half + b_pair);                               \
+  } while (0)
+  auto store_b = [&](uint16_t *Bt, int kp, uint4 lo4, uint4 hi4) {
+    const uint32_t lo[4] = {lo4.x, lo4.y, lo4.z, lo4.w};
+    const uint32_t hi[4] = {hi4.x, hi4.y, hi4.z, hi4.w};
 #pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      const int gr = m0 + r, gc = k0 + c;
-      if (VEC && gr < p.M && gc + 7 < p.K) {
-        ra[j] = *reinterpret_cast<const uint4 *>(A + int64_t(gr) * p.lda + gc);
-      } else {
-        ra[j] = pack8_guarded(A + int64_t(gr < p.M ? gr : 0) * p.lda + gc,
-                              [&](int e) { return gr < p.M && gc + e < p.K; });
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
-      const int gk = k0 + 2 * kp, gc = n0 + c;
-      const uint16_t *b0 = B + int64_t(gk < p.K ? gk : 0) * p.ldb + gc;
-      if (VEC && gk + 1 < p.K && gc + 7 < p.N) {
-        rb0[j] = *reinterpret_cast<const uint4 *>(b0);
-        rb1[j] = *reinterpret_cast<const uint4 *>(b0 + p.ldb);
-      } else {
-        rb0[j] = pack8_guarded(b0, [&](int e) { return gk < p.K && gc + e < p.N; });
-        const uint16_t *b1 = B + int64_t(gk + 1 < p.K ? gk + 1 : 0) * p.ldb + gc;
-        rb1[j] = pack8_guarded(b1, [&](int e) { return gk + 1 < p.K && gc + e < p.N; });
-      }
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint32_t *>(&Bt[(bc + 2 * q) * KP + 2 * kp]) = (lo[q] & 0xffffu) | (hi[q] << 16);
+      *reinterpret_cast<uint32_t *>(&Bt[(bc + 2 * q + 1) * KP + 2 * kp]) = (lo[q] >> 16) | (hi[q] & 0xffff0000u);
     }
   };
   auto store = [&](uint16_t *buf) {
-    uint16_t *As = buf, *Bt = buf + BM * KP;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int u = tid + NT * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
-      *reinterpret_cast<uint4 *>(&As[r * KP + c]) = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int u = tid + NT * j, kp = u / (BN / 8), c = (u % (BN / 8)) * 8;
-      const uint32_t lo[4] = {rb0[j].x, rb0[j].y, rb0[j].z, rb0[j].w};
-      const uint32_t hi[4] = {rb1[j].x, rb1[j].y, rb1[j].z, rb1[j].w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        *reinterpret_cast<uint32_t *>(&Bt[(c + 2 * q) * KP + 2 * kp]) = (lo[q] & 0xffffu) | (hi[q] << 16);
-        *reinterpret_cast<uint32_t *>(&Bt[(c + 2 * q + 1) * KP + 2 * kp]) = (lo[q] >> 16) | (hi[q] & 0xffff0000u);
-      }
-    }
+    uint16_t *As = buf + ar * KP + ac;
+    *reinterpret_cast<uint4 *>(As) = ra0;
+    *reinterpret_cast<uint4 *>(As + 64 * KP) = ra1;
+    *reinterpret_cast<uint4 *>(As + 128 * KP) = ra2;
+    *reinterpret_cast<uint4 *>(As + 192 * KP) = ra3;
+    store_b(buf + BM * KP, bkp, rb0, rb1);
+    store_b(buf + BM * KP, bkp + 16, rb2, rb3);
   };
 
   floatx4 acc[FM][FN];
@@ -629,41 +619,45 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](const uint16_t *buf) {
+    const uint16_t *As = buf + (wm * 128 + (lane & 15)) * KP + 8 * (lane >> 4);
+    const uint16_t *Bt = buf + BM * KP + (wn * 64 + (lane & 15)) * KP + 8 * (lane >> 4);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      // all fragments of this 32-deep slice first, so the LDS latency is paid once per slice
+      bf16x8 b[FN], a[FM];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(Bt + j * 16 * KP + kk);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(As + i * 16 * KP + kk);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  };
 
-  const int steps = (p.K + BK - 1) / BK;
-  load(0);
+  const int steps = p.K / BK;
+  PSC_BIG_LOAD(0);
   store(buf0);
   __syncthreads();
   for (int s = 0; s < steps; ++s) {
-    const uint16_t *As = (s & 1) ? buf1 : buf0;
-    const uint16_t *Bt = As + BM * KP;
-    if (s + 1 < steps) load((s + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 32) {
-      const int kq = kk + 8 * (lane >> 4);
-      bf16x8 b[FN];
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bt[(wn * 128 + j * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-      for (int i = 0; i < FM; ++i) {  // one A fragment at a time: fewer live registers
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(wm * 128 + i * 16 + (lane & 15)) * KP + kq]);
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
-      }
-    }
-    if (s + 1 < steps) store((s & 1) ? buf0 : buf1);
+    uint16_t *cur = (s & 1) ? buf1 : buf0, *nxt = (s & 1) ? buf0 : buf1;
+    if (s + 1 < steps) PSC_BIG_LOAD((s + 1) * BK);
+    compute(cur);
+    if (s + 1 < steps) store(nxt);
     __syncthreads();
   }
+#undef PSC_BIG_LOAD
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * 128 + j * 16 + (lane & 15);
+      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * 128 + i * 16 + (lane >> 4) * 4 + r;
-        if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
+        store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
       }
     }
 }

@@ -41,7 +41,7 @@ def test_gemm_f32_ternary_exact(m, n, k, tile):
     np.testing.assert_array_equal(got, oracle_outputs(spec, inp)["C"])
 
 
-@pytest.mark.parametrize("m,n,k", GEMM_SHAPES + [(1024, 64, 1024), (1024, 1024, 64)])
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES + [(1024, 64, 1024), (1024, 1024, 64), (512, 256, 512), (256, 256, 192), (512, 512, 320)])
 @pytest.mark.parametrize("tile", list(range(psc.psc_gemm_tile_count())))
 @pytest.mark.parametrize("cdt", ["f32", "bf16"])
 def test_gemm_bf16(m, n, k, tile, cdt):
