@@ -86,10 +86,10 @@ __device__ __forceinline__ void run_task(const ExecNode *ndp, int tile, unsigned
     case 153: gemm_direct_tile<1, false, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 154: gemm_direct_tile<1, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 155: gemm_direct_tile<1, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 158: gemm_direct_tile<2, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 159: gemm_direct_tile<2, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 162: gemm_direct_tile<4, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 163: gemm_direct_tile<4, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 158: gemm_direct_tile<2, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 159: gemm_direct_tile<2, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 162: gemm_direct_tile<4, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 163: gemm_direct_tile<4, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 210: gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 211: gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 214: gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
@@ -101,6 +101,14 @@ __device__ __forceinline__ void run_task(const ExecNode *ndp, int tile, unsigned
     case 248: gemm_bf16_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 249: gemm_bf16_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 250: gemm_bf16_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 252: gemm_direct_tile<1, true, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 253: gemm_direct_tile<1, true, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 254: gemm_direct_tile<1, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 255: gemm_direct_tile<1, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 258: gemm_direct_tile<2, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 259: gemm_direct_tile<2, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 262: gemm_direct_tile<4, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
+    case 263: gemm_direct_tile<4, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 251: gemm_bf16_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
     case 300: softmax_task<0, false, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
     case 301: softmax_task<0, false, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
@@ -232,7 +240,7 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 }  // namespace
 
-ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile) {
+ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile, int want) {
   ExecNode n{};
   switch (kind) {
     case 0: {  // GEMM
@@ -241,19 +249,29 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       if (g.M == 0 || g.N == 0) break;
       const bool vec = in_dtype == 0 ? (aligned16(g.A) && aligned16(g.B) && g.lda % 4 == 0 && g.ldb % 4 == 0)
                                      : (aligned16(g.A) && aligned16(g.B) && g.lda % 8 == 0 && g.ldb % 8 == 0);
-      // nearest executor tile configuration to the standalone choice
-      int cfg;
-      switch (tile) {
-        case 1: case 2: case 4: case 5: case 16: cfg = 2; break;
-        case 3: cfg = 3; break;
-        case 6: case 7: case 8: case 9: cfg = 9; break;
-        case 10: case 11: cfg = 10; break;
-        case 13: cfg = in_dtype == 0 ? 13 : 12; break;
-        case 14: cfg = in_dtype == 0 ? 14 : 10; break;
-        case 15: cfg = in_dtype == 0 ? 15 : 10; break;
-        default: cfg = 12; break;
+      // The executor's own tile choice: its parallelism comes from kernels running side by side,
+      // so a task should carry more work than the standalone kernels' small tiles (made to fill
+      // the GPU with one kernel).  `want` is the number of workgroups this kernel can expect
+      // (all of them divided by the kernels beside it): take the largest tile that still gives
+      // at least `want` tasks, else the smallest.  Candidates, largest first: 16 x 64 / 16 x 32 /
+      // 16 x 16 direct-load tiles for outputs at most 64 wide; 64 x 64, 32 x 32, 16 x 32 and
+      // 16 x 16 otherwise.  (`tile`, the standalone choice, is unused.)
+      (void)tile;
+      int cfg = -1;
+      if (!vec) {
+        cfg = in_dtype == 0 ? 13 : 12;
+      } else {
+        static constexpr int narrow[] = {15, 14, 13}, wide[] = {2, 3, 10, 12};
+        const int *c0 = g.N <= 64 ? narrow : wide;
+        const int nc = g.N <= 64 ? 3 : 4;
+        for (int i = 0; i < nc && cfg < 0; ++i) {
+          int bm = 16, bn = 16;
+          for (const PCfg &c : kPersistentGemm)
+            if (c.cfg == c0[i]) { bm = c.bm; bn = c.bn; }
+          const int64_t tiles = int64_t((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+          if (tiles >= want || i == nc - 1) cfg = c0[i];
+        }
       }
-      if (!vec) cfg = (in_dtype == 0 && cfg == 13) ? 13 : 12;
       int bm = 16, bn = 16;
       for (const PCfg &c : kPersistentGemm)
         if (c.cfg == cfg) { bm = c.bm; bn = c.bn; }

@@ -51,8 +51,9 @@ struct ExecArgs {
 };
 
 // Builds the executor's description of a kernel from the launch it would use standalone.
-// kind: psc_kind; dtypes: 0 = f32, 1 = bf16.
-ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile);
+// kind: psc_kind; dtypes: 0 = f32, 1 = bf16; want: workgroups the kernel can expect to use
+// (GEMM tiles are chosen to give at least that many tasks where possible).
+ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile, int want);
 
 // Launch helpers (enqueue on `stream`).  The executor runs a.n_workers workgroups, at most as
 // many as the GPU holds resident at once (a task may wait for any other workgroup's earlier task).

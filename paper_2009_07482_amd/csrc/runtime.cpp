@@ -189,11 +189,21 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   ExecPlan ep;
   ep.nodes.resize(nk);
+  // kernels beside each kernel: those at the same depth (longest path from a root)
+  std::vector<int32_t> depth(nk, 0), width;
+  for (int32_t k : g.bfs_order())
+    for (int32_t q : g.succ[k]) depth[q] = std::max(depth[q], depth[k] + 1);
+  for (int32_t k = 0; k < nk; ++k) {
+    if (depth[k] >= int32_t(width.size())) width.resize(depth[k] + 1, 0);
+    ++width[depth[k]];
+  }
+  const int32_t Wmax = std::max(1, max_workers);
   uint64_t total = 0;
   for (int32_t k = 0; k < nk; ++k) {
     const Kernel &ker = g.kers[k];
+    const int want = std::max(1, Wmax / std::max(1, width[depth[k]]));
     ep.nodes[k] = make_exec_node(ker.kind, launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
-                                 launch[k].tile);
+                                 launch[k].tile, want);
     ep.nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
     ep.nodes[k].pred_off = static_cast<int32_t>(ep.pred.size());
     ep.pred.insert(ep.pred.end(), g.pred[k].begin(), g.pred[k].end());
@@ -214,22 +224,50 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
   std::vector<int32_t> indeg(nk);
   for (int32_t k = 0; k < nk; ++k)
     if (!(indeg[k] = static_cast<int32_t>(g.pred[k].size()))) ready.push({-bl[k], k});
-  using Free = std::pair<double, int32_t>;  // (time the workgroup is free, workgroup)
+  // Tiles are placed one at a time on the workgroup predicted to finish them first.  A tile that
+  // continues its kernel's run on a workgroup costs its compute only; starting a kernel on a
+  // workgroup also costs publishing the run (a release, ~2 us) and, for a kernel with
+  // predecessors, the acquire (~2 us).  A kernel may use at most W / (kernels ready when it is
+  // placed) workgroups, so kernels that could run side by side (the heads of an attention layer,
+  // the instances of a batch) share the GPU instead of each spreading over all of it and paying
+  // a fence pair on every workgroup.
+  constexpr double kRelease = 2.1, kAcquire = 1.8;
+  std::vector<double> free_time(W, 0.0);
+  using Free = std::pair<double, int32_t>;  // (time the workgroup is free, workgroup); lazy entries
   std::priority_queue<Free, std::vector<Free>, std::greater<Free>> free_at;
   for (int32_t w = 0; w < W; ++w) free_at.push({0.0, w});
   std::vector<std::vector<ExecTask>> lists(W);
+  std::vector<int32_t> used;
   while (!ready.empty()) {
     const int32_t k = ready.top().second;
+    const int32_t cap = std::max<int32_t>(1, (W + int32_t(ready.size()) - 1) / int32_t(ready.size()));
     ready.pop();
     double rt = 0;
     for (int32_t p : g.pred[k]) rt = std::max(rt, finish[p]);
+    const double sw = kRelease + (g.pred[k].empty() ? 0.0 : kAcquire);
+    used.clear();
     for (int32_t t = 0; t < ep.nodes[k].n_tiles; ++t) {
-      const Free f = free_at.top();
-      free_at.pop();
-      const double end = std::max(f.first, rt) + cost[k];
+      // continue on the earliest-free workgroup already running this kernel ...
+      int32_t wc = -1;
+      for (int32_t w : used)
+        if (wc < 0 || free_time[w] < free_time[wc]) wc = w;
+      double end_c = wc >= 0 ? std::max(free_time[wc], rt) + cost[k] : 1e300;
+      // ... or start on the earliest-free workgroup, while under the cap
+      int32_t wn = -1;
+      double end_n = 1e300;
+      if (int32_t(used.size()) < cap) {
+        while (free_at.top().first != free_time[free_at.top().second]) free_at.pop();  // stale
+        wn = free_at.top().second;
+        end_n = std::max(free_time[wn], rt) + sw + cost[k];
+      }
+      const bool cont = end_c <= end_n;
+      const int32_t w = cont ? wc : wn;
+      const double end = cont ? end_c : end_n;
+      if (!cont) used.push_back(w);
+      free_time[w] = end;
+      free_at.push({end, w});
       finish[k] = std::max(finish[k], end);
-      free_at.push({end, f.second});
-      lists[f.second].push_back(ExecTask{k, t, 0, 0});
+      lists[w].push_back(ExecTask{k, t, 0, 0});
     }
     for (int32_t q : g.succ[k])
       if (--indeg[q] == 0) ready.push({-bl[q], q});

@@ -689,12 +689,14 @@ constexpr int gemm_direct_smem() {
 }
 
 
-template <int FN, bool BF16, bool VEC, bool OUT_BF16>
+// G: K steps per load group (default 8 / FN: bounded registers for the standalone kernels; the
+// device executor, which runs one workgroup per CU anyway, uses 8 for FP32).
+template <int FN, bool BF16, bool VEC, bool OUT_BF16, int G = 8 / FN>
 __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, unsigned char *smem) {
+  static_assert(!BF16 || G == 8 / FN, "the BF16 staging area is sized for G = 8 / FN");
   constexpr int TN = 16 * FN;
   constexpr int E = BF16 ? 8 : 4;     // consecutive k per lane per step
   constexpr int STEP = 4 * E;         // k per step
-  constexpr int G = 8 / FN;           // steps per load group
   constexpr int KP = gemm_direct_bkp<FN>();
   constexpr int UB = (16 * (TN / 8) + 63) / 64;  // BF16: (k-pair, 8-column) units per lane per step
   using T = typename std::conditional<BF16, uint16_t, float>::type;
