@@ -196,7 +196,8 @@ def source_digest():
     """Hash of the kernel sources; a stored counter profile applies only to the code it measured."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("tiles.hpp", "kernels.hip", "persistent.hip", "persistent.hpp", "kernels.hpp"):
+    # the kernels, and the runtime that plans the device executor's task lists
+    for f in ("tiles.hpp", "kernels.hip", "persistent.hip", "persistent.hpp", "kernels.hpp", "runtime.cpp"):
         with open(os.path.join(ROOT, "paper_2009_07482_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -264,12 +265,12 @@ def kernel_profile(a):
 
 
 def stored_traffic(kernel_key, tile):
-    """HBM bytes per launch from a committed counter profile of this kernel (profiles/*_pmc.md),
+    """HBM bytes per launch from a committed counter profile of this kernel (profiles/*.md),
     or None if there is none for this kernel, tile and kernel source."""
     import glob
     import re
     digest = source_digest()
-    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.md"))):
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         txt = open(f).read()
         kv = dict(re.findall(r"^- (\w+): `([^`]*)`", txt, re.M))
         if kv.get("kernel") == kernel_key and kv.get("source_digest") == digest and \
