@@ -83,10 +83,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_direct_kernel(GemmArgs p) {
   gemm_direct_tile<FN, true, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
-template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16>
+template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16, bool NT = false, int CW = 4>
 __global__ __launch_bounds__(256) void softmax_kernel(SoftmaxArgs p) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row < p.R) softmax_row<NV, VEC, IN_BF16, OUT_BF16>(p, row);
+  if (row < p.R) softmax_row<NV, VEC, IN_BF16, OUT_BF16, NT, CW>(p, row);
 }
 
 template <typename T>
@@ -95,10 +95,10 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransArgs p) {
   transpose_tile<T>(p, blockIdx.x, smem);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(256) void transpose_vec_kernel(TransArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[64 * 65 * sizeof(T)];
-  transpose_tile_vec<T>(p, blockIdx.x, smem);
+  transpose_tile_vec<T, NT>(p, blockIdx.x, smem);
 }
 
 template <bool IN_BF16, bool OUT_BF16>
@@ -106,15 +106,20 @@ __global__ __launch_bounds__(256) void add_kernel(AddArgs p) {
   add_block<IN_BF16, OUT_BF16>(p, blockIdx.x);
 }
 
-template <bool IN_BF16, bool OUT_BF16>
+template <bool IN_BF16, bool OUT_BF16, bool NT = false>
 __global__ __launch_bounds__(256) void add_vec_kernel(AddArgs p) {
-  add_block_vec<IN_BF16, OUT_BF16>(p, blockIdx.x);
+  add_block_vec<IN_BF16, OUT_BF16, NT>(p, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Launch factories
 // ---------------------------------------------------------------------------------------------
 namespace {
+
+// Softmax and transpose launches whose output is at least this large (bytes, the size of the
+// last-level cache) read and write with streaming hints: neither operand would stay cached for a
+// consumer.
+constexpr int64_t kStreamBytes = int64_t(256) << 20;
 
 template <typename Args>
 void set_args(Launch &L, const Args &a) {
@@ -260,19 +265,30 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype) {
   else if (a.C <= 512) nv = 2;
   else if (a.C <= 1024) nv = 4;
   else if (a.C <= 2048) nv = 8;
-#define PSC_SM(NV)                                                                                  \
-  (vec ? (ib ? (ob ? (const void *)&softmax_kernel<NV, true, true, true> : (const void *)&softmax_kernel<NV, true, true, false>) \
-             : (ob ? (const void *)&softmax_kernel<NV, true, false, true> : (const void *)&softmax_kernel<NV, true, false, false>)) \
-       : (ib ? (ob ? (const void *)&softmax_kernel<NV, false, true, true> : (const void *)&softmax_kernel<NV, false, true, false>) \
-             : (ob ? (const void *)&softmax_kernel<NV, false, false, true> : (const void *)&softmax_kernel<NV, false, false, false>)))
+  const bool nt = vec && nv > 0 && int64_t(a.R) * a.C * (ob ? 2 : 4) >= kStreamBytes;
+  // bf16 input in 16-byte chunks of eight where both operands allow it
+  const bool w16 = vec && ib && nv >= 2 && aligned16(a.X) && aligned16(a.Y) && a.ldx % 8 == 0 && a.ldy % 8 == 0;
+#define PSC_SMB(NV, NT, W)                                                                          \
+  (w16 ? (ob ? (const void *)&softmax_kernel<NV, true, true, true, NT, W> : (const void *)&softmax_kernel<NV, true, true, false, NT, W>) \
+       : (ob ? (const void *)&softmax_kernel<NV, true, true, true, NT> : (const void *)&softmax_kernel<NV, true, true, false, NT>))
+#define PSC_SM4(NV, NT, W)                                                                          \
+  (ib ? PSC_SMB(NV, NT, W)                                                                          \
+      : (ob ? (const void *)&softmax_kernel<NV, true, false, true, NT> : (const void *)&softmax_kernel<NV, true, false, false, NT>))
+#define PSC_SMS(NV)                                                                                 \
+  (ib ? (ob ? (const void *)&softmax_kernel<NV, false, true, true> : (const void *)&softmax_kernel<NV, false, true, false>) \
+      : (ob ? (const void *)&softmax_kernel<NV, false, false, true> : (const void *)&softmax_kernel<NV, false, false, false>))
+#define PSC_SM(NV, W) (vec ? (nt ? PSC_SM4(NV, true, W) : PSC_SM4(NV, false, W)) : PSC_SMS(NV))
   switch (nv) {
-    case 1: L.func = PSC_SM(1); break;
-    case 2: L.func = PSC_SM(2); break;
-    case 4: L.func = PSC_SM(4); break;
-    case 8: L.func = PSC_SM(8); break;
-    default: L.func = PSC_SM(0); break;
+    case 1: L.func = PSC_SM(1, 4); break;   // (no eight-wide chunks for rows of at most 256)
+    case 2: L.func = PSC_SM(2, 8); break;
+    case 4: L.func = PSC_SM(4, 8); break;
+    case 8: L.func = PSC_SM(8, 8); break;
+    default: L.func = PSC_SMS(0); break;
   }
 #undef PSC_SM
+#undef PSC_SMS
+#undef PSC_SM4
+#undef PSC_SMB
   L.grid = dim3(unsigned((a.R + 3) / 4), 1, 1);
   L.block = dim3(256, 1, 1);
   L.shmem = 0;
@@ -284,8 +300,10 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype) {
 bool make_transpose(Launch &L, TransArgs a, int dtype) {
   const int64_t v = dtype == 1 ? 8 : 4;  // elements per 16-byte vector
   const bool vec = aligned16(a.A) && aligned16(a.B) && a.lda % v == 0 && a.ldb % v == 0;
+  const bool nt = int64_t(a.R) * a.C * (dtype == 1 ? 2 : 4) >= kStreamBytes;
   if (vec)
-    L.func = dtype == 1 ? (const void *)&transpose_vec_kernel<uint16_t> : (const void *)&transpose_vec_kernel<float>;
+    L.func = dtype == 1 ? (nt ? (const void *)&transpose_vec_kernel<uint16_t, true> : (const void *)&transpose_vec_kernel<uint16_t, false>)
+                        : (nt ? (const void *)&transpose_vec_kernel<float, true> : (const void *)&transpose_vec_kernel<float, false>);
   else
     L.func = dtype == 1 ? (const void *)&transpose_kernel<uint16_t> : (const void *)&transpose_kernel<float>;
   L.grid = dim3(unsigned(int64_t((a.R + 63) / 64) * ((a.C + 63) / 64)), 1, 1);
@@ -301,6 +319,7 @@ bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype) {
   const bool vec = aligned16(a.A) && aligned16(a.B) && aligned16(a.Cp) && a.lda % 8 == 0 && a.ldb % 8 == 0 &&
                    a.ldc % 8 == 0;
   if (vec) {
+    // plain loads and stores: streaming hints measured slower for the two-input add
     L.func = ib ? (ob ? (const void *)&add_vec_kernel<true, true> : (const void *)&add_vec_kernel<true, false>)
                 : (ob ? (const void *)&add_vec_kernel<false, true> : (const void *)&add_vec_kernel<false, false>);
     L.grid = dim3(unsigned(int64_t((a.C + 2047) / 2048) * a.R), 1, 1);

@@ -20,6 +20,32 @@ namespace psc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// 16- and 8-byte global loads and stores.  NT: with the non-temporal (streaming) hint, for
+// operands far larger than the last-level cache, which are read or written once and would only
+// evict data still to be used.
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const void *src) {
+  if constexpr (NT) return __builtin_nontemporal_load(static_cast<const u32x4 *>(src));
+  else return *static_cast<const u32x4 *>(src);
+}
+template <bool NT>
+__device__ __forceinline__ u32x2 load8(const void *src) {
+  if constexpr (NT) return __builtin_nontemporal_load(static_cast<const u32x2 *>(src));
+  else return *static_cast<const u32x2 *>(src);
+}
+template <bool NT>
+__device__ __forceinline__ void store16(void *dst, u32x4 w) {
+  if constexpr (NT) __builtin_nontemporal_store(w, static_cast<u32x4 *>(dst));
+  else *static_cast<u32x4 *>(dst) = w;
+}
+template <bool NT>
+__device__ __forceinline__ void store8(void *dst, u32x2 w) {
+  if constexpr (NT) __builtin_nontemporal_store(w, static_cast<u32x2 *>(dst));
+  else *static_cast<u32x2 *>(dst) = w;
+}
 
 // ---------------------------------------------------------------------------------------------
 // bfloat16 <-> float.  A bfloat16 is the upper 16 bits of an IEEE binary32; conversion from
@@ -824,7 +850,7 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
 
 // ---------------------------------------------------------------------------------------------
 // Row softmax: one wavefront per row, four rows per 256-thread block.  NV > 0: the row is held in
-// registers as NV chunks of 4 per lane (rows up to 256*NV); NV == 0: three passes over memory.
+// registers, 4 NV values per lane (rows up to 256*NV); NV == 0: three passes over memory.
 // The max and the sum are reduced across the wavefront with butterfly shuffles, in FP32.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ float wave_max(float v) {
@@ -838,39 +864,51 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16>
+template <int NV, bool VEC, bool IN_BF16, bool OUT_BF16, bool NT = false, int CW = 4>
 __device__ __forceinline__ void softmax_row(const SoftmaxArgs &p, int row) {
   const int lane = threadIdx.x & 63;
   const int64_t xo = int64_t(row) * p.ldx, yo = int64_t(row) * p.ldy;
   const float ninf = -__builtin_huge_valf();
   if constexpr (NV > 0) {
-    float v[NV][4];
+    // NC chunks of CW consecutive elements per lane; chunk t of lane l starts at column
+    // (64 t + l) CW.  CW = 8 (bf16 input only): 16-byte loads of eight bf16 values.
+    constexpr int NC = NV * 4 / CW;
+    static_assert(CW == 4 || (CW == 8 && IN_BF16 && NV % 2 == 0), "chunk width");
+    float v[NC][CW];
     float m = ninf;
 #pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      const int c = (t * 64 + lane) * 4;
-      if (VEC && c + 3 < p.C) {
-        if constexpr (IN_BF16) {
-          const uint2 w = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(p.X) + xo + c);
+    for (int t = 0; t < NC; ++t) {
+      const int c = (t * 64 + lane) * CW;
+      if (VEC && c + CW - 1 < p.C) {
+        if constexpr (IN_BF16 && CW == 8) {
+          const u32x4 w = load16<NT>(static_cast<const uint16_t *>(p.X) + xo + c);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            v[t][2 * q] = __uint_as_float(w[q] << 16);
+            v[t][2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+          }
+        } else if constexpr (IN_BF16) {
+          const u32x2 w = load8<NT>(static_cast<const uint16_t *>(p.X) + xo + c);
           v[t][0] = __uint_as_float(w.x << 16); v[t][1] = __uint_as_float(w.x & 0xffff0000u);
           v[t][2] = __uint_as_float(w.y << 16); v[t][3] = __uint_as_float(w.y & 0xffff0000u);
         } else {
-          const float4 w = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.X) + xo + c);
-          v[t][0] = w.x; v[t][1] = w.y; v[t][2] = w.z; v[t][3] = w.w;
+          const u32x4 w = load16<NT>(static_cast<const float *>(p.X) + xo + c);
+          v[t][0] = __uint_as_float(w.x); v[t][1] = __uint_as_float(w.y);
+          v[t][2] = __uint_as_float(w.z); v[t][3] = __uint_as_float(w.w);
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[t][e] = (c + e < p.C) ? load_elem<IN_BF16>(p.X, xo + c + e) : ninf;
+        for (int e = 0; e < CW; ++e) v[t][e] = (c + e < p.C) ? load_elem<IN_BF16>(p.X, xo + c + e) : ninf;
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) m = fmaxf(m, v[t][e]);
+      for (int e = 0; e < CW; ++e) m = fmaxf(m, v[t][e]);
     }
     m = wave_max(m);
     float s = 0.f;
 #pragma unroll
-    for (int t = 0; t < NV; ++t)
+    for (int t = 0; t < NC; ++t)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < CW; ++e) {
         const float ex = (v[t][e] == ninf) ? 0.f : __expf(v[t][e] - m);
         v[t][e] = ex;
         s += ex;
@@ -878,21 +916,34 @@ __device__ __forceinline__ void softmax_row(const SoftmaxArgs &p, int row) {
     s = wave_sum(s);
     const float inv = 1.0f / s;
 #pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      const int c = (t * 64 + lane) * 4;
-      if (VEC && c + 3 < p.C) {
-        if constexpr (OUT_BF16) {
-          uint2 w;
-          w.x = uint32_t(f32_to_bf16(v[t][0] * inv)) | (uint32_t(f32_to_bf16(v[t][1] * inv)) << 16);
-          w.y = uint32_t(f32_to_bf16(v[t][2] * inv)) | (uint32_t(f32_to_bf16(v[t][3] * inv)) << 16);
-          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(p.Y) + yo + c) = w;
-        } else {
-          *reinterpret_cast<float4 *>(static_cast<float *>(p.Y) + yo + c) =
-              make_float4(v[t][0] * inv, v[t][1] * inv, v[t][2] * inv, v[t][3] * inv);
+    for (int t = 0; t < NC; ++t) {
+      const int c = (t * 64 + lane) * CW;
+      if (VEC && c + CW - 1 < p.C) {
+#pragma unroll
+        for (int h = 0; h < CW / 4; ++h) {
+          const float *q = &v[t][4 * h];
+          if constexpr (OUT_BF16 && CW == 8) {
+            if (h == 0) {
+              const float *q8 = v[t];
+              u32x4 w;
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                w[k] = uint32_t(f32_to_bf16(q8[2 * k] * inv)) | (uint32_t(f32_to_bf16(q8[2 * k + 1] * inv)) << 16);
+              store16<NT>(static_cast<uint16_t *>(p.Y) + yo + c, w);
+            }
+          } else if constexpr (OUT_BF16) {
+            const u32x2 w = {uint32_t(f32_to_bf16(q[0] * inv)) | (uint32_t(f32_to_bf16(q[1] * inv)) << 16),
+                             uint32_t(f32_to_bf16(q[2] * inv)) | (uint32_t(f32_to_bf16(q[3] * inv)) << 16)};
+            store8<NT>(static_cast<uint16_t *>(p.Y) + yo + c + 4 * h, w);
+          } else {
+            const u32x4 w = {__float_as_uint(q[0] * inv), __float_as_uint(q[1] * inv),
+                             __float_as_uint(q[2] * inv), __float_as_uint(q[3] * inv)};
+            store16<NT>(static_cast<float *>(p.Y) + yo + c + 4 * h, w);
+          }
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < CW; ++e)
           if (c + e < p.C) store_elem<OUT_BF16>(p.Y, yo + c + e, v[t][e] * inv);
       }
     }
@@ -941,29 +992,21 @@ __device__ __forceinline__ void transpose_tile(const TransArgs &p, int bid, unsi
 
 // Vector variant for aligned operands (base addresses 16-byte aligned, leading dimensions
 // multiples of V = 16 / sizeof(T)): 16-byte global reads along A's rows and 16-byte global writes
-// along B's rows; elements move through the padded LDS tile one by one.  Vectors that cross the
-// matrix edge fall back to element accesses.
-template <typename T>
-__device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, unsigned char *smem) {
-  constexpr int V = 16 / int(sizeof(T));   // elements per vector
-  constexpr int VPR = 64 / V;              // vectors per 64-element row
-  constexpr int RPP = 256 / VPR;           // rows per pass
-  constexpr int PASSES = 64 / RPP;
-  T(*tile)[65] = reinterpret_cast<T(*)[65]>(smem);
-  const int tiles_c = (p.C + 63) / 64, tiles_r = (p.R + 63) / 64;
-  // diagonal order: consecutive workgroups take different tile rows as well as different tile
-  // columns, so the ones in flight together write different column ranges of B (with a
-  // power-of-two leading dimension, equal column ranges of many rows share HBM channels)
-  const int tc = bid % tiles_c, tr = (bid / tiles_c + tc) % tiles_r;
+// along B's rows; elements move through the padded LDS tile one by one.  Tiles inside the matrix
+// take an unchecked path with all sixteen-byte loads in flight at once; edge tiles check every
+// vector and fall back to element accesses where one crosses the edge.  NT: streaming loads and
+// stores.
+template <typename T, bool CHECK, bool NT>
+__device__ __forceinline__ void transpose_vec_load(const TransArgs &p, int tr, int tc, T (*tile)[65]) {
+  constexpr int V = 16 / int(sizeof(T)), VPR = 64 / V, RPP = 256 / VPR, PASSES = 64 / RPP;
   const int vx = threadIdx.x % VPR, vy = threadIdx.x / VPR;
   const T *A = static_cast<const T *>(p.A);
-  T *B = static_cast<T *>(p.B);
-  uint4 v[PASSES];
+  u32x4 v[PASSES];
 #pragma unroll
   for (int i = 0; i < PASSES; ++i) {
     const int r = tr * 64 + vy + RPP * i, c = tc * 64 + vx * V;
-    if (r < p.R && c + V <= p.C) {
-      v[i] = *reinterpret_cast<const uint4 *>(A + int64_t(r) * p.lda + c);
+    if (!CHECK || (r < p.R && c + V <= p.C)) {
+      v[i] = load16<NT>(A + int64_t(r) * p.lda + c);
     } else {
       T e[V];
 #pragma unroll
@@ -978,7 +1021,13 @@ __device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, 
 #pragma unroll
     for (int j = 0; j < V; ++j) tile[vy + RPP * i][vx * V + j] = e[j];
   }
-  __syncthreads();
+}
+
+template <typename T, bool CHECK, bool NT>
+__device__ __forceinline__ void transpose_vec_store(const TransArgs &p, int tr, int tc, T (*tile)[65]) {
+  constexpr int V = 16 / int(sizeof(T)), VPR = 64 / V, RPP = 256 / VPR, PASSES = 64 / RPP;
+  const int vx = threadIdx.x % VPR, vy = threadIdx.x / VPR;
+  T *B = static_cast<T *>(p.B);
 #pragma unroll
   for (int i = 0; i < PASSES; ++i) {
     // output row orow = input column; V consecutive output columns = V consecutive input rows
@@ -986,15 +1035,34 @@ __device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, 
     T e[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) e[j] = tile[vx * V + j][oc];
-    if (orow < p.C && ocol + V <= p.R) {
-      uint4 w;
+    if (!CHECK || (orow < p.C && ocol + V <= p.R)) {
+      u32x4 w;
       memcpy(&w, e, 16);
-      *reinterpret_cast<uint4 *>(B + int64_t(orow) * p.ldb + ocol) = w;
+      store16<NT>(B + int64_t(orow) * p.ldb + ocol, w);
     } else if (orow < p.C) {
 #pragma unroll
       for (int j = 0; j < V; ++j)
         if (ocol + j < p.R) B[int64_t(orow) * p.ldb + ocol + j] = e[j];
     }
+  }
+}
+
+template <typename T, bool NT = false>
+__device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, unsigned char *smem) {
+  T(*tile)[65] = reinterpret_cast<T(*)[65]>(smem);
+  const int tiles_c = (p.C + 63) / 64, tiles_r = (p.R + 63) / 64;
+  // diagonal order: consecutive workgroups take different tile rows as well as different tile
+  // columns, so the ones in flight together write different column ranges of B (with a
+  // power-of-two leading dimension, equal column ranges of many rows share HBM channels)
+  const int tc = bid % tiles_c, tr = (bid / tiles_c + tc) % tiles_r;
+  if ((tr + 1) * 64 <= p.R && (tc + 1) * 64 <= p.C) {
+    transpose_vec_load<T, false, NT>(p, tr, tc, tile);
+    __syncthreads();
+    transpose_vec_store<T, false, NT>(p, tr, tc, tile);
+  } else {
+    transpose_vec_load<T, true, NT>(p, tr, tc, tile);
+    __syncthreads();
+    transpose_vec_store<T, true, NT>(p, tr, tc, tile);
   }
 }
 
@@ -1015,7 +1083,7 @@ __device__ __forceinline__ void add_block(const AddArgs &p, int bid) {
 // Vector variant (operands 16-byte aligned, leading dimensions multiples of 8): each thread adds
 // 8 consecutive elements per row of a 2048-column chunk; a workgroup covers one chunk of one row.
 // The FP32 sum of two values is rounded once to the output type, as in add_block.
-template <bool IN_BF16, bool OUT_BF16>
+template <bool IN_BF16, bool OUT_BF16, bool NT = false>
 __device__ __forceinline__ void add_block_vec(const AddArgs &p, int bid) {
   const int nbx = (p.C + 2047) / 2048;
   const int c = (bid % nbx) * 2048 + threadIdx.x * 8;
@@ -1025,8 +1093,8 @@ __device__ __forceinline__ void add_block_vec(const AddArgs &p, int bid) {
   float a[8], b[8];
   if (c + 8 <= p.C) {
     if constexpr (IN_BF16) {
-      const uint4 x = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p.A) + ia);
-      const uint4 y = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p.B) + ib);
+      const u32x4 x = load16<NT>(static_cast<const uint16_t *>(p.A) + ia);
+      const u32x4 y = load16<NT>(static_cast<const uint16_t *>(p.B) + ib);
       const uint32_t xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1038,10 +1106,13 @@ __device__ __forceinline__ void add_block_vec(const AddArgs &p, int bid) {
     } else {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float4 x = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.A) + ia + 4 * h);
-        const float4 y = *reinterpret_cast<const float4 *>(static_cast<const float *>(p.B) + ib + 4 * h);
-        a[4 * h] = x.x; a[4 * h + 1] = x.y; a[4 * h + 2] = x.z; a[4 * h + 3] = x.w;
-        b[4 * h] = y.x; b[4 * h + 1] = y.y; b[4 * h + 2] = y.z; b[4 * h + 3] = y.w;
+        const u32x4 x = load16<NT>(static_cast<const float *>(p.A) + ia + 4 * h);
+        const u32x4 y = load16<NT>(static_cast<const float *>(p.B) + ib + 4 * h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a[4 * h + e] = __uint_as_float(x[e]);
+          b[4 * h + e] = __uint_as_float(y[e]);
+        }
       }
     }
     if constexpr (OUT_BF16) {
@@ -1049,12 +1120,13 @@ __device__ __forceinline__ void add_block_vec(const AddArgs &p, int bid) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         w[q] = uint32_t(f32_to_bf16(a[2 * q] + b[2 * q])) | (uint32_t(f32_to_bf16(a[2 * q + 1] + b[2 * q + 1])) << 16);
-      *reinterpret_cast<uint4 *>(static_cast<uint16_t *>(p.Cp) + ic) = uint4{w[0], w[1], w[2], w[3]};
+      store16<NT>(static_cast<uint16_t *>(p.Cp) + ic, u32x4{w[0], w[1], w[2], w[3]});
     } else {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        *reinterpret_cast<float4 *>(static_cast<float *>(p.Cp) + ic + 4 * h) =
-            make_float4(a[4 * h] + b[4 * h], a[4 * h + 1] + b[4 * h + 1], a[4 * h + 2] + b[4 * h + 2], a[4 * h + 3] + b[4 * h + 3]);
+        store16<NT>(static_cast<float *>(p.Cp) + ic + 4 * h,
+                    u32x4{__float_as_uint(a[4 * h] + b[4 * h]), __float_as_uint(a[4 * h + 1] + b[4 * h + 1]),
+                          __float_as_uint(a[4 * h + 2] + b[4 * h + 2]), __float_as_uint(a[4 * h + 3] + b[4 * h + 3])});
     }
   } else {
     for (int e = 0; c + e < p.C; ++e)

@@ -79,7 +79,7 @@ def test_transpose_exact(r, c, dt):
 
 
 @pytest.mark.parametrize("r,c", [(1, 1), (4, 256), (512, 512), (1024, 1024), (37, 2048), (3, 2500), (77, 1000),
-                                 (5, 3)])
+                                 (5, 3), (6, 300), (9, 1996)])
 @pytest.mark.parametrize("idt,odt", [("f32", "f32"), ("f32", "bf16"), ("bf16", "bf16"), ("bf16", "f32")])
 def test_softmax(r, c, idt, odt):
     print(f"softmax {r}x{c} {idt}->{odt}", flush=True)
@@ -142,3 +142,37 @@ def test_add_and_transpose_on_column_windows(dt):
     want = round_bf16(round_f32(s_)) if dt == "bf16" else round_f32(s_)
     np.testing.assert_array_equal(out["Cv"], want)
     np.testing.assert_array_equal(out["T"], a[:, :C].T.astype(np.float64))
+
+
+# Outputs of 256 MiB and more take the streaming (non-temporal) variants; ragged edges on both axes.
+@pytest.mark.parametrize("dt,r,c", [("f32", 8200, 8216), ("bf16", 10000, 13432)])
+def test_transpose_large_streaming(dt, r, c):
+    print(f"transpose {r}x{c} {dt}", flush=True)
+    spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt])
+    a = uniform(14, (r, c))
+    got = _run(spec, {"A": a})
+    want = round_bf16(a.T) if dt == "bf16" else a.T.astype(np.float64)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("idt,odt,r,c", [("f32", "f32", 8200, 8200), ("bf16", "bf16", 8200, 16400)])
+def test_add_large_streaming(idt, odt, r, c):
+    spec = one_kernel_spec("add", [(r, c), (r, c), (r, c)], [idt, idt, odt])
+    a, b = uniform(15, (r, c)), uniform(16, (r, c))
+    got = _run(spec, {"A": a, "B": b})
+    if idt == "bf16":
+        a, b = round_bf16(a), round_bf16(b)
+    s = a.astype(np.float64) + b.astype(np.float64)
+    want = round_bf16(round_f32(s)) if odt == "bf16" else round_f32(s)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("idt,odt,r,c", [("f32", "f32", 65600, 1024), ("f32", "bf16", 65560, 2048),
+                                           ("bf16", "bf16", 65540, 2048)])
+def test_softmax_large_streaming(idt, odt, r, c):
+    print(f"softmax {r}x{c} {idt}->{odt}", flush=True)
+    spec = one_kernel_spec("softmax", [(r, c), (r, c)], [idt, odt])
+    x = (np.random.default_rng(17).standard_normal((r, c)) * 3).astype(np.float32)
+    got = _run(spec, {"A": x})
+    exact = oracle_outputs(spec, {"A": x})["C"]
+    assert normwise(got, exact) < (1e-5 if (idt, odt) == ("f32", "f32") else 2e-2)
