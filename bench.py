@@ -333,7 +333,7 @@ def one_kernel(kind, shapes, dtypes, tile=0, alpha=1.0):
 def kernels_main(a):
     """Standalone kernel rates at sizes large enough to reach the hardware's asymptotes: row
     softmax and transpose against HBM bandwidth (algorithmic bytes: input and output once), GEMMs
-    against the matrix-core peak (2MNK).  Each kernel: device-resident operands, the mean of
+    against the matrix-core peak (2MNK).  Each kernel: seeded device-resident operands, the mean of
     back-to-back launches timed with HIP events on its stream; GEMM tiles autotuned."""
     import paper_2009_07482_amd as psc
     es = {"f32": 4, "bf16": 2}
@@ -383,7 +383,17 @@ def kernels_main(a):
             unit, peak = "GB/s", PEAK["hbm"]
             label = f"{kind} {r_}x{c_} {idt}->{odt}"
         r = psc.SpecRunner(spec, "coarse")
-        psc.psc_sched_prepare(r.sched)
+        # seeded operands (uniform in [-1, 1); softmax rows standard normal): matrix-core power, and
+        # with it the clock, depends on the data, so zeros would overstate the rate
+        g = np.random.default_rng(0)
+        ins = {}
+        for b in spec["buffers"][:-1]:
+            shape = (b["rows"], b["cols"])
+            ins[b["name"]] = (g.standard_normal(shape, dtype=np.float32) if kind == "softmax"
+                              else g.random(shape, dtype=np.float32) * 2 - 1)
+        r.set_inputs(ins)
+        del ins
+        r.run(with_inputs=True, with_outputs=False)
         big = work > 1e11
         psc.psc_kernel_time(r.sched, 0, 3)
         us = psc.psc_kernel_time(r.sched, 0, 10 if big else 100)

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
 template <bool OUT_BF16>
 __global__ __launch_bounds__(512) void gemm_bf16_big_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_big_smem()];
-  gemm_bf16_big_tile<OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
+  // 4-row groups of tiles per XCD (measured 1-3% faster than plain rows at 4096^3 and 8192^3)
+  gemm_bf16_big_tile<OUT_BF16>(p, group_tile(xcd_tile(blockIdx.x, gridDim.x), gridDim.x / p.tiles_n, p.tiles_n, 4), smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
@@ -214,6 +215,39 @@ void make_mark(Launch &L, uint64_t *slot) {
   std::memcpy(L.args, &slot, sizeof(slot));
 }
 
+namespace {
+struct FillArgs {
+  uint32_t *p;
+  int64_t words;
+  int32_t bf16;
+  uint32_t seed;
+};
+// 32-bit integer mix (xor-shift-multiply rounds); only its spread matters here
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352du;
+  x ^= x >> 15; x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < a.words; i += int64_t(gridDim.x) * 256) {
+    const uint32_t h = mix32(uint32_t(i) ^ mix32(uint32_t(i >> 32) + a.seed));
+    const float lo = float(h & 0xffffu) * (1.0f / 32768.0f) - 1.0f, hi = float(h >> 16) * (1.0f / 32768.0f) - 1.0f;
+    a.p[i] = a.bf16 ? uint32_t(f32_to_bf16(lo)) | (uint32_t(f32_to_bf16(hi)) << 16) : __float_as_uint(lo);
+  }
+}
+}  // namespace
+
+void make_fill(Launch &L, void *p, int64_t bytes, int bf16, uint32_t seed) {
+  L = Launch{};
+  const FillArgs a{static_cast<uint32_t *>(p), bytes / 4, bf16, seed};
+  L.func = reinterpret_cast<const void *>(&fill_kernel);
+  L.grid = dim3(unsigned(std::min<int64_t>(4096, std::max<int64_t>(1, (a.words + 255) / 256))), 1, 1);
+  L.block = dim3(256, 1, 1);
+  L.empty = a.words == 0;
+  std::memcpy(L.args, &a, sizeof(a));
+}
+
 int gemm_auto_tile(int M, int N, int K, int dtype) {
   (void)dtype;
   // Enough output tiles to fill the chip: the large-tile kernels.  Otherwise the split-K kernels,
@@ -230,7 +264,7 @@ int gemm_auto_tile(int M, int N, int K, int dtype) {
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
-  if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 128 tile exists for BF16 operands only
+  if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 256 tile exists for BF16 operands only
   if (tile == 16) {  // whole tiles, aligned operands only
     const bool fits = a.M % 256 == 0 && a.N % 256 == 0 && a.K % 64 == 0 && a.K > 0 && aligned16(a.A) &&
                       aligned16(a.B) && a.lda % 8 == 0 && a.ldb % 8 == 0;

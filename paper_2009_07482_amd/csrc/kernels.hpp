@@ -58,6 +58,10 @@ bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype);
 int gemm_num_tiles();
 // One-thread kernel that stores the device wall clock (wall_clock64) to *slot.
 void make_mark(Launch &L, uint64_t *slot);
+// Fills bytes / 4 32-bit words at p with values uniform in [-1, 1) from a hash of (index, seed):
+// one FP32 value per word, or (bf16) two bfloat16 values.  Timing operands for the autotuner
+// (the matrix cores' power, and with it the clock, depends on the data).
+void make_fill(Launch &L, void *p, int64_t bytes, int bf16, uint32_t seed);
 void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
 int tile_cache_get(int M, int N, int K, int ab, int c);
 void tile_cache_clear();

@@ -799,8 +799,8 @@ void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) 
   if (ld) *ld = buffer_ld(g, it->second);
 }
 
-// Autotuner: times every GEMM tile configuration on device buffers of the given shape (zeros)
-// with back-to-back launches between HIP events, records the fastest in the tile cache and
+// Autotuner: times every GEMM tile configuration on device buffers of the given shape (seeded
+// values uniform in [-1, 1)) with back-to-back launches between HIP events, records the fastest in the tile cache and
 // returns it.  us_per_tile[t] (t < cap) receives each configuration's mean time (0 for t = 0).
 int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, float *best_us, float *us_per_tile,
                   int cap) {
@@ -826,6 +826,13 @@ int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, flo
     PSC_HIP(hipMemset(A, 0, std::max<size_t>(16, size_t(M) * K * ea)));
     PSC_HIP(hipMemset(B, 0, std::max<size_t>(16, size_t(K) * N * ea)));
     PSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    {
+      Launch fa, fb;
+      make_fill(fa, A, int64_t(M) * K * ea, ab == PSC_BF16, 1u);
+      make_fill(fb, B, int64_t(K) * N * ea, ab == PSC_BF16, 2u);
+      launch(fa, st);
+      launch(fb, st);
+    }
     PSC_HIP(hipEventCreate(&e0));
     PSC_HIP(hipEventCreate(&e1));
     for (int t = 1; t < gemm_num_tiles(); ++t) {

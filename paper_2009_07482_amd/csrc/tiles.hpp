@@ -85,6 +85,16 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// Grouped tile order: consecutive tile indices walk G tile rows column by column, so the tiles an
+// XCD runs at one time form a G-row block (4 x 8 for 32 compute units) that shares G row panels
+// of A and a few column panels of B in that XCD's L2, instead of one or two full tile rows that
+// each need every column panel of B.
+__device__ __forceinline__ int group_tile(int t, int tiles_m, int tiles_n, int G) {
+  const int per = G * tiles_n, g = t / per, w = t % per;
+  const int rows = min(G, tiles_m - g * G);
+  return (g * G + w % rows) * tiles_n + w / rows;
+}
+
 // ---------------------------------------------------------------------------------------------
 // GEMM, C = alpha * A * B.  Block tile BM x BN, K step BK, each wavefront a WM x WN sub-tile made
 // of 16 x 16 matrix-core blocks.  Operand tiles are staged through LDS with padded pitches so that
@@ -661,6 +671,8 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // ask the scheduler to interleave the LDS reads with the matrix products (measured ~5% faster)
+    __builtin_amdgcn_iglp_opt(0);
   };
 
   const int steps = p.K / BK;
