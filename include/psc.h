@@ -51,7 +51,8 @@ typedef enum psc_status {
   PSC_ERR_STATE = -6,    /* call not allowed in the object's current state */
   PSC_ERR_HIP = -7,      /* a HIP runtime call failed (message names it) */
   PSC_ERR_OOM = -8,      /* device or host allocation failed */
-  PSC_ERR_UNSUPPORTED = -9
+  PSC_ERR_UNSUPPORTED = -9,
+  PSC_ERR_TIMEOUT = -10  /* a run did not finish within psc_sched_opts.timeout_ms */
 } psc_status;
 
 typedef enum psc_dtype { PSC_F32 = 0, PSC_BF16 = 1 } psc_dtype;
@@ -124,7 +125,18 @@ typedef struct psc_sched_opts {
                               kernel, also inside the graph), so psc_sched_component_times can
                               report when each component finished -- per-instance latency of a
                               batch.  PSC_DEVICE always keeps per-kernel clocks instead. */
-  int32_t reserved[6];
+  int32_t fault_inject_op; /* failure-path testing: 0 = off; k > 0 = every psc_run of this schedule
+                              treats op k-1 (psc_sched_export's op id = host order) as failed to
+                              launch: the ops before it in host order are enqueued eagerly (one
+                              host thread, also for a use_graph schedule), psc_run waits for them
+                              and returns PSC_ERR_HIP naming op k-1; nothing from op k-1 on runs.
+                              The schedule stays usable.  Not for PSC_DEVICE. */
+  int32_t timeout_ms;   /* 0 = psc_run waits for the end of the run however long it takes;
+                           t > 0 = it waits at most t milliseconds after enqueueing and returns
+                           PSC_ERR_TIMEOUT when the run has not finished.  The work stays in
+                           flight: the next psc_run of the schedule, and psc_sched_destroy, first
+                           wait for it to finish.  Outputs of a timed-out run are unspecified. */
+  int32_t reserved[4];
 } psc_sched_opts;
 
 /* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..
@@ -241,6 +253,20 @@ psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass,
  * Errors: PSC_ERR_SHAPE, PSC_ERR_CYCLE, PSC_ERR_RACE (see psc_status), PSC_ERR_ARG. */
 psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts,
                         psc_sched **out);
+
+/* Schedules the DAGs dags[0..n) as one batch (n >= 1): the schedule holds its own copy of their
+ * disjoint union, planned with `policy` and `opts` as psc_schedule plans one DAG, run by one
+ * psc_run (one hipGraph with use_graph).  In the union, buffer and kernel names are "<i>/<name>"
+ * with i the DAG's position in `dags` (psc_host_io names them so); ids follow DAG order (DAG i's
+ * buffers, kernels and edges after DAG i-1's, each in its own order); task component c of DAG i
+ * becomes component c + (sum of the component counts of DAGs 0..i-1), so DAGs whose kernels all
+ * lie in component 0 become components 0..n-1 (per-instance completion times with
+ * mark_components).  Buffers bound with psc_bind_device keep their caller memory (DAGs may share
+ * device-resident weights that way).  The source DAGs are not modified, not frozen and may be
+ * destroyed right after this call.  Errors: as psc_schedule (validation errors name the buffer or
+ * kernel with its "<i>/" prefix); PSC_ERR_ARG for n < 1 or a NULL DAG. */
+psc_status psc_schedule_batch(psc_dag *const *dags, int32_t n, int32_t policy, const psc_sched_opts *opts,
+                              psc_sched **out);
 
 /* Copies the schedule's ops (ordered by id) into ops[0..cap) and their waits into
  * waits[0..waits_cap); *n_ops / *n_waits receive the totals.  With ops == NULL or waits == NULL

@@ -31,7 +31,7 @@ _lib = C.CDLL(LIB_PATH)
 PSC_OK = 0
 STATUS = {0: "PSC_OK", -1: "PSC_ERR_ARG", -2: "PSC_ERR_NAME", -3: "PSC_ERR_SHAPE", -4: "PSC_ERR_CYCLE",
           -5: "PSC_ERR_RACE", -6: "PSC_ERR_STATE", -7: "PSC_ERR_HIP", -8: "PSC_ERR_OOM",
-          -9: "PSC_ERR_UNSUPPORTED"}
+          -9: "PSC_ERR_UNSUPPORTED", -10: "PSC_ERR_TIMEOUT"}
 PSC_F32, PSC_BF16 = 0, 1
 DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
 PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
@@ -61,7 +61,7 @@ class psc_sched_opts(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("mapper", C.c_int32), ("copy_stream", C.c_int32),
                 ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
                 ("cost", C.c_void_p), ("host_threads", C.c_int32), ("mark_components", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("fault_inject_op", C.c_int32), ("timeout_ms", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class psc_op(C.Structure):
@@ -110,6 +110,7 @@ _SIGS = {
     "psc_buffer_id": [_P, _S, C.POINTER(_I)],
     "psc_dag_classify": [_P, _I, C.POINTER(_I), C.POINTER(_I)],
     "psc_schedule": [_P, _I, C.POINTER(psc_sched_opts), C.POINTER(_P)],
+    "psc_schedule_batch": [C.POINTER(_P), _I, _I, C.POINTER(psc_sched_opts), C.POINTER(_P)],
     "psc_sched_export": [_P, C.POINTER(psc_op), _I, C.POINTER(_I), C.POINTER(_I), _I,
                          C.POINTER(_I)],
     "psc_sched_streams": [_P, C.POINTER(_I)],
@@ -238,7 +239,8 @@ def psc_dag_classify(dag, component):
 
 
 def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
-              device=0, cost=None, host_threads=0, mark_components=False):
+              device=0, cost=None, host_threads=0, mark_components=False, fault_inject_op=0,
+              timeout_ms=0):
     o = psc_sched_opts()
     o.n_streams = int(n_streams)
     o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
@@ -249,6 +251,8 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
     o.cost = None if cost is None else C.c_void_p(int(cost.value if hasattr(cost, "value") else cost))
     o.host_threads = int(host_threads)
     o.mark_components = int(bool(mark_components))
+    o.fault_inject_op = int(fault_inject_op)
+    o.timeout_ms = int(timeout_ms)
     return o
 
 
@@ -258,6 +262,17 @@ def psc_schedule(dag, policy, opts=None, **kw):
     o = opts if opts is not None else make_opts(**kw)
     h = _P()
     _check(_lib.psc_schedule(dag, pol, C.byref(o), C.byref(h)))
+    return h
+
+
+def psc_schedule_batch(dags, policy, opts=None, **kw):
+    """One schedule for the disjoint union of ``dags`` (names "<i>/<name>"; see union_spec)."""
+    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+           if isinstance(policy, str) else int(policy))
+    o = opts if opts is not None else make_opts(**kw)
+    arr = (_P * max(1, len(dags)))(*[d.value if hasattr(d, "value") else d for d in dags])
+    h = _P()
+    _check(_lib.psc_schedule_batch(arr, len(dags), pol, C.byref(o), C.byref(h)))
     return h
 
 
@@ -700,6 +715,46 @@ class SpecRunner:
             self.close()
         except Exception:
             pass
+
+
+def union_spec(specs):
+    """The spec of the DAG psc_schedule_batch builds from ``specs``: names prefixed "<i>/",
+    kernel indices offset, task components offset by the component counts before them."""
+    bufs, kers, edges, comp = [], [], [], []
+    c_off = 0
+    for i, sp in enumerate(specs):
+        pre, base = f"{i}/", len(kers)
+        for b in sp["buffers"]:
+            bufs.append(dict(b, name=pre + b["name"], view_of=None if b["view_of"] is None else pre + b["view_of"]))
+        for k in sp["kernels"]:
+            kers.append(dict(k, name=pre + k["name"], inputs=[pre + x for x in k["inputs"]],
+                             outputs=[pre + x for x in k["outputs"]]))
+        edges += [(s_ + base, pre + sb, t + base, pre + tb) for (s_, sb, t, tb) in sp["edges"]]
+        cs = list(sp.get("component", [0] * len(sp["kernels"]))) or [0] * len(sp["kernels"])
+        comp += [c + c_off for c in cs]
+        c_off += (max(cs) + 1) if cs else 1
+    return {"buffers": bufs, "kernels": kers, "edges": edges, "component": comp}
+
+
+class BatchRunner(SpecRunner):
+    """Several specs scheduled as one batch by psc_schedule_batch; buffers are named "<i>/<name>".
+    The per-spec DAGs are destroyed right after scheduling (the schedule holds its own union)."""
+
+    def __init__(self, specs, policy="fine", **opts):
+        import workloads
+        self.spec = union_spec(specs)
+        self.by = {b["name"]: b for b in self.spec["buffers"]}
+        dags = [build_dag(sp) for sp in specs]
+        try:
+            self.sched = psc_schedule_batch(dags, policy, **opts)
+        finally:
+            for d in dags:
+                psc_dag_destroy(d)
+        self.dag = None
+        self.in_names = workloads.host_inputs_of(self.spec)
+        self.out_names = workloads.host_outputs_of(self.spec)
+        self.outputs = _LazyOutputs(self.by)
+        self.inputs = {}
 
 
 def run_spec(spec, inputs, policy="fine", **opts):

@@ -70,6 +70,7 @@ psc_status guard(F &&f) {
 void need(bool cond, psc_status st, const char *msg) {
   if (!cond) psc::fail(st, msg);
 }
+void need(bool cond, psc_status st, const std::string &msg) { need(cond, st, msg.c_str()); }
 
 void not_frozen(const psc::Dag &g) {
   if (g.frozen) psc::fail(PSC_ERR_STATE, "the DAG is frozen: it has been scheduled");
@@ -245,28 +246,99 @@ psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass, in
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+std::unique_ptr<psc_sched> new_sched(psc_dag *dag, int32_t policy, const psc_sched_opts *opts) {
+  need(policy == PSC_COARSE || policy == PSC_FINE || policy == PSC_DEVICE, PSC_ERR_ARG,
+       "policy must be PSC_COARSE, PSC_FINE or PSC_DEVICE");
+  psc_sched_opts o = opts ? *opts : default_opts();
+  if (policy != PSC_FINE) o.n_streams = 1;
+  need(!(policy == PSC_DEVICE && o.use_graph), PSC_ERR_ARG, "PSC_DEVICE runs one kernel; use_graph does not apply");
+  need(o.n_streams >= 1 && o.n_streams <= 64, PSC_ERR_ARG, "n_streams must be in [1, 64]");
+  need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
+  need(!(o.use_graph && o.record_ops), PSC_ERR_ARG, "record_ops cannot be combined with use_graph");
+  need(o.device >= 0, PSC_ERR_ARG, "negative device");
+  need(o.mark_components == 0 || o.mark_components == 1, PSC_ERR_ARG, "mark_components must be 0 or 1");
+  need(o.timeout_ms >= 0, PSC_ERR_ARG, "negative timeout_ms");
+  need(o.fault_inject_op >= 0, PSC_ERR_ARG, "negative fault_inject_op");
+  need(!(policy == PSC_DEVICE && o.fault_inject_op), PSC_ERR_ARG, "fault_inject_op does not apply to PSC_DEVICE");
+  psc::Dag &g = dag->g;
+  if (!g.validated || !g.frozen) g.validate();
+  g.frozen = true;
+  auto s = std::make_unique<psc_sched>();
+  s->dag = dag;
+  s->opts = o;
+  s->policy = policy;
+  s->plan = psc::build_plan(g, policy, o);
+  need(size_t(o.fault_inject_op) <= s->plan.ops.size(), PSC_ERR_ARG,
+       "fault_inject_op " + std::to_string(o.fault_inject_op) + " beyond the schedule's " +
+           std::to_string(s->plan.ops.size()) + " ops");
+  return s;
+}
+
+// Disjoint union of DAGs: names prefixed with "<i>/", ids and components offset.
+std::unique_ptr<psc_dag> dag_union(psc_dag *const *dags, int32_t n) {
+  auto u = std::make_unique<psc_dag>();
+  psc::Dag &m = u->g;
+  int32_t comp_off = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    need(dags[i] != nullptr, PSC_ERR_ARG, "NULL DAG at batch position " + std::to_string(i));
+    const psc::Dag &g = dags[i]->g;
+    const int32_t boff = int32_t(m.bufs.size()), koff = int32_t(m.kers.size());
+    const std::string pre = std::to_string(i) + "/";
+    for (psc::Buffer b : g.bufs) {
+      b.name = pre + b.name;
+      if (b.parent >= 0) b.parent += boff;
+      b.root += boff;
+      m.buf_by_name[b.name] = int32_t(m.bufs.size());
+      m.bufs.push_back(std::move(b));
+    }
+    int32_t n_comp = 0;
+    for (psc::Kernel k : g.kers) {
+      k.name = pre + k.name;
+      for (int32_t &x : k.ins) x += boff;
+      for (int32_t &x : k.outs) x += boff;
+      n_comp = std::max(n_comp, k.component + 1);
+      k.component += comp_off;
+      m.ker_by_name[k.name] = int32_t(m.kers.size());
+      m.kers.push_back(std::move(k));
+    }
+    for (psc::Edge e : g.edges) {
+      e.src += koff;
+      e.dst += koff;
+      e.src_buf += boff;
+      e.dst_buf += boff;
+      m.edges.push_back(e);
+    }
+    comp_off += n_comp;
+  }
+  return u;
+}
+
+}  // namespace
+
+extern "C" {
+
 psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, psc_sched **out) {
   return guard([&] {
     need(dag && out, PSC_ERR_ARG, "NULL argument");
-    need(policy == PSC_COARSE || policy == PSC_FINE || policy == PSC_DEVICE, PSC_ERR_ARG,
-         "policy must be PSC_COARSE, PSC_FINE or PSC_DEVICE");
-    psc_sched_opts o = opts ? *opts : default_opts();
-    if (policy != PSC_FINE) o.n_streams = 1;
-    need(!(policy == PSC_DEVICE && o.use_graph), PSC_ERR_ARG, "PSC_DEVICE runs one kernel; use_graph does not apply");
-    need(o.n_streams >= 1 && o.n_streams <= 64, PSC_ERR_ARG, "n_streams must be in [1, 64]");
-    need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
-    need(!(o.use_graph && o.record_ops), PSC_ERR_ARG, "record_ops cannot be combined with use_graph");
-    need(o.device >= 0, PSC_ERR_ARG, "negative device");
-    need(o.mark_components == 0 || o.mark_components == 1, PSC_ERR_ARG, "mark_components must be 0 or 1");
-    psc::Dag &g = dag->g;
-    if (!g.validated || !g.frozen) g.validate();
-    g.frozen = true;
-    auto s = std::make_unique<psc_sched>();
-    s->dag = dag;
-    s->opts = o;
-    s->policy = policy;
-    s->plan = psc::build_plan(g, policy, o);
-    ++g.live_scheds;
+    auto s = new_sched(dag, policy, opts);
+    ++dag->g.live_scheds;
+    *out = s.release();
+  });
+}
+
+psc_status psc_schedule_batch(psc_dag *const *dags, int32_t n, int32_t policy, const psc_sched_opts *opts,
+                              psc_sched **out) {
+  return guard([&] {
+    need(dags && out, PSC_ERR_ARG, "NULL argument");
+    need(n >= 1, PSC_ERR_ARG, "a batch needs at least one DAG");
+    auto u = dag_union(dags, n);
+    auto s = new_sched(u.get(), policy, opts);
+    ++u->g.live_scheds;
+    s->owned_dag = std::move(u);
     *out = s.release();
   });
 }

@@ -133,6 +133,7 @@ struct psc_dag {
 
 struct psc_sched {
   psc_dag *dag = nullptr;
+  std::unique_ptr<psc_dag> owned_dag;  // a batch's union (dag points to it); outlives dev
   psc_sched_opts opts{};
   int32_t policy = PSC_FINE;
   psc::SchedPlan plan;

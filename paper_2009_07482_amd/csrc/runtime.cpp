@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <queue>
@@ -46,6 +47,7 @@ struct Device {
   std::vector<hipEvent_t> op_ev;
   std::vector<hipEvent_t> join_ev;
   hipEvent_t start = nullptr, end = nullptr;
+  bool in_flight = false;          // a timed-out run may still execute (wait for `end` first)
   std::vector<hipEvent_t> t0, t1;  // per-op timing (record_ops)
   std::vector<Launch> launch;      // per kernel id
   hipGraph_t graph = nullptr;
@@ -67,6 +69,7 @@ struct Device {
   double clock_mhz = 100.0;   // device wall clock rate
 
   ~Device() {
+    if (in_flight && end) (void)hipEventSynchronize(end);  // a timed-out run still executing
     disp.reset();
     if (exec_mem) (void)hipFree(exec_mem);
     if (marks) (void)hipFree(marks);
@@ -556,11 +559,64 @@ void build_graph(psc_sched &s, const std::vector<CopyDesc> &cd) {
 
 }  // namespace
 
+namespace {
+
+// Failure injection: enqueue the host-order prefix before the failing op on its streams (waits
+// of a prefix op only name earlier ops), wait for it, then fail as a launch error would.
+[[noreturn]] void run_fault_prefix(psc_sched &s, const std::vector<CopyDesc> &cd) {
+  Device &d = *s.dev;
+  const int32_t k = s.opts.fault_inject_op - 1;
+  HipBackend backend(s, cd, false);
+  PSC_HIP(hipEventRecord(d.start, d.streams[0]));
+  fork_streams(d, d.start);
+  for (int32_t o = 0; o < k; ++o) {
+    const Op &op = s.plan.ops[o];
+    for (int32_t w : op.waits) backend.wait(o, w);
+    backend.exec(o);
+    if (op.recorded) backend.record(o);
+  }
+  for (hipStream_t st : d.streams) PSC_HIP(hipStreamSynchronize(st));
+  const Op &f = s.plan.ops[k];
+  const std::string what = f.type == PSC_OP_KERNEL ? "kernel '" + s.dag->g.kers[f.kernel].name + "'"
+                                                   : std::string(f.type == PSC_OP_H2D ? "H2D of '" : "D2H of '") +
+                                                         s.dag->g.bufs[f.buffer].name + "'";
+  fail(PSC_ERR_HIP, "injected fault: op " + std::to_string(k) + " (" + what + ") was not launched; the " +
+                        std::to_string(k) + " ops before it in host order ran and have finished");
+}
+
+// Waits for the run's end event, at most timeout_ms when that is set.
+void wait_end(psc_sched &s) {
+  Device &d = *s.dev;
+  if (s.opts.timeout_ms <= 0) {
+    PSC_HIP(hipEventSynchronize(d.end));
+    return;
+  }
+  const auto limit = std::chrono::steady_clock::now() + std::chrono::milliseconds(s.opts.timeout_ms);
+  for (;;) {
+    const hipError_t q = hipEventQuery(d.end);
+    if (q == hipSuccess) return;
+    if (q != hipErrorNotReady) PSC_HIP(q);
+    if (std::chrono::steady_clock::now() >= limit) {
+      d.in_flight = true;
+      fail(PSC_ERR_TIMEOUT, "run not finished within timeout_ms = " + std::to_string(s.opts.timeout_ms) +
+                                " (still executing; the next psc_run or psc_sched_destroy waits for it)");
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
 void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats) {
   prepare(s);
   Device &d = *s.dev;
   PSC_HIP(hipSetDevice(d.device));
+  if (d.in_flight) {  // the previous run timed out: its work must end before buffers are reused
+    PSC_HIP(hipEventSynchronize(d.end));
+    d.in_flight = false;
+  }
   const std::vector<CopyDesc> cd = resolve_io(s, io, n_io);
+  if (s.opts.fault_inject_op > 0) run_fault_prefix(s, cd);
   const bool timed = s.opts.record_ops != 0;
   hipStream_t s0 = d.streams[0];
   double host_ms = 0;
@@ -601,7 +657,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     PSC_HIP(hipEventRecord(d.end, s0));
     host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   }
-  PSC_HIP(hipEventSynchronize(d.end));
+  wait_end(s);
   float ms = 0;
   PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
   d.have_marks = d.marks != nullptr || s.plan.device;
@@ -894,7 +950,7 @@ float kernel_time(psc_sched &s, int32_t kernel, int32_t iters) {
   PSC_HIP(hipEventRecord(d.start, st));
   for (int32_t i = 0; i < iters; ++i) launch(d.launch[kernel], st);
   PSC_HIP(hipEventRecord(d.end, st));
-  PSC_HIP(hipEventSynchronize(d.end));
+  wait_end(s);
   float ms = 0;
   PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
   return ms * 1000.f / float(std::max(1, iters));

@@ -105,3 +105,96 @@ def test_batch64_full_size_sampled_instances():
             print(f"instance {i} n={lengths[i]}: normwise error {err:.2e}", flush=True)
             assert err < 2e-2
     r.close()
+
+
+# --- psc_schedule_batch: separate DAGs, one schedule --------------------------------------------
+
+@pytest.mark.parametrize("kw", [dict(n_streams=4, mapper="component", mark_components=True),
+                                dict(n_streams=3, mapper="eft", use_graph=True),
+                                dict(n_streams=1)], ids=["eager", "graph-eft", "one-stream"])
+def test_schedule_batch_equals_separate_runs(kw):
+    """Eight attention DAGs of uneven length, each with its own inputs, scheduled as one batch:
+    every output bit-identical to the DAG run alone, and within the FP32 bar of the oracle."""
+    d, heads, layers = 64, 2, 2
+    specs = [workloads.mha_spec(n, d, heads, layers) for n in LENGTHS]
+    inps = [workloads.mha_inputs(10 + i, n, d, layers) for i, n in enumerate(LENGTHS)]
+    print(f"schedule_batch {LENGTHS} {kw}", flush=True)
+    r = psc.BatchRunner(specs, "fine", **kw)
+    try:
+        r.set_inputs({f"{i}/{k}": v for i, inp in enumerate(inps) for k, v in inp.items()})
+        r.run()
+        for i, (sp, inp) in enumerate(zip(specs, inps)):
+            alone, _ = psc.run_spec(sp, inp, "coarse")
+            want = oracle_outputs(sp, inp)
+            for name in workloads.host_outputs_of(sp):
+                got = r.result(f"{i}/{name}")
+                assert np.array_equal(got, alone[name]), (i, name)
+                assert normwise(got, want[name]) < 1e-4, (i, name)
+        if kw.get("mark_components"):
+            done = psc.psc_sched_component_times(r.sched)
+            assert done.shape == (max(r.spec["component"]) + 1,)   # heads and joins of every DAG
+            assert np.all(done > 0)
+    finally:
+        r.close()
+
+
+# --- failure paths forced from the host ----------------------------------------------------------
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_fault_injection_runs_the_prefix_and_reports(use_graph):
+    spec = workloads.mha_spec(64, 64, 2, 1)
+    inp = workloads.mha_inputs(3, 64, 64, 1)
+    d = psc.build_dag(spec)
+    s0 = psc.psc_schedule(d, "fine", n_streams=3)
+    n_ops = len(psc.psc_sched_export(s0))
+    psc.psc_sched_destroy(s0)
+    psc.psc_dag_destroy(d)
+    for k in (1, n_ops // 2, n_ops):
+        print(f"fault at op {k - 1} of {n_ops} graph={use_graph}", flush=True)
+        r = psc.SpecRunner(spec, "fine", n_streams=3, use_graph=use_graph, fault_inject_op=k)
+        try:
+            r.set_inputs(inp)
+            for _ in range(2):      # the schedule stays usable and fails the same way
+                with pytest.raises(psc.PscError) as e:
+                    r.run()
+                assert e.value.name == "PSC_ERR_HIP" and f"injected fault: op {k - 1} " in str(e.value)
+        finally:
+            r.close()
+    # the same DAG without the fault: correct results
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=3)
+    want = oracle_outputs(spec, inp)
+    for name, w in want.items():
+        assert normwise(out[name], w) < 1e-4
+
+
+def _gemm_chain(n, length):
+    bufs = [{"name": "A", "dtype": "f32", "rows": n, "cols": n, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "B", "dtype": "f32", "rows": n, "cols": n, "view_of": None, "row_off": 0, "col_off": 0}]
+    bufs += [{"name": f"C{i}", "dtype": "f32", "rows": n, "cols": n, "view_of": None, "row_off": 0, "col_off": 0}
+             for i in range(length)]
+    kers = [{"name": f"g{i}", "kind": "gemm", "inputs": ["A" if i == 0 else f"C{i - 1}", "B"],
+             "outputs": [f"C{i}"], "alpha": 1.0, "tile": 1} for i in range(length)]
+    edges = [(i - 1, f"C{i - 1}", i, f"C{i - 1}") for i in range(1, length)]
+    return {"buffers": bufs, "kernels": kers, "edges": edges, "component": [0] * length}
+
+
+def test_timeout_returns_and_later_calls_drain_the_run():
+    """Eight dependent 4096^3 FP32 GEMMs (~10 ms) under a 1 ms limit: psc_run returns
+    PSC_ERR_TIMEOUT while the GEMMs still run; the next run waits for them first; destroying the
+    schedule waits too.  Operands stay on the device (no copies)."""
+    spec = _gemm_chain(4096, 8)
+    r = psc.SpecRunner(spec, "fine", n_streams=2, timeout_ms=1)
+    try:
+        for _ in range(2):
+            with pytest.raises(psc.PscError) as e:
+                r.run(with_inputs=False, with_outputs=False)
+            assert e.value.name == "PSC_ERR_TIMEOUT"
+    finally:
+        r.close()
+    # a generous limit: the same chain completes, on small ternary operands exactly
+    spec = _gemm_chain(256, 3)
+    g = np.random.default_rng(4)
+    inp = {"A": g.integers(-1, 2, (256, 256)).astype(np.float32),
+           "B": (np.eye(256) * g.choice([-1.0, 1.0], 256)).astype(np.float32)}
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=2, timeout_ms=60000)
+    np.testing.assert_array_equal(out["C2"], oracle_outputs(spec, inp)["C2"])
