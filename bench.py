@@ -594,7 +594,7 @@ def batch_cpu_baseline(lengths, d, h, L, inp, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the executor runs on one GPU; --gpus must be 1 (the sharded design is described, not built)"}))
         sys.exit(2)
     import paper_2009_07482_amd as psc
 

@@ -19,7 +19,7 @@ Modules
                 Adam.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py`` except the cost
-model's makespan *predictions*, which have no published values (parity unpinned; they are judged
+model's makespan *predictions*, which have no published values (parity unpinned; they are assessed
 by measured makespans instead).
 """
 from . import kernels, bf16, dag, attention, validator, mlp  # noqa: F401
