@@ -249,10 +249,11 @@ void make_fill(Launch &L, void *p, int64_t bytes, int bf16, uint32_t seed) {
 }
 
 int gemm_auto_tile(int M, int N, int K, int dtype) {
-  (void)dtype;
-  // Enough output tiles to fill the chip: the large-tile kernels.  Otherwise the split-K kernels,
-  // which run four wavefronts per tile along K: the largest tile that still yields >= 256 blocks
-  // (>= 128 when K is long), else the smallest tile.
+  // BF16 shapes of whole 256 x 256 tiles that fill the chip: the eight-wavefront tile (the
+  // launch factory still checks alignment).  Otherwise, enough output tiles to fill the chip: the
+  // large-tile kernels; else the split-K kernels, which run four wavefronts per tile along K: the
+  // largest tile that still yields >= 256 blocks (>= 128 when K is long), else the smallest tile.
+  if (dtype == 1 && M % 256 == 0 && N % 256 == 0 && K % 64 == 0 && K > 0 && tiles_of(16, M, N) >= 256) return 16;
   for (int t : {1, 4, 5, 2})
     if (tiles_of(t, M, N) >= 256) return t;
   const int64_t want = K >= 256 ? 128 : 256;
