@@ -729,7 +729,15 @@ constexpr int gemm_direct_smem() {
 
 // G: K steps per load group (default 8 / FN: bounded registers for the standalone kernels; the
 // device executor, which runs one workgroup per CU anyway, uses 8 for FP32).
-template <int FN, bool BF16, bool VEC, bool OUT_BF16, int G = 8 / FN>
+// FP32 B, two ways to reach each lane's E rows of its columns (measured, FN = 2 and 4):
+//   BCOL = false: the FN consecutive columns FN c .. FN c + FN - 1 of one B row in one vector
+//     load (block j then holds the tile columns = j mod FN): 4x fewer load instructions, 256
+//     contiguous bytes per 16 lanes -- faster with short load groups (9.8 -> 7.6 us for a
+//     512 x 64 x 512 GEMM in 16 x 64 tiles);
+//   BCOL = true: one 4-byte load per (block, row), block j holding columns 16 j .. 16 j + 15 --
+//     faster with the executor's groups of 8 steps (its projection tasks ran ~10% longer with
+//     the vector loads, 128 of them in flight per lane).
+template <int FN, bool BF16, bool VEC, bool OUT_BF16, int G = 8 / FN, bool BCOL = (G > 8 / FN)>
 __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, unsigned char *smem) {
   static_assert(!BF16 || G == 8 / FN, "the BF16 staging area is sized for G = 8 / FN");
   constexpr int TN = 16 * FN;
@@ -789,7 +797,7 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
             rb1[g][u] = pack8_guarded(b0 + p.ldb, [&](int e) { return uok && k0 + 1 < ke && c + e < p.N; });
           }
         }
-      } else {
+      } else if constexpr (BCOL) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
           const int col = n0 + 16 * j + (lane & 15);
@@ -797,6 +805,27 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
 #pragma unroll
           for (int e = 0; e < E; ++e)
             rbf[g][j][e] = (col_ok && k + e < ke) ? reinterpret_cast<const float *>(B)[int64_t(k + e) * p.ldb + col] : 0.f;
+        }
+      } else {
+        // FP32 B: the lane's FN consecutive columns of one B row in one load (block j holds the
+        // columns = j mod FN of the tile), for each of its E rows k + e
+        const int colb = n0 + FN * (lane & 15);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const float *brow = reinterpret_cast<const float *>(B) + int64_t(k + e) * p.ldb + colb;
+          if (VEC && FN > 1 && colb + FN <= p.N && k + e < ke) {
+            if constexpr (FN == 4) {
+              const float4 v = *reinterpret_cast<const float4 *>(brow);
+              rbf[g][0][e] = v.x; rbf[g][FN > 1 ? 1 : 0][e] = v.y; rbf[g][FN > 2 ? 2 : 0][e] = v.z; rbf[g][FN > 3 ? 3 : 0][e] = v.w;
+            } else if constexpr (FN == 2) {
+              const float2 v = *reinterpret_cast<const float2 *>(brow);
+              rbf[g][0][e] = v.x; rbf[g][FN > 1 ? 1 : 0][e] = v.y;
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              rbf[g][j][e] = (colb + j < p.N && k + e < ke) ? brow[j] : 0.f;
+          }
         }
       }
     }
@@ -848,9 +877,12 @@ __device__ __forceinline__ void gemm_direct_tile(const GemmArgs &p, int bid, uns
   __syncthreads();  // all waves done with their staging before the LDS holds partial sums
   float *red = reinterpret_cast<float *>(smem);
 #pragma unroll
-  for (int j = 0; j < FN; ++j)
+  for (int j = 0; j < FN; ++j) {
+    // block j, lane column slot c: tile column 16 j + c (BF16, FP32 with BCOL) or FN c + j
+    const int tc = (BF16 || BCOL) ? j * 16 + (lane & 15) : FN * (lane & 15) + j;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[w * 16 * TN + ((lane >> 4) * 4 + r) * TN + j * 16 + (lane & 15)] = acc[j][r];
+    for (int r = 0; r < 4; ++r) red[w * 16 * TN + ((lane >> 4) * 4 + r) * TN + tc] = acc[j][r];
+  }
   __syncthreads();
   for (int e = tid; e < 16 * TN; e += 256) {
     const int orow = m0 + e / TN, col = n0 + e % TN;
