@@ -593,9 +593,11 @@ __device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
 // step's operands are loaded into registers while the current step is multiplied out of LDS; two
 // LDS buffers alternate, so each step needs one barrier.  Shapes are whole tiles (no edge guards,
 // no per-load branches), every load an offset from one per-thread base pointer.  A is staged as
-// As[m][k], B transposed as Bt[n][k] with (k, k+1) pairs in 32-bit writes; the unit-to-lane order
-// of the B loads (4 lanes along n, then 16 along k) keeps those writes at most 2-way bank
-// conflicted while each 4-lane group still reads 64 contiguous bytes of a B row.
+// As[m][k]; B is transposed in registers: each thread loads a 4 x 8 block (four k rows of eight
+// n), builds each column's four k values with two byte permutes and writes them as one 8-byte
+// run of Bt[n][k].  Sixteen consecutive lanes take consecutive k quads of one column block, so
+// each 16-lane group writes 128 contiguous bytes (no bank conflicts), while the four 16-lane
+// groups of a wavefront read 64 contiguous bytes of each of 16 B rows.
 // ---------------------------------------------------------------------------------------------
 constexpr int gemm_bf16_big_smem() { return 2 * (256 + 256) * 72 * 2; }
 
@@ -610,12 +612,12 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
   const int wm = wave >> 2, wn = wave & 3;
   const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
-  // A units: row ar + 64 j (j < 4), 8 k at ac.  B units: k pair bkp + 16 j (j < 2), 8 n at bc.
+  // A units: row ar + 64 j (j < 4), 8 k at ac.  B unit: k rows 4 bq .. 4 bq + 3, 8 n at bc.
   const int ar = tid >> 3, ac = (tid & 7) * 8;
-  const int bc = (wave * 4 + (lane & 3)) * 8, bkp = (lane >> 2) & 15;
+  const int bq = lane & 15, bc = (wave * 4 + (lane >> 4)) * 8;
   const uint16_t *pa = static_cast<const uint16_t *>(p.A) + int64_t(m0 + ar) * p.lda + ac;
-  const uint16_t *pb = static_cast<const uint16_t *>(p.B) + int64_t(2 * bkp) * p.ldb + n0 + bc;
-  const int64_t a_step = int64_t(64) * p.lda, b_pair = p.ldb, b_half = int64_t(32) * p.ldb;
+  const uint16_t *pb = static_cast<const uint16_t *>(p.B) + int64_t(4 * bq) * p.ldb + n0 + bc;
+  const int64_t a_step = int64_t(64) * p.lda, b_row = p.ldb;
 
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // one K step in flight
 #define PSC_BIG_LOAD(k0)                                                                         \
@@ -627,27 +629,26 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
     ra3 = *reinterpret_cast<const uint4 *>(qa_ + 3 * a_step);                                    \
     const uint16_t *qb_ = pb + int64_t(k0) * p.ldb;                                              \
     rb0 = *reinterpret_cast<const uint4 *>(qb_);                                                 \
-    rb1 = *reinterpret_cast<const uint4 *>(qb_ + b_pair);                                        \
-    rb2 = *reinterpret_cast<const uint4 *>(qb_ + b_half);                                        \
-    rb3 = *reinterpret_cast<const uint4 *>(qb_ + b_half + b_pair);                               \
+    rb1 = *reinterpret_cast<const uint4 *>(qb_ + b_row);                                         \
+    rb2 = *reinterpret_cast<const uint4 *>(qb_ + 2 * b_row);                                     \
+    rb3 = *reinterpret_cast<const uint4 *>(qb_ + 3 * b_row);                                     \
   } while (0)
-  auto store_b = [&](uint16_t *Bt, int kp, uint4 lo4, uint4 hi4) {
-    const uint32_t lo[4] = {lo4.x, lo4.y, lo4.z, lo4.w};
-    const uint32_t hi[4] = {hi4.x, hi4.y, hi4.z, hi4.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<uint32_t *>(&Bt[(bc + 2 * q) * KP + 2 * kp]) = (lo[q] & 0xffffu) | (hi[q] << 16);
-      *reinterpret_cast<uint32_t *>(&Bt[(bc + 2 * q + 1) * KP + 2 * kp]) = (lo[q] >> 16) | (hi[q] & 0xffff0000u);
-    }
-  };
   auto store = [&](uint16_t *buf) {
     uint16_t *As = buf + ar * KP + ac;
     *reinterpret_cast<uint4 *>(As) = ra0;
     *reinterpret_cast<uint4 *>(As + 64 * KP) = ra1;
     *reinterpret_cast<uint4 *>(As + 128 * KP) = ra2;
     *reinterpret_cast<uint4 *>(As + 192 * KP) = ra3;
-    store_b(buf + BM * KP, bkp, rb0, rb1);
-    store_b(buf + BM * KP, bkp + 16, rb2, rb3);
+    // column c of the block: (row 0, row 1) and (row 2, row 3) of that column, one 8-byte write
+    const uint32_t r0[4] = {rb0.x, rb0.y, rb0.z, rb0.w}, r1[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
+    const uint32_t r2[4] = {rb2.x, rb2.y, rb2.z, rb2.w}, r3[4] = {rb3.x, rb3.y, rb3.z, rb3.w};
+    uint16_t *Bt = buf + BM * KP + bc * KP + 4 * bq;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+      const u32x2 w = {__builtin_amdgcn_perm(r1[c >> 1], r0[c >> 1], sel), __builtin_amdgcn_perm(r3[c >> 1], r2[c >> 1], sel)};
+      *reinterpret_cast<u32x2 *>(Bt + c * KP) = w;
+    }
   };
 
   floatx4 acc[FM][FN];
