@@ -410,7 +410,8 @@ def kernels_main(a):
 
 def costmodel_main(a):
     """Learned cost model at full scale: ~20k op timings recorded by the runtime from random
-    layered DAGs (50-500 nodes, widths 1-16, dims 64-4096, FP32 or BF16), the MLP trained on the
+    layered DAGs (50-500 nodes, widths 1-16, dims 64-4096, FP32 or BF16; each op's time the median
+    of three runs), the MLP trained on the
     GPU, then on held-out DAGs: op-time error of the MLP vs the roofline heuristic, and the
     measured makespan of EFT schedules (4 streams) under each model, beside round robin."""
     import paper_2009_07482_amd as psc
@@ -428,7 +429,7 @@ def costmodel_main(a):
         else:
             spec = workloads.random_dag_spec(seed)
             inp = None
-        x, t = costmodel.record_samples(spec, inp, n_streams=(1, 2, 4, 8)[seed % 4], runs=1)
+        x, t = costmodel.record_samples(spec, inp, n_streams=(1, 2, 4, 8)[seed % 4], runs=3, reduce="median")
         xs.append(x)
         ts.append(t)
         seed += 1
@@ -447,7 +448,7 @@ def costmodel_main(a):
     e_mlp, e_heu = [], []
     for hs in range(1000, 1000 + a.heldout):
         spec = workloads.random_dag_spec(hs)
-        x, t = costmodel.record_samples(spec, None, n_streams=4, runs=1)
+        x, t = costmodel.record_samples(spec, None, n_streams=4, runs=3, reduce="median")
         if a.dump_samples:
             np.savez(a.dump_samples.replace(".npz", f"_heldout{hs}.npz"), X=x, T=t)
         e_mlp.append(costmodel.mape(cm.predict_us(x), t))

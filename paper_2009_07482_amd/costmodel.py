@@ -11,11 +11,13 @@ import numpy as np
 import paper_2009_07482_amd as psc
 
 
-def record_samples(spec, inputs=None, n_streams=4, mapper="rr", runs=2, device=0):
+def record_samples(spec, inputs=None, n_streams=4, mapper="rr", runs=2, device=0, reduce=None):
     """Run ``spec`` ``runs`` times (after one warm-up) with per-op timing; returns (X, t).
 
     With ``inputs`` (host arrays by name) the host copies run and are sampled too; without, the
-    data stays on the device and only kernels are sampled.
+    data stays on the device and only kernels are sampled.  ``reduce=None`` returns every run's
+    rows; ``reduce="median"`` one row per op with the median of its ``runs`` log-durations (single
+    event-timed runs under concurrency vary by ~0.23 in ln us between repeats).
     """
     r = psc.SpecRunner(spec, "fine", n_streams=n_streams, mapper=mapper, record_ops=True,
                        host_threads=1, device=device)
@@ -30,6 +32,12 @@ def record_samples(spec, inputs=None, n_streams=4, mapper="rr", runs=2, device=0
             x, t = r.samples()
             xs.append(x)
             ts.append(t)
+        if reduce == "median":
+            # the same ops do work in every run, in op order; only the busy-stream count may differ
+            assert all(len(x) == len(xs[0]) and np.array_equal(x[:, :11], xs[0][:, :11]) for x in xs)
+            X = xs[0].copy()
+            X[:, 11] = np.median(np.stack([x[:, 11] for x in xs]), axis=0)
+            return X, np.median(np.stack(ts), axis=0)
         return np.concatenate(xs), np.concatenate(ts)
     finally:
         r.close()

@@ -131,6 +131,9 @@ def test_samples_of_a_recorded_run():
     assert g[6] == 9 and g[9] == pytest.approx(np.log2(4 * (512 * 512 + 512 * 64 + 512 * 64)))
     Xd, _ = costmodel.record_samples(spec, None, n_streams=2, runs=1)
     assert Xd.shape == (57, F)   # device-resident: kernels only
+    # one row per op with the median over runs
+    Xm, tm = costmodel.record_samples(spec, None, n_streams=2, runs=3, reduce="median")
+    assert Xm.shape == (57, F) and np.array_equal(Xm[:, :11], Xd[:, :11]) and np.all(np.isfinite(tm))
 
 
 def _collect(seeds, dim=(64, 1024), nodes=(40, 120)):
