@@ -109,17 +109,19 @@ def test_batch64_full_size_sampled_instances():
 
 # --- psc_schedule_batch: separate DAGs, one schedule --------------------------------------------
 
-@pytest.mark.parametrize("kw", [dict(n_streams=4, mapper="component", mark_components=True),
-                                dict(n_streams=3, mapper="eft", use_graph=True),
-                                dict(n_streams=1)], ids=["eager", "graph-eft", "one-stream"])
-def test_schedule_batch_equals_separate_runs(kw):
+@pytest.mark.parametrize("policy,kw", [("fine", dict(n_streams=4, mapper="component", mark_components=True)),
+                                       ("fine", dict(n_streams=3, mapper="eft", use_graph=True)),
+                                       ("fine", dict(n_streams=1)), ("device", {})],
+                         ids=["eager", "graph-eft", "one-stream", "device"])
+def test_schedule_batch_equals_separate_runs(policy, kw):
     """Eight attention DAGs of uneven length, each with its own inputs, scheduled as one batch:
-    every output bit-identical to the DAG run alone, and within the FP32 bar of the oracle."""
+    every output within the FP32 bar of the oracle, and bit-identical to the DAG run alone on
+    streams (the device executor picks its own GEMM tiles, so its sums may round differently)."""
     d, heads, layers = 64, 2, 2
     specs = [workloads.mha_spec(n, d, heads, layers) for n in LENGTHS]
     inps = [workloads.mha_inputs(10 + i, n, d, layers) for i, n in enumerate(LENGTHS)]
-    print(f"schedule_batch {LENGTHS} {kw}", flush=True)
-    r = psc.BatchRunner(specs, "fine", **kw)
+    print(f"schedule_batch {LENGTHS} {policy} {kw}", flush=True)
+    r = psc.BatchRunner(specs, policy, **kw)
     try:
         r.set_inputs({f"{i}/{k}": v for i, inp in enumerate(inps) for k, v in inp.items()})
         r.run()
@@ -128,7 +130,8 @@ def test_schedule_batch_equals_separate_runs(kw):
             want = oracle_outputs(sp, inp)
             for name in workloads.host_outputs_of(sp):
                 got = r.result(f"{i}/{name}")
-                assert np.array_equal(got, alone[name]), (i, name)
+                if policy != "device":
+                    assert np.array_equal(got, alone[name]), (i, name)
                 assert normwise(got, want[name]) < 1e-4, (i, name)
         if kw.get("mark_components"):
             done = psc.psc_sched_component_times(r.sched)
