@@ -592,32 +592,38 @@ __device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {
 // v_mfma_f32_16x16x32_bf16, 128 accumulators per lane); two wavefronts per SIMD.  The next K
 // step's operands are loaded into registers while the current step is multiplied out of LDS; two
 // LDS buffers alternate, so each step needs one barrier.  Shapes are whole tiles (no edge guards,
-// no per-load branches), every load an offset from one per-thread base pointer.  A is staged as
-// As[m][k]; B is transposed in registers: each thread loads a 4 x 8 block (four k rows of eight
-// n), builds each column's four k values with two byte permutes and writes them as one 8-byte
-// run of Bt[n][k].  Sixteen consecutive lanes take consecutive k quads of one column block, so
-// each 16-lane group writes 128 contiguous bytes (no bank conflicts), while the four 16-lane
-// groups of a wavefront read 64 contiguous bytes of each of 16 B rows.
+// no per-load branches), every load an offset from one per-thread base pointer.
+// Both operands are staged as they lie in memory, with 16-byte copies: A as As[m][k] (pitch 72),
+// B as Bs[k][n] (pitch 272: eight consecutive rows start 32 bytes apart in the LDS banks).  The
+// matrix core needs, per lane, eight consecutive k of one B column; gfx950's transposing LDS read
+// (ds_read_b64_tr_b16) provides them: within each aligned group of 16 lanes, the 16 lanes' 4-wide
+// reads form a 16 x 4 matrix M and lane j receives M[j/4 + 4e][j%4], e < 4.  So when lane r of the
+// group reads the four columns 4 (r%4) .. 4 (r%4) + 3 of B row k0 + r/4, lane j gets
+// B[k0 + e][j] -- four consecutive k of column j; two such reads (k0 and k0 + 4) give the eight.
 // ---------------------------------------------------------------------------------------------
-constexpr int gemm_bf16_big_smem() { return 2 * (256 + 256) * 72 * 2; }
+constexpr int kBigKP = 72, kBigBP = 272;
+constexpr int gemm_bf16_big_smem() { return 2 * (256 * kBigKP + 64 * kBigBP) * 2; }
+
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 // Requires M % 256 == 0, N % 256 == 0, K % 64 == 0, 16-byte aligned operands and leading
 // dimensions that are multiples of 8 (the launch factory checks; other shapes use tile 4).
 template <bool OUT_BF16>
 __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, unsigned char *smem) {
-  constexpr int BM = 256, BN = 256, BK = 64, KP = 72, FM = 8, FN = 4;
+  constexpr int BM = 256, BK = 64, KP = kBigKP, BP = kBigBP, FM = 8, FN = 4;
+  constexpr int BUF = BM * KP + BK * BP;  // elements per LDS buffer
   uint16_t *const buf0 = reinterpret_cast<uint16_t *>(smem);
-  uint16_t *const buf1 = buf0 + (BM + BN) * KP;
+  uint16_t *const buf1 = buf0 + BUF;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // 8 wavefronts
   const int wm = wave >> 2, wn = wave & 3;
   const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
-  const int m0 = tm * BM, n0 = tn * BN;
-  // A units: row ar + 64 j (j < 4), 8 k at ac.  B unit: k rows 4 bq .. 4 bq + 3, 8 n at bc.
+  const int m0 = tm * BM, n0 = tn * 256;
+  // A units: row ar + 64 j (j < 4), 8 k at ac.  B units: k row br + 16 j (j < 4), 8 n at bc.
   const int ar = tid >> 3, ac = (tid & 7) * 8;
-  const int bq = lane & 15, bc = (wave * 4 + (lane >> 4)) * 8;
+  const int br = tid >> 5, bc = (tid & 31) * 8;
   const uint16_t *pa = static_cast<const uint16_t *>(p.A) + int64_t(m0 + ar) * p.lda + ac;
-  const uint16_t *pb = static_cast<const uint16_t *>(p.B) + int64_t(4 * bq) * p.ldb + n0 + bc;
-  const int64_t a_step = int64_t(64) * p.lda, b_row = p.ldb;
+  const uint16_t *pb = static_cast<const uint16_t *>(p.B) + int64_t(br) * p.ldb + n0 + bc;
+  const int64_t a_step = int64_t(64) * p.lda, b_step = int64_t(16) * p.ldb;
 
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // one K step in flight
 #define PSC_BIG_LOAD(k0)                                                                         \
@@ -629,9 +635,9 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
     ra3 = *reinterpret_cast<const uint4 *>(qa_ + 3 * a_step);                                    \
     const uint16_t *qb_ = pb + int64_t(k0) * p.ldb;                                              \
     rb0 = *reinterpret_cast<const uint4 *>(qb_);                                                 \
-    rb1 = *reinterpret_cast<const uint4 *>(qb_ + b_row);                                         \
-    rb2 = *reinterpret_cast<const uint4 *>(qb_ + 2 * b_row);                                     \
-    rb3 = *reinterpret_cast<const uint4 *>(qb_ + 3 * b_row);                                     \
+    rb1 = *reinterpret_cast<const uint4 *>(qb_ + b_step);                                        \
+    rb2 = *reinterpret_cast<const uint4 *>(qb_ + 2 * b_step);                                    \
+    rb3 = *reinterpret_cast<const uint4 *>(qb_ + 3 * b_step);                                    \
   } while (0)
   auto store = [&](uint16_t *buf) {
     uint16_t *As = buf + ar * KP + ac;
@@ -639,16 +645,11 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
     *reinterpret_cast<uint4 *>(As + 64 * KP) = ra1;
     *reinterpret_cast<uint4 *>(As + 128 * KP) = ra2;
     *reinterpret_cast<uint4 *>(As + 192 * KP) = ra3;
-    // column c of the block: (row 0, row 1) and (row 2, row 3) of that column, one 8-byte write
-    const uint32_t r0[4] = {rb0.x, rb0.y, rb0.z, rb0.w}, r1[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
-    const uint32_t r2[4] = {rb2.x, rb2.y, rb2.z, rb2.w}, r3[4] = {rb3.x, rb3.y, rb3.z, rb3.w};
-    uint16_t *Bt = buf + BM * KP + bc * KP + 4 * bq;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
-      const u32x2 w = {__builtin_amdgcn_perm(r1[c >> 1], r0[c >> 1], sel), __builtin_amdgcn_perm(r3[c >> 1], r2[c >> 1], sel)};
-      *reinterpret_cast<u32x2 *>(Bt + c * KP) = w;
-    }
+    uint16_t *Bs = buf + BM * KP + br * BP + bc;
+    *reinterpret_cast<uint4 *>(Bs) = rb0;
+    *reinterpret_cast<uint4 *>(Bs + 16 * BP) = rb1;
+    *reinterpret_cast<uint4 *>(Bs + 32 * BP) = rb2;
+    *reinterpret_cast<uint4 *>(Bs + 48 * BP) = rb3;
   };
 
   floatx4 acc[FM][FN];
@@ -656,15 +657,26 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // this lane's part of the transposing B reads: row 8 (lane / 16) + r / 4 of the slice, columns
+  // 4 (r % 4) .. + 3 of the 16-column block (r = lane % 16)
+  const int b_lane = (8 * (lane >> 4) + ((lane & 15) >> 2)) * BP + wn * 64 + 4 * (lane & 3);
   auto compute = [&](const uint16_t *buf) {
     const uint16_t *As = buf + (wm * 128 + (lane & 15)) * KP + 8 * (lane >> 4);
-    const uint16_t *Bt = buf + BM * KP + (wn * 64 + (lane & 15)) * KP + 8 * (lane >> 4);
+    const uint16_t *Bs = buf + BM * KP + b_lane;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       // all fragments of this 32-deep slice first, so the LDS latency is paid once per slice
       bf16x8 b[FN], a[FM];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(Bt + j * 16 * KP + kk);
+      for (int j = 0; j < FN; ++j) {
+        const uint16_t *q = Bs + kk * BP + j * 16;
+        const shortx4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) shortx4 *)(q));
+        const shortx4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) shortx4 *)(q + 4 * BP));
+        const short v[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        memcpy(&b[j], v, 16);
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(As + i * 16 * KP + kk);
 #pragma unroll
