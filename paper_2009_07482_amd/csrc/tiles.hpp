@@ -117,6 +117,11 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs &p, int bid, unsign
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int SA = ((BM + 63) / 64) * 64 + 16;  // pitch = 16 (mod 64) dwords
   constexpr int SB = ((BN + 63) / 64) * 64 + 16;
+  // A is written transposed (k-major), four k rows per float4: with the pitch above those rows
+  // start in the same banks, so A's column index is XOR-swizzled by the k row's group of four
+  // (bits 4-5): the four writes of a float4 land 16 banks apart, and a fragment read, whose
+  // lanes share k / 4, still covers 64 distinct banks.
+  auto swz = [](int k) { return ((k >> 2) & 3) << 4; };
   constexpr int UA = BM * (BK / 4), UB = BK * (BN / 4);  // float4 units per tile
   constexpr int NA = (UA + NT - 1) / NT, NB = (UB + NT - 1) / NT;
   float *As = reinterpret_cast<float *>(smem);  // k-major: As[k][m]
@@ -173,10 +178,10 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs &p, int bid, unsign
     for (int j = 0; j < NA; ++j) {
       const int u = tid + NT * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
       if (u < UA) {
-        As[(c + 0) * SA + r] = ra[j].x;
-        As[(c + 1) * SA + r] = ra[j].y;
-        As[(c + 2) * SA + r] = ra[j].z;
-        As[(c + 3) * SA + r] = ra[j].w;
+        As[(c + 0) * SA + (r ^ swz(c + 0))] = ra[j].x;
+        As[(c + 1) * SA + (r ^ swz(c + 1))] = ra[j].y;
+        As[(c + 2) * SA + (r ^ swz(c + 2))] = ra[j].z;
+        As[(c + 3) * SA + (r ^ swz(c + 3))] = ra[j].w;
       }
     }
 #pragma unroll
@@ -191,7 +196,7 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs &p, int bid, unsign
       const int k = kk + (lane >> 4);
       float a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[k * SA + wm * WM + i * 16 + (lane & 15)];
+      for (int i = 0; i < FM; ++i) a[i] = As[k * SA + ((wm * WM + i * 16 + (lane & 15)) ^ swz(k))];
 #pragma unroll
       for (int j = 0; j < FN; ++j) b[j] = Bs[k * SB + wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
