@@ -109,8 +109,11 @@ typedef struct psc_sched_opts {
                            forced to 1 by PSC_COARSE */
   int32_t mapper;       /* psc_mapper; used by PSC_FINE */
   int32_t copy_stream;  /* 0: copies on their kernel's stream (paper's enq rules);
-                           1: every H2D on one extra stream, enqueued before any kernel, so
-                              uploads overlap compute; D2H stays on its producer's stream */
+                           1: every H2D on one extra stream (index n_streams), enqueued before
+                              any kernel, so uploads overlap compute; every D2H on a second extra
+                              stream (index n_streams + 1, present when the DAG has isolated
+                              reads) after an event wait on its producer, so read-backs overlap
+                              the kernels that follow on the producer's stream */
   int32_t use_graph;    /* 1: psc_run builds the schedule as one hipGraph -- a node per op, an
                            edge per stream-order or wait precedence -- once (again when the host
                            pointers change) and launches it with hipGraphLaunch */
@@ -268,13 +271,16 @@ psc_status psc_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts
 psc_status psc_schedule_batch(psc_dag *const *dags, int32_t n, int32_t policy, const psc_sched_opts *opts,
                               psc_sched **out);
 
-/* Copies the schedule's ops (ordered by id) into ops[0..cap) and their waits into
+/* The command-queue structure of Def. 4 (Sec. III): per-queue op lists (stream, pos) and the
+ * cross-queue precedences (waits), for the schedule validator.
+ * Copies the schedule's ops (ordered by id) into ops[0..cap) and their waits into
  * waits[0..waits_cap); *n_ops / *n_waits receive the totals.  With ops == NULL or waits == NULL
  * only the totals are returned.  PSC_ERR_ARG if a capacity is too small. */
 psc_status psc_sched_export(const psc_sched *sched, psc_op *ops, int32_t cap, int32_t *n_ops,
                             int32_t *waits, int32_t waits_cap, int32_t *n_waits);
 
-/* Number of streams the schedule uses (n_streams, plus one with copy_stream). */
+/* Number of streams the schedule uses (n_streams, plus the upload and read-back streams of
+ * copy_stream). */
 psc_status psc_sched_streams(const psc_sched *sched, int32_t *n_streams);
 
 /* [GPU] Allocates device storage for every unbound root buffer (one arena), creates streams
@@ -282,7 +288,9 @@ psc_status psc_sched_streams(const psc_sched *sched, int32_t *n_streams);
  * Errors: PSC_ERR_HIP, PSC_ERR_OOM. */
 psc_status psc_sched_prepare(psc_sched *sched);
 
-/* [GPU] Runs the schedule once and waits for it: records a start event, enqueues every op in
+/* [GPU] The dispatch step of Algorithm 1 (Sec. IV-B): after setup_cq has built the queues, flush
+ * them to the device with their precedences and wait for completion.
+ * Runs the schedule once and waits for it: records a start event, enqueues every op in
  * host order (each wait as hipStreamWaitEvent on the producing op's event), joins all streams
  * and waits for the end event.  io[0..n_io) gives host memory for isolated writes / reads by
  * buffer name (see psc_host_io); buffers not listed are not copied.  stats may be NULL.

@@ -96,7 +96,7 @@ struct Op {
 struct SchedPlan {
   bool device = false;         // PSC_DEVICE: streams beyond 0 only describe precedences
   int32_t n_streams = 1;       // compute streams
-  int32_t total_streams = 1;   // + copy stream
+  int32_t total_streams = 1;   // + upload and read-back streams (copy_stream)
   std::vector<Op> ops;         // index = op id; host order = id order
   std::vector<int32_t> kernel_op;  // kernel id -> op id
 };

@@ -67,6 +67,11 @@ void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &ord
     if (is_h2d[b]) copy_features(g, b, true, 0, &feat[size_t(nk * S + b) * kFeatures]);
   std::vector<double> pred(size_t(nk * S + nb), 0.0);
   cost.predict_us(feat.data(), int64_t(pred.size()), pred.data());
+  // a learned model can return non-finite or negative times (an untrained or corrupt network);
+  // every comparison below would then fail silently, so the roofline heuristic takes over
+  bool usable = true;
+  for (double v : pred) usable = usable && std::isfinite(v) && v >= 0.0;
+  if (!usable) make_heuristic_cost()->predict_us(feat.data(), int64_t(pred.size()), pred.data());
   auto w = [&](int32_t k, int32_t j) { return pred[size_t(k * S + std::min(j, S - 1))]; };
   auto up_us = [&](int32_t b) { return pred[size_t(nk * S + b)]; };
   // bottom-level rank over a reverse topological order, with the uncontended durations
@@ -197,8 +202,13 @@ SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
   const int32_t S = policy == PSC_COARSE ? 1 : o.n_streams;
   plan.n_streams = S;
   const bool cs = policy != PSC_COARSE && o.copy_stream;
+  bool any_d2h = false;
+  for (const auto &v : g.iso_out) any_d2h = any_d2h || !v.empty();
+  // with copy streams: uploads on stream S, read-backs on stream S + 1 (the two directions use
+  // different DMA engines, and a read-back never holds up a later kernel of its producer's stream)
   const int32_t copy_s = cs ? S : -1;
-  plan.total_streams = S + (cs ? 1 : 0);
+  const int32_t read_s = cs && any_d2h ? S + 1 : -1;
+  plan.total_streams = S + (cs ? 1 : 0) + (read_s >= 0 ? 1 : 0);
 
   std::vector<int32_t> order, stream_of(nk, 0);
   if (policy == PSC_COARSE) {
@@ -248,7 +258,7 @@ SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
     for (int32_t b : g.iso_in[k]) d.push_back(h2d_op[b]);
     const int32_t kop = emit(PSC_OP_KERNEL, k, -1, s, d);
     plan.kernel_op[k] = kop;
-    for (int32_t b : g.iso_out[k]) emit(PSC_OP_D2H, -1, b, s, {kop});
+    for (int32_t b : g.iso_out[k]) emit(PSC_OP_D2H, -1, b, read_s >= 0 ? read_s : s, {kop});
   }
 
   // waits: vector clocks over streams; vc[i][t] = last position on stream t known to precede op i

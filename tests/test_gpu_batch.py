@@ -81,9 +81,9 @@ def test_batch_graph_equals_eager_bit_identical():
 
 
 @pytest.mark.timeout(900)
-def test_batch64_full_size_sampled_instances():
+def test_batch64_full_size_every_instance():
     """64 instances, n log-uniform in [64, 2048], d = 512, 8 heads, 6 layers, BF16 GEMMs, run as
-    one graph: the shortest, the longest and a median-length instance against the FP64 oracle."""
+    one graph: every instance's output against the FP64 oracle (normwise 2e-2)."""
     lengths = workloads.batch_lengths(0)
     d, heads, layers = 512, 8, 6
     spec = workloads.batch_spec(lengths, d, heads, layers, gemm_dtype="bf16")
@@ -96,14 +96,15 @@ def test_batch64_full_size_sampled_instances():
     print(f"makespan with copies {st['makespan_ms']:.2f} ms; instance completion p50 "
           f"{np.percentile(done, 50) / 1000:.2f} ms p99 {np.percentile(done, 99) / 1000:.2f} ms", flush=True)
     assert np.all(done > 0)
-    order = np.argsort(lengths)
-    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+    worst = 0.0
+    for i in range(len(lengths)):
         sub, sub_inp = _instance(lengths, i, d, heads, layers, "bf16", inp)
         want = oracle_outputs(sub, sub_inp)
         for name, w in want.items():
             err = normwise(r.result(name), w)
-            print(f"instance {i} n={lengths[i]}: normwise error {err:.2e}", flush=True)
-            assert err < 2e-2
+            worst = max(worst, err)
+            assert err < 2e-2, (i, lengths[i], err)
+    print(f"worst instance error {worst:.2e} over {len(lengths)} instances", flush=True)
     r.close()
 
 

@@ -155,15 +155,27 @@ def test_ragged_attention(n, d, h, layers, dt):
 @pytest.mark.parametrize("policy,kw", [("coarse", {}), ("fine", dict(n_streams=4, mapper="eft")), ("device", {})],
                          ids=["coarse", "fine-eft", "device"])
 def test_random_dags_against_oracle(policy, kw):
-    for seed in range(4):
+    """Random layered DAGs (seeds 0-7: six draw BF16, two FP32).  Every output against the exact
+    FP64 oracle (1e-4 FP32, 2e-2 BF16) and, for BF16, against the storage-emulating oracle, which
+    rounds exactly where the GPU stores: what is left there is FP32 accumulation order and the
+    rare rounding decision it flips, so the bar is 5e-3, below the ~4e-3 that BF16 storage
+    itself costs against the exact result on these DAGs."""
+    for seed in range(8):
         spec = workloads.random_dag_spec(seed, n_nodes=(20, 40), dim=(8, 160))
         inp = workloads.random_dag_inputs(seed, spec)
         ref = oracle_outputs(spec, inp)
-        if True:
-            out, _ = psc.run_spec(spec, inp, policy, **kw)
-            for name, want in ref.items():
-                tol = 1e-4 if spec["dtype"] == "f32" else 5e-2
-                assert normwise(out[name], want) < tol, (seed, policy, name)
+        emul = oracle_outputs(spec, inp, emulate=True) if spec["dtype"] == "bf16" else None
+        out, _ = psc.run_spec(spec, inp, policy, **kw)
+        worst = (0.0, 0.0)
+        for name, want in ref.items():
+            e = normwise(out[name], want)
+            assert e < (1e-4 if spec["dtype"] == "f32" else 2e-2), (seed, policy, name, e)
+            if emul is not None:
+                e2 = normwise(out[name], emul[name])
+                assert e2 < 5e-3, (seed, policy, name, e2)
+                worst = (max(worst[0], e), max(worst[1], e2))
+        print(f"seed {seed} {spec['dtype']}: worst error vs exact {worst[0]:.2e}, vs emulating {worst[1]:.2e}",
+              flush=True)
 
 
 def test_io_errors():
@@ -208,21 +220,43 @@ def test_device_executor_node_times_respect_dependencies():
         assert t[s_][1] <= t[d_][0] + 1e-3, (s_, d_, t[s_], t[d_])
 
 
-@pytest.mark.timeout(900)
-def test_mha_12_layers_bf16_full_size():
-    # 12 stacked layers, 16 heads, d_model = n = 1024, BF16 GEMM operands with FP32 accumulation,
-    # FP32 softmax; fine schedule with a copy stream overlapping the weight uploads.  Every
-    # layer's output is compared with the exact FP64 oracle (normwise relative error < 2e-2).
+@pytest.fixture(scope="module")
+def mha12():
+    """12 stacked layers, 16 heads, d_model = n = 1024, BF16 GEMM operands (FP32 accumulation),
+    FP32 softmax: the last layer's output from the exact and the storage-emulating oracle."""
     n, d, h, L = 1024, 1024, 16, 12
     spec = workloads.mha_spec(n, d, h, L, gemm_dtype="bf16")
     inp = workloads.mha_inputs(0, n, d, L)
-    r = psc.SpecRunner(spec, "fine", n_streams=4, mapper="component", copy_stream=True)
+    y = f"Y{L - 1}"
+    exact = odag.read_buffer(spec, odag.run_dag(spec, inp), y)
+    emul = odag.read_buffer(spec, odag.run_dag(spec, inp, emulate=True), y)
+    return spec, inp, y, exact, emul, {}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("policy,kw", [("coarse", {}), ("fine", dict(n_streams=4, mapper="rr")),
+                                       ("fine", dict(n_streams=4, mapper="component", copy_stream=True)),
+                                       ("device", {})],
+                         ids=["coarse", "fine-rr", "fine-component-copystream", "device"])
+def test_mha_12_layers_bf16_full_size(mha12, policy, kw):
+    """The full-size 12-layer DAG under each schedule: the final output Y11 (the only isolated
+    read; intermediate layers stay on the device) within 2e-2 of the exact FP64 oracle and within
+    5e-3 of the storage-emulating oracle; the stream schedules bit-identical to each other (same
+    kernels, no atomics, fixed reduction order).  The device executor picks its own GEMM tiles,
+    so it is held to the oracles only."""
+    spec, inp, y, exact, emul, seen = mha12
+    print(f"mha 12x1024 bf16 {policy} {kw}", flush=True)
+    r = psc.SpecRunner(spec, policy, **kw)
     r.set_inputs(inp)
     st = r.run()
-    got = r.result(f"Y{L - 1}")
+    got = r.result(y)
     r.close()
-    print(f"makespan with copies {st['makespan_ms']:.3f} ms", flush=True)
-    ref = dag_outputs = odag.run_dag(spec, inp)
-    err = normwise(got, odag.read_buffer(spec, ref, f"Y{L - 1}"))
-    print(f"Y{L - 1}: normwise relative error vs FP64 oracle {err:.3e}", flush=True)
-    assert err < 2e-2
+    e1, e2 = normwise(got, exact), normwise(got, emul)
+    print(f"makespan with copies {st['makespan_ms']:.3f} ms; {y} error vs exact {e1:.3e}, "
+          f"vs emulating {e2:.3e}", flush=True)
+    assert e1 < 2e-2 and e2 < 5e-3
+    if policy != "device":
+        if "streams" in seen:
+            np.testing.assert_array_equal(got, seen["streams"])
+        else:
+            seen["streams"] = got

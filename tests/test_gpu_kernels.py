@@ -87,9 +87,13 @@ def test_softmax(r, c, idt, odt):
     x = (np.random.default_rng(8).standard_normal((r, c)) * 3).astype(np.float32)
     got = _run(spec, {"A": x})
     exact = oracle_outputs(spec, {"A": x})["C"]
-    tol = 1e-5 if (idt, odt) == ("f32", "f32") else 2e-2
-    ref = exact if idt == "f32" else oracle_outputs(spec, {"A": x}, emulate=True)["C"]
-    assert normwise(got, ref) < tol
+    emul = oracle_outputs(spec, {"A": x}, emulate=True)["C"]
+    # the emulating oracle rounds the BF16 input as the host does and the output to its dtype;
+    # what remains is FP32 exponentials and sums (~1e-7) and, for BF16 output, the rare rounding
+    # decision they flip
+    assert normwise(got, emul) < (1e-5 if odt == "f32" else 1e-3)
+    if idt == "f32":
+        assert normwise(got, exact) < (1e-5 if odt == "f32" else 2e-2)
     np.testing.assert_allclose(got.astype(np.float64).sum(axis=1), 1.0, atol=1e-5 if odt == "f32" else 1e-2 * max(1, c / 512))
 
 

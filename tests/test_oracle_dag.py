@@ -130,3 +130,55 @@ def test_spec_counts_match_structure():
     spec12 = workloads.mha_spec(1024, 1024, 16, 12, "bf16")
     assert len(spec12["kernels"]) == 12 * 113
     assert workloads.spec_flops(spec12) == pytest.approx(154.6e9, rel=1e-3)
+
+
+def _bf16_chain_spec():
+    b = lambda name, dt, view_of=None: {"name": name, "dtype": dt, "rows": 2, "cols": 2, "view_of": view_of,
+                                        "row_off": 0, "col_off": 0}
+    return {"buffers": [b("A", "bf16"), b("B", "bf16"), b("C", "bf16"), b("D", "bf16"), b("E", "f32")],
+            "kernels": [{"name": "k0", "kind": "gemm", "inputs": ["A", "B"], "outputs": ["C"], "alpha": 1.0},
+                        {"name": "k1", "kind": "gemm", "inputs": ["C", "D"], "outputs": ["E"], "alpha": 1.0}],
+            "edges": [(0, "C", 1, "C")], "component": [0, 0]}
+
+
+def test_emulate_mode_hand_example(golden_dir):
+    """A two-GEMM chain worked by hand (tests/golden/bf16_chain_emulate.json): host BF16 inputs
+    rounded with a tie to even, the stored BF16 intermediate rounded visibly, the FP32 output
+    dropping a term below its grid step.  Not rounding the host inputs changes C11, not rounding
+    C changes E00, rounding E to BF16 changes E00, a transposed operand changes every entry."""
+    import json
+    import os
+    with open(os.path.join(golden_dir, "bf16_chain_emulate.json")) as fh:
+        gold = json.load(fh)
+    spec = _bf16_chain_spec()
+    inp = {k: np.array(v, np.float32) for k, v in gold["inputs"].items()}
+    for k, v in gold["inputs"].items():
+        assert np.array_equal(inp[k].astype(np.float64), np.array(v))   # the inputs are float32 values
+    for emulate, key in ((True, "expected_emulate"), (False, "expected_exact")):
+        st = dag.run_dag(spec, inp, emulate=emulate)
+        for name in ("C", "E"):
+            np.testing.assert_array_equal(st[name], np.array(gold[key][name]), err_msg=f"{key} {name}")
+
+
+def test_emulate_mode_rounds_view_windows_in_place():
+    """BF16 outputs written into column windows of one buffer are rounded where they land, and the
+    rest of the parent keeps what other kernels wrote (a 1 x 4 parent, two 1 x 2 windows)."""
+    bufs = [{"name": "a", "dtype": "bf16", "rows": 1, "cols": 1, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "w", "dtype": "bf16", "rows": 1, "cols": 4, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "w0", "dtype": "bf16", "rows": 1, "cols": 2, "view_of": "w", "row_off": 0, "col_off": 0},
+            {"name": "w1", "dtype": "bf16", "rows": 1, "cols": 2, "view_of": "w", "row_off": 0, "col_off": 2},
+            {"name": "o", "dtype": "bf16", "rows": 1, "cols": 4, "view_of": None, "row_off": 0, "col_off": 0},
+            {"name": "o0", "dtype": "bf16", "rows": 1, "cols": 2, "view_of": "o", "row_off": 0, "col_off": 0},
+            {"name": "o1", "dtype": "bf16", "rows": 1, "cols": 2, "view_of": "o", "row_off": 0, "col_off": 2}]
+    kers = [{"name": "g0", "kind": "gemm", "inputs": ["a", "w0"], "outputs": ["o0"], "alpha": 1.0},
+            {"name": "g1", "kind": "gemm", "inputs": ["a", "w1"], "outputs": ["o1"], "alpha": 1.0}]
+    spec = {"buffers": bufs, "kernels": kers, "edges": [], "component": [0, 0]}
+    # a = 3; w = [1, 1 + 2^-7, 1 + 2^-6, 2^-8]: 3 * (1 + 2^-7) = 3 + 3 * 2^-7 lies in [2, 4), where
+    # the bfloat16 step is 2^-6, so it is 3 + 1.5 * 2^-6 -> tie -> 3 + 2 * 2^-6 = 3.03125;
+    # 3 * (1 + 2^-6) = 3.046875 = 3 + 3 * 2^-6 is exact; 3 * 2^-8 = 0.01171875 is exact.
+    inp = {"a": np.array([[3.0]], np.float32),
+           "w": np.array([[1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -6, 2.0 ** -8]], np.float32)}
+    st = dag.run_dag(spec, inp, emulate=True)
+    np.testing.assert_array_equal(st["o"], [[3.0, 3.03125, 3.046875, 0.01171875]])
+    st = dag.run_dag(spec, inp)
+    np.testing.assert_array_equal(st["o"], [[3.0, 3.0 + 3 * 2.0 ** -7, 3.046875, 0.01171875]])

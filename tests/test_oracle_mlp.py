@@ -82,3 +82,33 @@ def test_training_reduces_loss():
         y, c = mlp.forward(p, x)
         p, m, v = mlp.adam_step(p, mlp.backward(p, c, y, t), m, v, step, lr=1e-2)
     assert mlp.loss(mlp.forward(p, x)[0], t) < 0.2 * l0
+
+
+def test_adam_two_steps_closed_form():
+    """Two Adam steps on one scalar parameter, worked by hand (Kingma and Ba, 2015, Algorithm 1).
+    beta1 = 1/2, beta2 = 3/4, lr = 0.1, eps = 0, gradients g1 = 2 then g2 = 1:
+      step 1: m1 = (1/2) 2 = 1, v1 = (1/4) 4 = 1, m^ = 1 / (1 - 1/2) = 2, v^ = 1 / (1 - 3/4) = 4,
+              theta1 = theta0 - 0.1 * 2 / 2 = theta0 - 0.1;
+      step 2: m2 = (1/2) 1 + (1/2) 1 = 1, v2 = (3/4) 1 + (1/4) 1 = 1,
+              m^ = 1 / (1 - 1/4) = 4/3, v^ = 1 / (1 - 9/16) = 16/7,
+              theta2 = theta1 - 0.1 * (4/3) / (4 / sqrt 7) = theta1 - 0.1 sqrt(7) / 3.
+    A bias correction left at beta^1 on step 2 would give m^ = 2, v^ = 4 and theta2 = theta1 - 0.1;
+    moments without their (1 - beta) weights, or v from g instead of g^2, change step 1 already."""
+    p0 = {k: np.full(s, 0.5) for k, s in (("W1", (1, 1)), ("b1", (1,)), ("W2", (1, 1)), ("b2", (1,)),
+                                          ("W3", (1, 1)), ("b3", (1,)))}
+    g1 = {k: np.full_like(v, 2.0) for k, v in p0.items()}
+    g2 = {k: np.full_like(v, 1.0) for k, v in p0.items()}
+    kw = dict(lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    p1, m1, v1 = mlp.adam_step(p0, g1, mlp.zeros_like(p0), mlp.zeros_like(p0), 1, **kw)
+    p2, m2, v2 = mlp.adam_step(p1, g2, m1, v1, 2, **kw)
+    for k in mlp.NAMES:
+        assert m1[k].item() == 1.0 and v1[k].item() == 1.0
+        assert p1[k].item() == 0.5 - 0.1
+        assert m2[k].item() == 1.0 and v2[k].item() == 1.0
+        np.testing.assert_allclose(p2[k].item(), 0.4 - 0.1 * np.sqrt(7.0) / 3.0, rtol=1e-15)
+    # default hyper-parameters, equal gradients: both bias-corrected moments equal g and g^2 at
+    # every step, so each step moves by lr * g / (|g| + eps)
+    q1, a1, b1 = mlp.adam_step(p0, g2, mlp.zeros_like(p0), mlp.zeros_like(p0), 1, lr=1e-3)
+    q2, _, _ = mlp.adam_step(q1, g2, a1, b1, 2, lr=1e-3)
+    for k in mlp.NAMES:
+        np.testing.assert_allclose(q2[k].item(), 0.5 - 2e-3 / (1.0 + 1e-8), rtol=1e-14)
