@@ -1,23 +1,28 @@
 """Benchmark: makespan and inferences/s of the attention DAG under coarse- and fine-grained
-schedules on one MI355X, with a roofline figure for the dominant kernel and the CPU oracle's
-throughput beside it.
+schedules on one MI355X, BF16 beside FP32, with a roofline figure for the dominant kernel and the
+CPU oracle's throughput beside it.
 
-Default workload (--config mha512): one multi-head attention layer, n = d = 512, 8 heads of
-dim 64, FP32: 57 kernels (per head three projection GEMMs, a transpose, the score GEMM, a row
-softmax and the P*V GEMM; then the output projection).  --config mha1024x12: 12 stacked layers,
-16 heads, n = d = 1024, BF16 GEMM operands (1,356 kernels).  A step is one pass of the whole DAG
-over device-resident inputs -- every kernel enqueued on the schedule's streams with its event
-waits, then a join.  ``value`` is inferences/s of the fine-grained schedule: the clustering scheme
-of Sec. V (each head's kernels one task component, components on 4 HIP streams, each stream
-enqueued by its own host thread).  GEMM tiles are chosen by the autotuner first (--no-tune: size
-heuristic).
+Default workload (--config mha1024x12): 12 stacked multi-head attention layers, n = d_model = 1024,
+16 heads of dim 64, BF16 GEMM operands with FP32 accumulation, FP32 softmax input (1,356 kernels:
+per layer and head three projection GEMMs, a transpose, the score GEMM, a row softmax and the P*V
+GEMM; then the output projection).  A step is one pass of the whole DAG over device-resident inputs
+(``value``); the makespan from the first upload to the last read-back (inputs and weights from
+page-locked memory) is reported beside it for every schedule.  ``value`` is inferences/s of the
+fine-grained schedule the schedule autotuner picks among stream counts, mappers (clustering: one
+task component per head on a stream; round robin), enqueue threads and the two dispatchers (AQL
+packets on the GPU's own HSA queues with barrier-AND packets on completion signals, or HIP streams
+and events).  The coarse schedule (one in-order queue) is timed with both dispatchers; the device
+executor (one persistent kernel) is reported as a separate row, never as ``value``.  The same DAG
+with FP32 GEMMs is timed after it (``fp32_same_dag``).  GEMM tiles are autotuned first.
 
+--config mha512: one layer, n = d = 512, 8 heads, FP32 (57 kernels).
 --config kernels: standalone softmax / transpose / add against HBM bandwidth and GEMMs against the
 matrix-core peak, at large sizes.
 --config batch64: 64 instances of log-uniform length, 6 layers, BF16 (21,888 kernels), inferences/s
 and per-instance latency p50/p99, eager streams vs one hipGraph, untuned vs autotuned.
+--config costmodel: the learned cost model at full scale.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha512|mha1024x12|batch64|forkjoin]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mha1024x12|mha512|batch64|kernels|costmodel]
 """
 import argparse
 import json
@@ -38,7 +43,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
-    p.add_argument("--config", default="mha512")
+    p.add_argument("--config", default="mha1024x12")
+    p.add_argument("--no-fp32", action="store_true", help="skip the FP32 run of the 12-layer DAG")
     p.add_argument("--streams", type=int, default=4)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
@@ -52,17 +58,15 @@ def parse():
     p.add_argument("--kernel-profile", choices=["dominant", "executor"], default=None,
                    help="launch sequence for rocprofv3 counter runs (no timing line): the dominant "
                         "kernel of the stream schedule, or the device executor, then a calibration copy")
-    p.add_argument("--schedule", choices=["auto", "streams", "device"], default="auto",
-                   help="fine-grained schedule reported: the faster of the two (auto) or a fixed one")
     p.add_argument("--profile-tile", type=int, default=0,
                    help="with --kernel-profile: GEMM tile of the shape --profile-shape (0 = autotune)")
     p.add_argument("--profile-shape", default="512x64x512", help="MxNxK pinned by --profile-tile")
     a = p.parse_args()
     big = a.config in ("mha1024x12", "batch64")
     if a.steps is None:
-        a.steps = {"mha1024x12": 20, "batch64": 5}.get(a.config, 300)
+        a.steps = {"mha1024x12": 50, "batch64": 5}.get(a.config, 300)
     if a.warmup is None:
-        a.warmup = 2 if a.config == "batch64" else (3 if big else 30)
+        a.warmup = 2 if a.config == "batch64" else (5 if big else 30)
     return a
 
 
@@ -280,25 +284,6 @@ def stored_traffic(kernel_key, tile):
             except (KeyError, ValueError):
                 return None
     return None
-
-
-def executor_roofline(spec, r):
-    """The device executor is one kernel per step: its achieved rate is the DAG's GEMM FLOPs over
-    the median GPU time of a device-resident run (HIP events around the executor's reset and
-    main kernels on its stream)."""
-    import workloads
-    dts = {k["inputs"][0] for k in spec["kernels"] if k["kind"] == "gemm"}
-    by = {b["name"]: b for b in spec["buffers"]}
-    bf16 = any(by[n]["dtype"] == "bf16" for n in dts)
-    flops = workloads.spec_flops(spec)
-    t = r["makespan_ms_median"] * 1e-3
-    peak = PEAK["mfma_bf16"] if bf16 else PEAK["mfma_f32"]
-    return {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": flops / t / peak, "traffic": None, "kernel": "exec_kernel (whole DAG, one launch)",
-            "avg_us": t * 1e6, "launches_per_step": 1, "work_per_launch": flops,
-            "timing": "median of the timed steps, HIP events around the executor's reset and main kernels",
-            "traffic_note": "bytes of the whole DAG's data movement inside the one kernel"} | \
-        {"traffic": stored_traffic("exec_kernel (whole DAG, one launch)", None)}
 
 
 def environment():
@@ -592,10 +577,96 @@ def batch_cpu_baseline(lengths, d, h, L, inp, seconds):
                       f"scaled to the batch by FLOPs"}
 
 
+FINE_CANDIDATES = [dict(n_streams=s_, mapper=m_, host_threads=t_, dispatch=d_)
+                   for d_ in ("aql", "hip") for s_ in (2, 4, 8, 16) for m_ in ("component", "rr") for t_ in (1, 0)]
+
+
+def measure_runner(r, steps, warmup, copies_runs=5):
+    """Device-resident timing (the value) and the PCIe-inclusive makespan (inputs uploaded and the
+    output read back inside the run, from page-locked memory: first H2D to last D2H)."""
+    io = [r.run()["makespan_ms"] for _ in range(copies_runs)]
+    wall, mk, st = timed(r, steps, warmup)
+    return {"ms_per_step": wall / steps * 1e3, "makespan_ms_median": float(np.median(mk)),
+            "makespan_ms_p5": float(np.percentile(mk, 5)), "makespan_ms_p95": float(np.percentile(mk, 95)),
+            "host_enqueue_ms": st["host_enqueue_ms"], "makespan_with_copies_ms": float(np.median(io)),
+            "n_waits": st["n_waits"], "n_streams": st["n_streams"], "aql_packets": st["aql_packets"]}
+
+
+def describe(opts):
+    if opts is None:
+        return "device executor (one persistent kernel)"
+    how = ("AQL packets on HSA queues, barrier-AND packets on completion signals"
+           if opts.get("dispatch") == "aql" else "HIP streams and events")
+    if opts.get("n_streams", 1) == 1 and not opts.get("mapper"):
+        return f"coarse: one in-order queue ({how})"
+    m = {"component": "clustering (one task component per head per stream)", "rr": "round robin per kernel",
+         "eft": "EFT list scheduling"}[opts.get("mapper", "rr")]
+    th = "one enqueue thread" if opts.get("host_threads") == 1 else "one enqueue thread per stream"
+    return f"fine: {opts['n_streams']} streams, {m}, {th}; {how}"
+
+
+def dag_bench(spec, inp, a, tune=True, with_device=True, label=""):
+    """Coarse (both dispatchers), the autotuned fine schedule, the best HIP-stream fine schedule
+    and the device executor on one DAG; returns (results, fine opts, runners kept for the roofline)."""
+    import paper_2009_07482_amd as psc
+    tuned = 0
+    if tune and not a.no_tune:
+        d0 = psc.build_dag(spec)
+        tuned = psc.psc_autotune_dag(d0, iters=20)
+        psc.psc_dag_destroy(d0)
+    d1 = psc.build_dag(spec)
+    bi, cms = psc.psc_autotune_schedule(d1, "fine", FINE_CANDIDATES, iters=max(5, a.steps // 4))
+    psc.psc_dag_destroy(d1)
+    fine_opts = FINE_CANDIDATES[bi]
+    hip_idx = [i for i, c in enumerate(FINE_CANDIDATES) if c["dispatch"] == "hip"]
+    hip_opts = FINE_CANDIDATES[min(hip_idx, key=lambda i: cms[i] if cms[i] > 0 else 1e30)]
+    print(f"# {label} schedule autotuner: chose {fine_opts} ({cms[bi]:.3f} ms/run); " +
+          ", ".join(f"{c['dispatch']}/{c['n_streams']}/{c['mapper'][0]}/{'1t' if c['host_threads'] == 1 else 'mt'}={m:.3f}"
+                    for c, m in zip(FINE_CANDIDATES, cms)), file=sys.stderr, flush=True)
+    plan = {"coarse_hip": ("coarse", dict(dispatch="hip")), "coarse_aql": ("coarse", dict(dispatch="aql")),
+            "fine": ("fine", fine_opts), "fine_hip": ("fine", hip_opts)}
+    if with_device:
+        plan["device_executor"] = ("device", {})
+    res, keep = {}, {}
+    for name, (policy, kw) in plan.items():
+        r = psc.SpecRunner(spec, policy, **kw)
+        r.set_inputs(inp)
+        res[name] = measure_runner(r, a.steps, a.warmup)
+        res[name]["schedule"] = describe(kw if policy != "device" else None) if policy != "coarse" else describe(dict(kw, n_streams=1))
+        print(f"# {label} {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
+        if name == "fine":
+            keep[name] = r
+        else:
+            r.close()
+    res["coarse"] = min((res["coarse_hip"], res["coarse_aql"]), key=lambda v: v["ms_per_step"])
+    return res, fine_opts, keep, tuned
+
+
+def kernel_timeline(spec, inp, opts):
+    """Kernels in flight and per-class in-DAG durations from one recorded run of the fine schedule
+    (AQL: the queues' profiler timestamps; HIP: event pairs)."""
+    import paper_2009_07482_amd as psc
+    rec = psc.SpecRunner(spec, "fine", record_ops=True, **opts)
+    rec.set_inputs(inp)
+    rec.run()
+    rec.run(with_inputs=False, with_outputs=False)
+    times = psc.psc_sched_op_times(rec.sched)
+    ops = psc.psc_sched_export(rec.sched)
+    rec.close()
+    kern = [t for t, o in zip(times, ops) if o["type"] == "kernel" and t[3] > t[2]]
+    by_class = {}
+    for t, o in zip(times, ops):
+        if o["type"] == "kernel" and t[3] > t[2]:
+            key = kernel_class(spec, o["kernel"])[0]
+            by_class.setdefault(key, []).append(t[3] - t[2])
+    return overlap(kern), {k: float(np.mean(v)) for k, v in by_class.items()}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "the executor runs on one GPU; --gpus must be 1 (the sharded design is described, not built)"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (how the DAG would shard is "
+                                   "described in the design notes, not built)"}))
         sys.exit(2)
     import paper_2009_07482_amd as psc
 
@@ -612,100 +683,48 @@ def main():
         kernel_profile(a)
         return
     spec, inp, desc = workload(a.config)
-    tuned = 0
-    if not a.no_tune:
-        d0 = psc.build_dag(spec)
-        tuned = psc.psc_autotune_dag(d0, iters=20)
-        psc.psc_dag_destroy(d0)
-
-    S = a.streams
-    # schedule autotuner: stream count, mapper and enqueue threads of the fine schedule
-    cands = [dict(n_streams=s_, mapper=m_, host_threads=t_) for s_ in (2, 4, 8) for m_ in ("component", "rr")
-             for t_ in (1, 0)]
-    d1 = psc.build_dag(spec)
-    bi, cms = psc.psc_autotune_schedule(d1, "fine", cands, iters=max(5, a.steps // 10))
-    psc.psc_dag_destroy(d1)
-    fine_opts = cands[bi]
-    print(f"# schedule autotuner: chose {fine_opts} ({cms[bi]:.3f} ms/run) among "
-          + ", ".join(f"{c['n_streams']}/{c['mapper']}/{'1t' if c['host_threads'] == 1 else 'mt'}={m:.3f}"
-                      for c, m in zip(cands, cms)), file=sys.stderr, flush=True)
-    runners = {
-        "coarse": psc.SpecRunner(spec, "coarse"),
-        "fine_streams": psc.SpecRunner(spec, "fine", **fine_opts),
-        "device": psc.SpecRunner(spec, "device"),
-    }
-    if a.variants:
-        runners.update({
-            "fine_1thread": psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", host_threads=1),
-            "fine_rr": psc.SpecRunner(spec, "fine", n_streams=S, mapper="rr"),
-            "fine_eft": psc.SpecRunner(spec, "fine", n_streams=S, mapper="eft"),
-            "fine_8streams": psc.SpecRunner(spec, "fine", n_streams=8, mapper="component"),
-            "fine_copystream": psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", copy_stream=True),
-        })
-    if a.graph:
-        runners["fine_graph"] = psc.SpecRunner(spec, "fine", n_streams=S, mapper="component", use_graph=True)
-    res = {}
-    for name, r in runners.items():
-        r.set_inputs(inp)
-        st_io = r.run()                      # uploads inputs; PCIe-inclusive makespan
-        for _ in range(2):
-            st_io = r.run()
-        wall, mk, st = timed(r, a.steps, a.warmup)
-        res[name] = {"ms_per_step": wall / a.steps * 1e3, "makespan_ms_median": float(np.median(mk)),
-                     "makespan_ms_p5": float(np.percentile(mk, 5)), "makespan_ms_p95": float(np.percentile(mk, 95)),
-                     "host_enqueue_ms": st["host_enqueue_ms"], "makespan_with_copies_ms": st_io["makespan_ms"],
-                     "n_waits": st["n_waits"], "n_streams": st["n_streams"]}
-        print(f"# {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
-
-    # the fine-grained schedule: the faster of the best stream schedule and the device executor
-    if a.schedule == "auto":
-        best_fine = min(("fine_streams", "device"), key=lambda k: res[k]["ms_per_step"])
-    else:
-        best_fine = "fine_streams" if a.schedule == "streams" else "device"
-    res["fine"] = res[best_fine]
-    if best_fine == "device":
-        roof = executor_roofline(spec, res["device"])
-    else:
-        roof = dominant_roofline(spec, runners["fine_streams"], a.kernel_iters)
-
-    # concurrency of the stream schedule from a per-op timeline (start/end events around every op)
-    rec = psc.SpecRunner(spec, "fine", record_ops=True, **fine_opts)
-    rec.set_inputs(inp)
-    rec.run()
-    rec.run(with_inputs=False, with_outputs=False)
-    concurrency = overlap(psc.psc_sched_op_times(rec.sched))
-    rec.close()
-
+    res, fine_opts, keep, tuned = dag_bench(spec, inp, a, label=desc.get("gemm_dtype", ""))
     fine = res["fine"]
-    streams_desc = (f"{fine_opts['n_streams']} HIP streams, "
-                    f"{'clustering (one task component per head per stream)' if fine_opts['mapper'] == 'component' else 'round robin per kernel'}, "
-                    f"{'one enqueue thread' if fine_opts['host_threads'] == 1 else 'one enqueue thread per stream'}")
-    if best_fine == "device":
-        schedule_desc = ("fine, device executor: one persistent kernel runs every kernel's tiles from host-planned "
-                         "per-workgroup lists with per-kernel completion counters (faster than the best stream "
-                         f"schedule, {streams_desc})")
-    else:
-        schedule_desc = f"fine, chosen by the schedule autotuner: {streams_desc}"
+    roof = dominant_roofline(spec, keep["fine"], a.kernel_iters)
+    keep["fine"].close()
+    in_flight, in_dag_us = kernel_timeline(spec, inp, fine_opts)
+    roof["in_dag_avg_us"] = in_dag_us.get(roof["kernel"])
     line = {
         "metric": "DAG makespan (ms) + inferences/s, fine vs coarse schedule, BF16 vs FP32",
         "value": 1e3 / fine["ms_per_step"], "unit": "inferences/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": fine["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": desc.get("gemm_dtype", "f32"),
         "data": "synthetic (seeded N(0,1) inputs, N(0,1/d) weights)",
-        "config": dict(desc, schedule=schedule_desc, inputs="device-resident",
+        "config": dict(desc, schedule=fine["schedule"], inputs="device-resident",
                        gemm_tiles="autotuned" if tuned else "size heuristic"),
         "makespan_ms": {k: v["makespan_ms_median"] for k, v in res.items()},
         "ms_per_step_by_schedule": {k: v["ms_per_step"] for k, v in res.items()},
         "makespan_with_copies_ms": {k: v["makespan_with_copies_ms"] for k, v in res.items()},
+        "schedules": {k: v["schedule"] for k, v in res.items()},
         "fine_vs_coarse_speedup": res["coarse"]["ms_per_step"] / fine["ms_per_step"],
-        "fine_streams_mean_ops_in_flight": concurrency,
+        "fine_vs_coarse_speedup_same_dispatch": {
+            "hip": res["coarse_hip"]["ms_per_step"] / res["fine_hip"]["ms_per_step"],
+            "aql": res["coarse_aql"]["ms_per_step"] / fine["ms_per_step"] if fine_opts["dispatch"] == "aql" else None},
+        "fine_kernels_in_flight_mean": in_flight,
         "dag_bound_us": dag_bound_us(spec),
         "makespan_over_dag_bound": fine["makespan_ms_median"] * 1e3 / dag_bound_us(spec),
         "roofline": roof,
         "environment": environment(),
     }
-    for r in runners.values():
-        r.close()
+    if a.config == "mha1024x12" and not a.no_fp32:
+        # the same DAG with FP32 GEMMs (and FP32 storage throughout): the other half of the metric
+        import workloads
+        spec32 = workloads.mha_spec(1024, 1024, 16, 12, gemm_dtype="f32")
+        res32, opts32, keep32, _ = dag_bench(spec32, inp, a, with_device=False, label="f32")
+        keep32["fine"].close()
+        line["fp32_same_dag"] = {
+            "inferences_per_s": 1e3 / res32["fine"]["ms_per_step"],
+            "makespan_ms": {k: v["makespan_ms_median"] for k, v in res32.items()},
+            "ms_per_step_by_schedule": {k: v["ms_per_step"] for k, v in res32.items()},
+            "makespan_with_copies_ms": {k: v["makespan_with_copies_ms"] for k, v in res32.items()},
+            "schedule": res32["fine"]["schedule"],
+            "fine_vs_coarse_speedup": res32["coarse"]["ms_per_step"] / res32["fine"]["ms_per_step"]}
+        line["bf16_vs_fp32_speedup"] = res32["fine"]["ms_per_step"] / fine["ms_per_step"]
     if not a.no_cpu:
         if a.config == "mha1024x12":
             # bounded sample: the first 2 of the 12 identical-shape layers, scaled to 12

@@ -75,8 +75,26 @@ typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_AD
  * pulls the tiles of every kernel from a device work queue and releases a kernel's tiles when
  * all its predecessor kernels have completed; host copies run before (H2D) and after (D2H) it on
  * one stream.  Its exported structure puts each kernel on its own queue with a wait on every
- * predecessor kernel and on the H2D copies of its inputs, which is what the device enforces. */
-typedef enum psc_policy { PSC_COARSE = 0, PSC_FINE = 1, PSC_DEVICE = 2 } psc_policy;
+ * predecessor kernel and on the H2D copies of its inputs, which is what the device enforces.
+ * Eager and HEFT: the dynamic coarse-grained baselines of Sec. V (Experiments 2 and 3, after
+ * StarPU's policies), run through the scheduling loop of Algorithm 1 (schedule, select, cb):
+ * every kernel is its own task component, and each of n_streams streams is one device with one
+ * command queue.  At run time the host keeps a ready queue of kernels whose predecessors have all
+ * finished, ordered by bottom-level rank (predicted durations from the cost model in the options,
+ * else the heuristic), and the set of available streams.  It dispatches the top kernel with its
+ * uploads and read-backs to a stream -- eager: the lowest-numbered available one; HEFT: the one
+ * with the earliest predicted finish time, waiting if that one is still busy -- followed by a
+ * host callback (hipLaunchHostFunc) that, when the stream reaches it, marks the kernel finished,
+ * moves newly ready successors into the ready queue and returns the stream, under a lock; the
+ * dispatching thread sleeps until a callback arrives.  No two kernels of one DAG edge are ever in
+ * flight together, so no device-side precedence is needed (uploads shared between streams are
+ * ordered by an event).  psc_sched_export reports the structure of the last run (PSC_ERR_STATE
+ * before the first): each kernel waits for its predecessors on other streams, whose completion
+ * the host saw before dispatching it.  Not with use_graph, fault_inject_op, timeout_ms,
+ * mark_components or PSC_DISPATCH_AQL. */
+typedef enum psc_policy {
+  PSC_COARSE = 0, PSC_FINE = 1, PSC_DEVICE = 2, PSC_EAGER = 3, PSC_HEFT = 4
+} psc_policy;
 
 /* Stream choice of the fine policy.
  *  PSC_MAP_RR         round robin per kernel in breadth-first order from the DAG's roots
@@ -88,6 +106,21 @@ typedef enum psc_policy { PSC_COARSE = 0, PSC_FINE = 1, PSC_DEVICE = 2 } psc_pol
 typedef enum psc_mapper { PSC_MAP_RR = 0, PSC_MAP_EFT = 1, PSC_MAP_COMPONENT = 2 } psc_mapper;
 
 typedef enum psc_op_type { PSC_OP_H2D = 0, PSC_OP_KERNEL = 1, PSC_OP_D2H = 2 } psc_op_type;
+
+/* How psc_run hands a coarse or fine schedule to the GPU (the command queues and events of
+ * Sec. III, Def. 4, and the dispatch step of Algorithm 1).
+ *  PSC_DISPATCH_HIP  every stream a HIP stream, every precedence a HIP event record and wait,
+ *                    kernels by hipLaunchKernel, copies by hipMemcpyAsync.
+ *  PSC_DISPATCH_AQL  every stream that holds a kernel an HSA user-mode queue of the GPU's
+ *                    command processor: the host writes one AQL dispatch packet per kernel; every
+ *                    op completes a signal, and a cross-stream precedence is a barrier-AND
+ *                    packet on the waiting queue (five signals per packet); copies go to the DMA
+ *                    engines (hsa_amd_memory_async_copy, with the same signals as dependencies),
+ *                    in the order of their stream.  Host memory of psc_host_io must then be
+ *                    page-locked (psc_host_alloc); strided copies need 4-byte aligned rows.
+ *                    Not with use_graph or fault_inject_op.  The kernels are the same code
+ *                    object the HIP path runs (libpsc_kernels.hsaco beside libpsc.so). */
+typedef enum psc_dispatch { PSC_DISPATCH_HIP = 0, PSC_DISPATCH_AQL = 1 } psc_dispatch;
 
 /* Kernel classes of a task component (Defs. 1-3 of Sec. III); a kernel may be in FRONT and END. */
 typedef enum psc_kclass { PSC_FRONT = 1, PSC_END = 2, PSC_IN = 4 } psc_kclass;
@@ -139,7 +172,8 @@ typedef struct psc_sched_opts {
                            PSC_ERR_TIMEOUT when the run has not finished.  The work stays in
                            flight: the next psc_run of the schedule, and psc_sched_destroy, first
                            wait for it to finish.  Outputs of a timed-out run are unspecified. */
-  int32_t reserved[4];
+  int32_t dispatch;     /* psc_dispatch (PSC_FINE and PSC_COARSE) */
+  int32_t reserved[3];
 } psc_sched_opts;
 
 /* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..
@@ -168,9 +202,12 @@ typedef struct psc_host_io {
 
 typedef struct psc_run_stats {
   double makespan_ms;      /* GPU time from the start event (recorded before the first op) to
-                              the end event (after every stream joined) */
+                              the end event (after every stream joined); with PSC_DISPATCH_AQL
+                              the device clock of a start mark, which every stream waits for,
+                              to that of an end mark, after every stream joined */
   double host_enqueue_ms;  /* host wall time spent enqueueing (graph launch only, in graph mode) */
-  int32_t n_ops, n_kernels, n_h2d, n_d2h, n_waits, n_streams, graph, reserved;
+  int32_t n_ops, n_kernels, n_h2d, n_d2h, n_waits, n_streams, graph;
+  int32_t aql_packets;     /* AQL packets written (PSC_DISPATCH_AQL), else 0 */
 } psc_run_stats;
 
 /* Per-op timing of the last psc_run with record_ops = 1, relative to the start event. */
@@ -299,6 +336,14 @@ psc_status psc_run(psc_sched *sched, const psc_host_io *io, int32_t n_io, psc_ru
 
 /* Per-op timeline of the last psc_run made with record_ops = 1: out[0..cap), *n = op count. */
 psc_status psc_sched_op_times(const psc_sched *sched, psc_op_time *out, int32_t cap, int32_t *n);
+
+/* Host-only check for PSC_DISPATCH_AQL: builds every kernel launch of the schedule on stand-in
+ * addresses and looks each kernel up in the code object's argument table (libpsc_kernels.kargs:
+ * named by its host handle, explicit record within the launch record, only implicit arguments
+ * of the kinds the dispatcher fills).  *n_kernels (may be NULL) = distinct kernels, or -1 if one
+ * is not dispatchable, with the reason in why[0..why_cap) (may be NULL).  Returns PSC_OK either
+ * way (errors only for bad arguments). */
+psc_status psc_sched_aql_check(const psc_sched *sched, int32_t *n_kernels, char *why, int32_t why_cap);
 
 /* [GPU] Completion of each task component in the last psc_run: done_us[c] = microseconds from
  * the run's start mark to the end of component c's last END kernel (a kernel with no successor

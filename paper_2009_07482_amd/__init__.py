@@ -36,10 +36,13 @@ PSC_F32, PSC_BF16 = 0, 1
 DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
 PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
 KINDS = {"gemm": PSC_GEMM, "transpose": PSC_TRANSPOSE, "softmax": PSC_SOFTMAX, "add": PSC_ADD}
-PSC_COARSE, PSC_FINE, PSC_DEVICE = 0, 1, 2
+PSC_COARSE, PSC_FINE, PSC_DEVICE, PSC_EAGER, PSC_HEFT = 0, 1, 2, 3, 4
+POLICIES = {"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE, "eager": PSC_EAGER, "heft": PSC_HEFT}
 PSC_MAP_RR, PSC_MAP_EFT, PSC_MAP_COMPONENT = 0, 1, 2
 MAPPERS = {"rr": PSC_MAP_RR, "eft": PSC_MAP_EFT, "component": PSC_MAP_COMPONENT}
 PSC_OP_H2D, PSC_OP_KERNEL, PSC_OP_D2H = 0, 1, 2
+PSC_DISPATCH_HIP, PSC_DISPATCH_AQL = 0, 1
+DISPATCH = {"hip": PSC_DISPATCH_HIP, "aql": PSC_DISPATCH_AQL}
 OP_TYPES = {0: "h2d", 1: "kernel", 2: "d2h"}
 PSC_FRONT, PSC_END, PSC_IN = 1, 2, 4
 
@@ -61,7 +64,8 @@ class psc_sched_opts(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("mapper", C.c_int32), ("copy_stream", C.c_int32),
                 ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
                 ("cost", C.c_void_p), ("host_threads", C.c_int32), ("mark_components", C.c_int32),
-                ("fault_inject_op", C.c_int32), ("timeout_ms", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("fault_inject_op", C.c_int32), ("timeout_ms", C.c_int32), ("dispatch", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class psc_op(C.Structure):
@@ -76,7 +80,7 @@ class psc_host_io(C.Structure):
 class psc_run_stats(C.Structure):
     _fields_ = [("makespan_ms", C.c_double), ("host_enqueue_ms", C.c_double)] + [
         (n, C.c_int32) for n in ("n_ops", "n_kernels", "n_h2d", "n_d2h", "n_waits", "n_streams",
-                                 "graph", "reserved")]
+                                 "graph", "aql_packets")]
 
 
 class psc_op_time(C.Structure):
@@ -145,6 +149,7 @@ _SIGS = {
     "psc_device_info": [_I, C.c_char_p, _I, C.c_char_p, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I64)],
     "psc_sched_device_tasks": [_P, _I, C.c_void_p, _I, C.POINTER(_I), C.c_void_p],
     "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
+    "psc_sched_aql_check": [_P, C.POINTER(_I), C.c_char_p, _I],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
     "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
                               C.POINTER(C.c_float)],
@@ -240,7 +245,7 @@ def psc_dag_classify(dag, component):
 
 def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
               device=0, cost=None, host_threads=0, mark_components=False, fault_inject_op=0,
-              timeout_ms=0):
+              timeout_ms=0, dispatch="hip"):
     o = psc_sched_opts()
     o.n_streams = int(n_streams)
     o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
@@ -253,11 +258,12 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
     o.mark_components = int(bool(mark_components))
     o.fault_inject_op = int(fault_inject_op)
     o.timeout_ms = int(timeout_ms)
+    o.dispatch = DISPATCH[dispatch] if isinstance(dispatch, str) else int(dispatch)
     return o
 
 
 def psc_schedule(dag, policy, opts=None, **kw):
-    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+    pol = (POLICIES[policy]
            if isinstance(policy, str) else int(policy))
     o = opts if opts is not None else make_opts(**kw)
     h = _P()
@@ -267,7 +273,7 @@ def psc_schedule(dag, policy, opts=None, **kw):
 
 def psc_schedule_batch(dags, policy, opts=None, **kw):
     """One schedule for the disjoint union of ``dags`` (names "<i>/<name>"; see union_spec)."""
-    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+    pol = (POLICIES[policy]
            if isinstance(policy, str) else int(policy))
     o = opts if opts is not None else make_opts(**kw)
     arr = (_P * max(1, len(dags)))(*[d.value if hasattr(d, "value") else d for d in dags])
@@ -340,6 +346,14 @@ def psc_sched_device_tasks(sched, workers):
     off = np.zeros(int(workers) + 1, np.int32)
     _check(_lib.psc_sched_device_tasks(sched, int(workers), t.ctypes.data, n.value, C.byref(n), off.ctypes.data))
     return [[tuple(int(v) for v in t[i]) for i in range(off[w], off[w + 1])] for w in range(int(workers))]
+
+
+def psc_sched_aql_check(sched):
+    """(distinct kernels, "") if AQL dispatch can run every kernel of the schedule, else (-1, reason)."""
+    n = _I()
+    why = C.create_string_buffer(512)
+    _check(_lib.psc_sched_aql_check(sched, C.byref(n), why, 512))
+    return n.value, why.value.decode()
 
 
 def psc_sched_component_times(sched):
@@ -531,7 +545,7 @@ def psc_autotune_dag(dag, iters=50, device=0):
 
 def psc_autotune_schedule(dag, policy, candidates, iters=20):
     """candidates: list of make_opts() keyword dicts.  Returns (best index, [ms per run])."""
-    pol = ({"coarse": PSC_COARSE, "fine": PSC_FINE, "device": PSC_DEVICE}[policy]
+    pol = (POLICIES[policy]
            if isinstance(policy, str) else int(policy))
     arr = (psc_sched_opts * len(candidates))(*[make_opts(**c) for c in candidates])
     best = _I()

@@ -23,6 +23,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
 void op_times(const psc_sched &s, psc_op_time *out, int32_t cap, int32_t *n);
 void samples(const psc_sched &s, float *feat, float *log_us, int32_t cap, int32_t *n);
 void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n);
+int32_t aql_check(const psc_sched &s, char *why, int32_t why_cap);
 void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t cap, int32_t *n_tasks,
                   int32_t *work_off);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
@@ -251,10 +252,17 @@ psc_status psc_dag_classify(psc_dag *dag, int32_t component, int32_t *kclass, in
 namespace {
 
 std::unique_ptr<psc_sched> new_sched(psc_dag *dag, int32_t policy, const psc_sched_opts *opts) {
-  need(policy == PSC_COARSE || policy == PSC_FINE || policy == PSC_DEVICE, PSC_ERR_ARG,
-       "policy must be PSC_COARSE, PSC_FINE or PSC_DEVICE");
+  need(policy >= PSC_COARSE && policy <= PSC_HEFT, PSC_ERR_ARG,
+       "policy must be PSC_COARSE, PSC_FINE, PSC_DEVICE, PSC_EAGER or PSC_HEFT");
   psc_sched_opts o = opts ? *opts : default_opts();
-  if (policy != PSC_FINE) o.n_streams = 1;
+  const bool dynamic = policy == PSC_EAGER || policy == PSC_HEFT;
+  if (policy != PSC_FINE && !dynamic) o.n_streams = 1;
+  if (dynamic) {
+    need(!o.use_graph, PSC_ERR_ARG, "dynamic schedules decide at run time; use_graph does not apply");
+    need(o.dispatch == PSC_DISPATCH_HIP, PSC_ERR_UNSUPPORTED, "dynamic schedules use PSC_DISPATCH_HIP");
+    need(!o.fault_inject_op && !o.timeout_ms && !o.mark_components, PSC_ERR_UNSUPPORTED,
+         "fault_inject_op, timeout_ms and mark_components apply to static schedules");
+  }
   need(!(policy == PSC_DEVICE && o.use_graph), PSC_ERR_ARG, "PSC_DEVICE runs one kernel; use_graph does not apply");
   need(o.n_streams >= 1 && o.n_streams <= 64, PSC_ERR_ARG, "n_streams must be in [1, 64]");
   need(o.mapper >= PSC_MAP_RR && o.mapper <= PSC_MAP_COMPONENT, PSC_ERR_ARG, "unknown mapper");
@@ -264,6 +272,12 @@ std::unique_ptr<psc_sched> new_sched(psc_dag *dag, int32_t policy, const psc_sch
   need(o.timeout_ms >= 0, PSC_ERR_ARG, "negative timeout_ms");
   need(o.fault_inject_op >= 0, PSC_ERR_ARG, "negative fault_inject_op");
   need(!(policy == PSC_DEVICE && o.fault_inject_op), PSC_ERR_ARG, "fault_inject_op does not apply to PSC_DEVICE");
+  need(o.dispatch == PSC_DISPATCH_HIP || o.dispatch == PSC_DISPATCH_AQL, PSC_ERR_ARG, "unknown dispatch");
+  if (o.dispatch == PSC_DISPATCH_AQL) {
+    need(policy != PSC_DEVICE, PSC_ERR_ARG, "PSC_DEVICE runs one kernel; dispatch does not apply");
+    need(!o.use_graph, PSC_ERR_ARG, "use_graph applies to PSC_DISPATCH_HIP only");
+    need(!o.fault_inject_op, PSC_ERR_UNSUPPORTED, "fault_inject_op applies to PSC_DISPATCH_HIP only");
+  }
   psc::Dag &g = dag->g;
   if (!g.validated || !g.frozen) g.validate();
   g.frozen = true;
@@ -347,6 +361,8 @@ psc_status psc_sched_export(const psc_sched *sched, psc_op *ops, int32_t cap, in
                             int32_t waits_cap, int32_t *n_waits) {
   return guard([&] {
     need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    need(!sched->plan.dynamic || sched->plan.realized, PSC_ERR_STATE,
+         "a dynamic schedule's queue structure exists after its first psc_run");
     const auto &P = sched->plan.ops;
     int32_t nw = 0;
     for (const auto &op : P) nw += int32_t(op.waits.size());
@@ -408,6 +424,14 @@ psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32
     need(sched && n_tasks, PSC_ERR_ARG, "NULL argument");
     need(workers >= 1, PSC_ERR_ARG, "workers must be >= 1");
     psc::device_tasks(*sched, workers, tasks, cap, n_tasks, work_off);
+  });
+}
+
+psc_status psc_sched_aql_check(const psc_sched *sched, int32_t *n_kernels, char *why, int32_t why_cap) {
+  return guard([&] {
+    need(sched != nullptr, PSC_ERR_ARG, "NULL schedule");
+    const int32_t k = psc::aql_check(*sched, why, why_cap);
+    if (n_kernels) *n_kernels = k;
   });
 }
 

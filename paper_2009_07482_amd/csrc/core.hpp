@@ -95,6 +95,14 @@ struct Op {
 
 struct SchedPlan {
   bool device = false;         // PSC_DEVICE: streams beyond 0 only describe precedences
+  // PSC_EAGER / PSC_HEFT: kernels are dispatched one at a time at run time, each after its
+  // predecessors' completion callbacks; the ops below hold every upload, kernel and read-back,
+  // and each run rewrites their stream, pos, host_order and waits with what it did
+  bool dynamic = false;
+  bool heft = false;
+  bool realized = false;       // a dynamic schedule has run at least once
+  std::vector<double> dyn_us;    // per kernel: predicted microseconds (the cost model)
+  std::vector<double> dyn_rank;  // per kernel: bottom-level rank on those predictions
   int32_t n_streams = 1;       // compute streams
   int32_t total_streams = 1;   // + upload and read-back streams (copy_stream)
   std::vector<Op> ops;         // index = op id; host order = id order

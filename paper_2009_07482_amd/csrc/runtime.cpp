@@ -12,12 +12,15 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstring>
 #include <queue>
 #include <string>
 
+#include "aql.hpp"
 #include "core.hpp"
 #include "dispatch.hpp"
 #include "kernels.hpp"
@@ -38,6 +41,47 @@ struct CopyDesc {  // one resolved host copy
   size_t dpitch = 0, spitch = 0, width = 0, height = 0;
   hipMemcpyKind kind = hipMemcpyHostToDevice;
 };
+
+// State the dynamic schedulers share with their completion callbacks (Algorithm 1's F, A and the
+// finished-kernel status), guarded by one lock.
+struct DynState {
+  std::mutex mu;
+  std::condition_variable cv;
+  const Dag *g = nullptr;
+  const SchedPlan *plan = nullptr;
+  std::vector<int32_t> indeg;                   // unfinished predecessors per kernel
+  std::vector<std::pair<double, int32_t>> heap;  // ready kernels: (rank, -kernel), a max-heap
+  std::vector<char> available;                  // per stream (device queue)
+  int32_t finished = 0;
+  uint64_t updates = 0;                          // callbacks seen
+  struct Arg {
+    DynState *st;
+    int32_t kernel, stream;
+  };
+  std::vector<Arg> args;                         // per kernel, the callback's user argument
+
+  void push_ready(int32_t k) {
+    heap.push_back({plan->dyn_rank[k], -k});
+    std::push_heap(heap.begin(), heap.end());
+  }
+};
+
+// cb of Algorithm 1: the kernel finished (its stream reached the callback); its successors whose
+// predecessors have all finished join the ready queue and its stream is available again.  Runs on
+// the HIP runtime's callback thread and makes no HIP call.
+void dyn_callback(void *p) {
+  auto *a = static_cast<DynState::Arg *>(p);
+  DynState &st = *a->st;
+  {
+    std::lock_guard<std::mutex> lk(st.mu);
+    for (int32_t q : st.g->succ[a->kernel])
+      if (--st.indeg[q] == 0) st.push_ready(q);
+    st.available[a->stream] = 1;
+    ++st.finished;
+    ++st.updates;
+  }
+  st.cv.notify_one();
+}
 
 struct Device {
   int device = 0;
@@ -62,6 +106,8 @@ struct Device {
   std::vector<Launch> mark_after;  // per kernel; .func == nullptr unless an END kernel
   bool have_marks = false;
   std::unique_ptr<Dispatcher> disp;
+  std::unique_ptr<AqlSchedule> aql;  // PSC_DISPATCH_AQL: queues, signals, argument records
+  std::unique_ptr<struct DynState> dyn;  // PSC_EAGER / PSC_HEFT: the run-time scheduler's state
   // PSC_DEVICE executor
   void *exec_mem = nullptr;
   ExecArgs ea{};
@@ -70,6 +116,7 @@ struct Device {
 
   ~Device() {
     if (in_flight && end) (void)hipEventSynchronize(end);  // a timed-out run still executing
+    aql.reset();                                           // (waits for its own run the same way)
     disp.reset();
     if (exec_mem) (void)hipFree(exec_mem);
     if (marks) (void)hipFree(marks);
@@ -372,15 +419,17 @@ void prepare(psc_sched &s) {
   const bool dev_mode = s.plan.device;
   d->streams.assign(dev_mode ? 1 : s.plan.total_streams, nullptr);
   for (auto &st : d->streams) PSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  const bool aql_mode = !dev_mode && s.opts.dispatch == PSC_DISPATCH_AQL;
   d->op_ev.assign(s.plan.ops.size(), nullptr);
-  if (!dev_mode)
+  if (!dev_mode && !aql_mode)
     for (size_t i = 0; i < s.plan.ops.size(); ++i)
-      if (s.plan.ops[i].recorded) PSC_HIP(hipEventCreateWithFlags(&d->op_ev[i], hipEventDisableTiming));
+      if (s.plan.ops[i].recorded || (s.plan.dynamic && s.plan.ops[i].type == PSC_OP_H2D))
+        PSC_HIP(hipEventCreateWithFlags(&d->op_ev[i], hipEventDisableTiming));
   d->join_ev.assign(d->streams.size(), nullptr);
   for (auto &e : d->join_ev) PSC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   PSC_HIP(hipEventCreate(&d->start));
   PSC_HIP(hipEventCreate(&d->end));
-  if (s.opts.record_ops && !dev_mode) {
+  if (s.opts.record_ops && !dev_mode && !aql_mode) {
     d->t0.assign(s.plan.ops.size(), nullptr);
     d->t1.assign(s.plan.ops.size(), nullptr);
     for (auto &e : d->t0) PSC_HIP(hipEventCreate(&e));
@@ -406,9 +455,14 @@ void prepare(psc_sched &s) {
   }
   if (dev_mode) {
     prepare_executor(g, *d);
+  } else if (s.plan.dynamic) {
+    d->dyn = std::make_unique<DynState>();
   } else {
     const int32_t nt = s.opts.host_threads > 0 ? s.opts.host_threads : s.plan.total_streams;
     d->disp = std::make_unique<Dispatcher>(s.plan, nt);
+    if (aql_mode)
+      d->aql = std::make_unique<AqlSchedule>(d->device, s.plan, d->launch, d->mark_after,
+                                             d->marks ? &d->mark_start : nullptr, s.opts.record_ops != 0);
   }
   s.dev = std::move(d);
 }
@@ -493,6 +547,17 @@ struct HipBackend final : Backend {
   void stream_done(int32_t stream) override {
     if (stream != 0) PSC_HIP(hipEventRecord(d.join_ev[stream], d.streams[stream]));
   }
+};
+
+// The same dispatch sequence written as AQL packets (waits become barrier-AND packets; records
+// are implicit: every op completes its own signal).
+struct AqlBackend final : Backend {
+  AqlSchedule &a;
+  explicit AqlBackend(AqlSchedule &a_) : a(a_) {}
+  void wait(int32_t op, int32_t awaited) override { a.wait(op, awaited); }
+  void exec(int32_t op) override { a.exec(op); }
+  void record(int32_t) override {}
+  void stream_done(int32_t) override {}
 };
 
 void fork_streams(Device &d, hipEvent_t ev) {
@@ -610,12 +675,158 @@ void wait_end(psc_sched &s) {
 
 }  // namespace
 
+namespace {
+
+// The scheduling loop of Algorithm 1 for PSC_EAGER / PSC_HEFT on one GPU: select a ready kernel
+// and a stream (a device with one command queue), enqueue its uploads, the kernel, its
+// read-backs and the callback, and sleep until a callback updates the ready queue or the
+// available streams.  Afterwards the plan's ops carry the structure this run had.
+void run_dynamic(psc_sched &s, const std::vector<CopyDesc> &cd, bool timed) {
+  Device &d = *s.dev;
+  const Dag &g = s.dag->g;
+  SchedPlan &plan = s.plan;
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  const int32_t S = plan.total_streams;
+  DynState &st = *d.dyn;
+  // ops of each kernel in the coarse op list: its uploads before it, its read-backs after it
+  std::vector<std::vector<int32_t>> ups(nk), reads(nk);
+  {
+    std::vector<int32_t> pending_up;
+    int32_t last_kernel = -1;
+    for (size_t o = 0; o < plan.ops.size(); ++o) {
+      const Op &op = plan.ops[o];
+      if (op.type == PSC_OP_H2D) {
+        pending_up.push_back(int32_t(o));
+      } else if (op.type == PSC_OP_KERNEL) {
+        ups[op.kernel] = pending_up;
+        pending_up.clear();
+        last_kernel = op.kernel;
+      } else if (last_kernel >= 0) {
+        reads[last_kernel].push_back(int32_t(o));
+      }
+    }
+  }
+  // an upload is issued by whichever of its buffer's readers is dispatched first
+  std::vector<int32_t> upload_of(g.bufs.size(), -1);
+  for (int32_t k = 0; k < nk; ++k)
+    for (int32_t o : ups[k]) upload_of[plan.ops[o].buffer] = o;
+  std::vector<int32_t> up_stream(plan.ops.size(), -1);
+  st.g = &g;
+  st.plan = &plan;
+  st.indeg.assign(nk, 0);
+  st.heap.clear();
+  st.available.assign(S, 1);
+  st.finished = 0;
+  st.updates = 0;
+  st.args.assign(nk, DynState::Arg{&st, 0, 0});
+  for (int32_t k = 0; k < nk; ++k) {
+    st.indeg[k] = static_cast<int32_t>(g.pred[k].size());
+    st.args[k].kernel = k;
+  }
+  for (int32_t k = 0; k < nk; ++k)
+    if (!st.indeg[k]) st.push_ready(k);
+  std::vector<int32_t> stream_of(nk, -1), pos(S, 0);
+  std::vector<double> busy_until(S, 0.0);  // HEFT: predicted time each stream's kernel ends (us)
+  std::vector<std::vector<int32_t>> new_waits(plan.ops.size());
+  std::vector<int32_t> new_stream(plan.ops.size(), 0), new_pos(plan.ops.size(), 0), new_order(plan.ops.size(), 0);
+  int32_t order = 0;
+  hipStream_t s0 = d.streams[0];
+  PSC_HIP(hipEventRecord(d.start, s0));
+  fork_streams(d, d.start);
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now_us = [&] { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count(); };
+  auto timed_op = [&](int32_t o, hipStream_t q, auto &&body) {
+    if (timed) PSC_HIP(hipEventRecord(d.t0[o], q));
+    body();
+    if (timed) PSC_HIP(hipEventRecord(d.t1[o], q));
+  };
+  try {
+    std::unique_lock<std::mutex> lk(st.mu);
+    while (st.finished < nk) {
+      while (!st.heap.empty()) {
+        const int32_t k = -st.heap.front().second;
+        int32_t q = -1;
+        if (!plan.heft) {  // eager: any available stream
+          for (int32_t x = 0; x < S && q < 0; ++x)
+            if (st.available[x]) q = x;
+        } else {           // HEFT: earliest predicted finish over every stream; wait for it if busy
+          const double now = now_us();
+          double best = 1e300;
+          int32_t arg = 0;
+          for (int32_t x = 0; x < S; ++x) {
+            const double f = std::max(now, st.available[x] ? now : busy_until[x]) + plan.dyn_us[k];
+            if (f < best - 1e-9) { best = f; arg = x; }
+          }
+          if (st.available[arg]) q = arg;
+        }
+        if (q < 0) break;
+        std::pop_heap(st.heap.begin(), st.heap.end());
+        st.heap.pop_back();
+        st.available[q] = 0;
+        st.args[k].stream = q;
+        lk.unlock();
+        // dispatch (uploads, kernel, read-backs, callback) outside the lock
+        hipStream_t hs = d.streams[q];
+        const int32_t kop = plan.kernel_op[k];
+        for (int32_t b : g.iso_in[k]) {
+          const int32_t uo = upload_of[b];
+          if (uo < 0) continue;
+          if (up_stream[uo] < 0) {
+            timed_op(uo, hs, [&] { do_copy(cd[uo], hs); });
+            PSC_HIP(hipEventRecord(d.op_ev[uo], hs));
+            up_stream[uo] = q;
+            new_stream[uo] = q, new_pos[uo] = pos[q]++, new_order[uo] = order++;
+          } else if (up_stream[uo] != q) {
+            PSC_HIP(hipStreamWaitEvent(hs, d.op_ev[uo], 0));
+            new_waits[kop].push_back(uo);
+          }
+        }
+        for (int32_t p : g.pred[k])
+          if (stream_of[p] != q) new_waits[kop].push_back(plan.kernel_op[p]);
+        timed_op(kop, hs, [&] { launch(d.launch[k], hs); });
+        new_stream[kop] = q, new_pos[kop] = pos[q]++, new_order[kop] = order++;
+        for (int32_t ro : reads[k]) {
+          timed_op(ro, hs, [&] { do_copy(cd[ro], hs); });
+          new_stream[ro] = q, new_pos[ro] = pos[q]++, new_order[ro] = order++;
+        }
+        stream_of[k] = q;
+        busy_until[q] = now_us() + plan.dyn_us[k];
+        PSC_HIP(hipLaunchHostFunc(hs, dyn_callback, &st.args[k]));
+        lk.lock();
+      }
+      if (st.finished >= nk) break;
+      const uint64_t seen = st.updates;
+      st.cv.wait(lk, [&] { return st.updates != seen; });   // sleep_till_cb_update
+    }
+  } catch (...) {
+    // callbacks of what was dispatched still reference the state: let them all run first
+    for (hipStream_t x : d.streams) (void)hipStreamSynchronize(x);
+    throw;
+  }
+  for (int32_t x = 1; x < S; ++x) PSC_HIP(hipEventRecord(d.join_ev[x], d.streams[x]));
+  join_streams(d);
+  PSC_HIP(hipEventRecord(d.end, s0));
+  for (size_t o = 0; o < plan.ops.size(); ++o) {
+    Op &op = plan.ops[o];
+    op.stream = new_stream[o];
+    op.pos = new_pos[o];
+    op.host_order = new_order[o];
+    std::sort(new_waits[o].begin(), new_waits[o].end());
+    new_waits[o].erase(std::unique(new_waits[o].begin(), new_waits[o].end()), new_waits[o].end());
+    op.waits = new_waits[o];
+  }
+  plan.realized = true;
+}
+
+}  // namespace
+
 void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats) {
   prepare(s);
   Device &d = *s.dev;
   PSC_HIP(hipSetDevice(d.device));
   if (d.in_flight) {  // the previous run timed out: its work must end before buffers are reused
-    PSC_HIP(hipEventSynchronize(d.end));
+    if (d.aql) (void)d.aql->wait_end(0);
+    else PSC_HIP(hipEventSynchronize(d.end));
     d.in_flight = false;
   }
   const std::vector<CopyDesc> cd = resolve_io(s, io, n_io);
@@ -634,6 +845,30 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
     PSC_HIP(hipEventRecord(d.end, s0));
+    host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  } else if (s.plan.dynamic) {
+    const auto h0 = std::chrono::steady_clock::now();
+    run_dynamic(s, cd, timed);
+    host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  } else if (d.aql) {
+    std::vector<AqlCopy> ac(cd.size());
+    for (size_t o = 0; o < cd.size(); ++o) {
+      const CopyDesc &c = cd[o];
+      ac[o] = AqlCopy{c.active, c.kind == hipMemcpyHostToDevice, c.dst, c.src, c.dpitch, c.spitch, c.width, c.height};
+    }
+    const auto h0 = std::chrono::steady_clock::now();
+    d.aql->begin(ac);
+    AqlBackend backend(*d.aql);
+    try {
+      d.disp->run(backend);
+    } catch (...) {
+      // nothing may wait forever on an op that was never enqueued: complete those, join, drain
+      d.aql->release_undispatched();
+      d.aql->end();
+      (void)d.aql->wait_end(0);
+      throw;
+    }
+    d.aql->end();
     host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   } else if (s.opts.use_graph) {
     std::vector<const void *> key;
@@ -660,9 +895,18 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     PSC_HIP(hipEventRecord(d.end, s0));
     host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   }
-  wait_end(s);
   float ms = 0;
-  PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
+  if (d.aql) {
+    if (!d.aql->wait_end(s.opts.timeout_ms)) {
+      d.in_flight = true;
+      fail(PSC_ERR_TIMEOUT, "run not finished within timeout_ms = " + std::to_string(s.opts.timeout_ms) +
+                                " (still executing; the next psc_run or psc_sched_destroy waits for it)");
+    }
+    ms = float(d.aql->makespan_ms());
+  } else {
+    wait_end(s);
+    PSC_HIP(hipEventElapsedTime(&ms, d.start, d.end));
+  }
   d.have_marks = d.marks != nullptr || s.plan.device;
   if (s.plan.device && *d.h_err)
     fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) +
@@ -685,6 +929,17 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
         d.times[o].start_us = float(double(int64_t(tf[op.kernel] - t0)) / d.clock_mhz);
         d.times[o].end_us = float(double(int64_t(tl[op.kernel] - t0)) / d.clock_mhz);
       }
+    }
+    d.have_times = true;
+  } else if (timed && d.aql) {
+    std::vector<float> a, b;
+    d.aql->op_times(a, b);
+    d.times.resize(s.plan.ops.size());
+    d.active.assign(s.plan.ops.size(), 0);
+    for (size_t o = 0; o < s.plan.ops.size(); ++o) {
+      const Op &op = s.plan.ops[o];
+      d.times[o] = psc_op_time{int32_t(o), op.stream, a[o], b[o]};
+      d.active[o] = op.type == PSC_OP_KERNEL ? !d.launch[op.kernel].empty : cd[o].active;
     }
     d.have_times = true;
   } else if (timed) {
@@ -713,6 +968,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
     }
     stats->n_streams = s.plan.total_streams;
     stats->graph = s.opts.use_graph != 0;
+    stats->aql_packets = d.aql ? d.aql->packets_last_run() : 0;
   }
 }
 
@@ -797,6 +1053,39 @@ void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t c
     }
   if (work_off)  // workgroups beyond the task count get empty lists
     for (int32_t w = 0; w <= workers; ++w) work_off[w] = ep.work_off[std::min<size_t>(w, ep.work_off.size() - 1)];
+}
+
+// Host-only: every kernel launch of the schedule (built on stand-in addresses) is known to the
+// AQL dispatcher's code object table; returns the number of distinct kernels, or -1 and a reason.
+int32_t aql_check(const psc_sched &s, char *why, int32_t why_cap) {
+  const Dag &g = s.dag->g;
+  Device d;
+  d.base.assign(g.bufs.size(), nullptr);
+  uintptr_t at = uintptr_t(1) << 32;
+  for (size_t b = 0; b < g.bufs.size(); ++b) {
+    const Buffer &x = g.bufs[b];
+    if (x.parent >= 0) continue;
+    d.base[b] = reinterpret_cast<char *>(at);
+    at += (size_t(x.rows) * x.cols * elem_size(x.dtype) + 255) & ~size_t(255);
+  }
+  std::vector<Launch> ls(g.kers.size() + 1);
+  for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, d, int32_t(k), ls[k]);
+  make_mark(ls.back(), reinterpret_cast<uint64_t *>(at));
+  std::vector<const void *> seen;
+  for (const Launch &L : ls) {
+    if (L.empty) continue;
+    std::string reason;
+    if (!aql_launch_supported(L, &reason)) {
+      if (why && why_cap > 0) {
+        std::strncpy(why, reason.c_str(), size_t(why_cap - 1));
+        why[why_cap - 1] = 0;
+      }
+      return -1;
+    }
+    if (std::find(seen.begin(), seen.end(), L.func) == seen.end()) seen.push_back(L.func);
+  }
+  if (why && why_cap > 0) why[0] = 0;
+  return int32_t(seen.size());
 }
 
 void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n) {

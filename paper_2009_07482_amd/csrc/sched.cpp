@@ -195,8 +195,40 @@ SchedPlan build_device_plan(const Dag &g) {
 
 }  // namespace
 
+// PSC_EAGER / PSC_HEFT (the dynamic coarse-grained baselines of Sec. V, Experiments 2 and 3):
+// every kernel its own task component.  The op list is the coarse one (each kernel with its
+// uploads before and its read-backs after it); which stream -- device queue -- runs it, and when,
+// is decided at run time.  Here: predicted durations and the bottom-level ranks that order the
+// ready queue.
+SchedPlan build_dynamic_plan(const Dag &g, int policy, const psc_sched_opts &o) {
+  psc_sched_opts one = o;
+  one.copy_stream = 0;
+  SchedPlan plan = build_plan(g, PSC_COARSE, one);
+  plan.dynamic = true;
+  plan.heft = policy == PSC_HEFT;
+  plan.n_streams = plan.total_streams = o.n_streams;
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  std::vector<float> feat(size_t(std::max(1, nk)) * kFeatures, 0.0f);
+  for (int32_t k = 0; k < nk; ++k) kernel_features(g, k, 0, &feat[size_t(k) * kFeatures]);
+  plan.dyn_us.assign(nk, 0.0);
+  auto cost = o.cost ? mlp_cost_model(o.cost) : make_heuristic_cost();
+  if (nk) cost->predict_us(feat.data(), nk, plan.dyn_us.data());
+  bool usable = true;
+  for (double v : plan.dyn_us) usable = usable && std::isfinite(v) && v >= 0.0;
+  if (!usable && nk) make_heuristic_cost()->predict_us(feat.data(), nk, plan.dyn_us.data());
+  plan.dyn_rank.assign(nk, 0.0);
+  const std::vector<int32_t> topo = g.bfs_order();
+  for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
+    double m = 0;
+    for (int32_t q : g.succ[*it]) m = std::max(m, plan.dyn_rank[q]);
+    plan.dyn_rank[*it] = plan.dyn_us[*it] + m;
+  }
+  return plan;
+}
+
 SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
   if (policy == PSC_DEVICE) return build_device_plan(g);
+  if (policy == PSC_EAGER || policy == PSC_HEFT) return build_dynamic_plan(g, policy, o);
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   SchedPlan plan;
   const int32_t S = policy == PSC_COARSE ? 1 : o.n_streams;

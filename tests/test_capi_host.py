@@ -387,3 +387,36 @@ def test_device_executor_plan_cannot_deadlock(name, spec, workers):
                 queue.append(y)
     assert seen == len(indeg), "wait-for cycle"
     assert len([L for L in lists if L]) == min(workers, len(indeg))
+
+
+def test_aql_code_object_covers_every_kernel():
+    """Host-only: the code object beside libpsc.so and its argument table name every kernel the
+    schedules of the workloads launch, with only implicit arguments the AQL dispatcher fills."""
+    specs = [workloads.forkjoin_spec(256), workloads.mha_spec(512, 512, 8),
+             workloads.mha_spec(1024, 1024, 16, 2, "bf16"), workloads.mha_spec(137, 64, 2, 2, "f32")]
+    specs += [workloads.random_dag_spec(s) for s in range(4)]
+    for spec in specs:
+        d = psc.build_dag(spec)
+        s = psc.psc_schedule(d, "fine", n_streams=4, dispatch="aql")
+        n, why = psc.psc_sched_aql_check(s)
+        assert n >= 2 and why == "", why
+        psc.psc_sched_destroy(s)
+        psc.psc_dag_destroy(d)
+
+
+def test_dynamic_policies_validate_options_on_the_host():
+    spec = workloads.forkjoin_spec(16)
+    d = psc.build_dag(spec)
+    for pol in ("eager", "heft"):
+        s = psc.psc_schedule(d, pol, n_streams=2)
+        with pytest.raises(psc.PscError) as e:
+            psc.psc_sched_export(s)
+        assert e.value.name == "PSC_ERR_STATE"
+        assert psc.psc_sched_streams(s) == 2
+        psc.psc_sched_destroy(s)
+        for kw, want in ((dict(use_graph=True), "PSC_ERR_ARG"), (dict(timeout_ms=5), "PSC_ERR_UNSUPPORTED"),
+                         (dict(dispatch="aql"), "PSC_ERR_UNSUPPORTED"), (dict(mark_components=True), "PSC_ERR_UNSUPPORTED")):
+            with pytest.raises(psc.PscError) as e:
+                psc.psc_schedule(d, pol, **kw)
+            assert e.value.name == want, (pol, kw)
+    psc.psc_dag_destroy(d)
