@@ -254,6 +254,63 @@ psc_status psc_add_kernel(psc_dag *dag, const char *name, int32_t kind,
 psc_status psc_add_edge(psc_dag *dag, int32_t src_kernel, const char *src_output,
                         int32_t dst_kernel, const char *dst_input);
 
+/* What psc_dag_from_json built (any field may be ignored). */
+typedef struct psc_spec_info {
+  int32_t n_kernels, n_buffers, n_edges;
+  int32_t n_components;  /* task components: one per tc sub-list, then one per kernel in none */
+  int32_t gpu_queues;    /* the file's cq entry for the GPU (0 if it gives none): the paper's
+                            command-queue count, to pass as psc_sched_opts.n_streams */
+  int32_t reserved[3];
+} psc_spec_info;
+
+/* The specification file of Sec. IV-A (the dag.json of PySchedCL, in JSON text) lowered onto the
+ * calls above: a new DAG in *out, owned by the caller (psc_dag_destroy).
+ *   json       NUL-terminated UTF-8 text of one object with the members
+ *     "kernels"  list of {"id": 0..n-1, "name": "gemm"|"matmul"|"transpose"|"softmax"|"add"|"vadd",
+ *                "dev": "gpu" (optional; any other device is PSC_ERR_UNSUPPORTED: one GPU),
+ *                "inputBuffers" / "outputBuffers": buffer tuples {"type": "float"|"bfloat16",
+ *                "size": elements, "pos": argument position} (and optionally "name": buffers of
+ *                one name in several kernels share storage, e.g. an input read by many kernels;
+ *                "view_of" + "row_off"/"col_off": a window of a "buffers" entry),
+ *                "varArguments": tuples {"type": "int"|"float", "pos", "value"}: in position
+ *                order the integers are M, N, K for a GEMM (C = alpha A B, A M x K, B K x N, C
+ *                M x N; an optional float is alpha) and rows, cols for the others (transpose of
+ *                rows x cols gives cols x rows), "globalWorkSize": evaluated, otherwise unused --
+ *                each kernel chooses its own grid; "ioBuffers" must be absent or empty}.
+ *                Buffer arguments are the inputs then the output in position order; each "size"
+ *                must equal the element count the kernel's dimensions give (PSC_ERR_SHAPE).
+ *     "edges"    list of "k_i,b_r -> k_j,b_s" strings (or [k_i, b_r, k_j, b_s]): the output at
+ *                argument position b_r of kernel k_i is the input at position b_s of k_j.
+ *     "tc"       optional list of lists of kernel ids: the task components, in order.
+ *     "cq"       optional {"gpu": n} or ["gpu:n"]: command queues per device.
+ *     "buffers"  optional list of {"name", "type", "rows", "cols"}: storage that arguments window.
+ *     "symbols"  optional object of default symbol values.
+ *   Numbers anywhere may be expressions over symbols: + - * / % ( ), integers where an integer
+ *   is meant.  sym_names[0..n_sym) / sym_values bind symbols at load time, over the defaults.
+ * Buffers are named by "name", else "k<i>_a<pos>" after the producing kernel's argument (or the
+ * first reader's); kernels "<name>_<id>", ids as in the file.  Every error destroys what was
+ * built and leaves *out untouched: PSC_ERR_ARG (malformed JSON, with line and column; unbound
+ * symbol; wrong argument counts), PSC_ERR_NAME (edge argument that is not an output / input,
+ * name clashes), PSC_ERR_SHAPE, PSC_ERR_UNSUPPORTED (CPU device, ioBuffers, unknown kernel);
+ * cycles and races are found by psc_schedule as for any DAG. */
+psc_status psc_dag_from_json(const char *json, const char *const *sym_names, const int64_t *sym_values,
+                             int32_t n_sym, psc_dag **out, psc_spec_info *info);
+
+/* Description of buffer `id` (ids as psc_buffer_id): its name (NUL-terminated, truncated to
+ * name_cap - 1 bytes; name may be NULL), dtype, shape and, for a view, its parent's id and offset
+ * (parent -1 for a root).  Output pointers may be NULL.  PSC_ERR_ARG for a bad id. */
+psc_status psc_buffer_desc(const psc_dag *dag, int32_t id, char *name, int32_t name_cap, int32_t *dtype,
+                           int64_t *rows, int64_t *cols, int32_t *parent, int64_t *row_off, int64_t *col_off);
+
+/* Description of kernel `id`: name, kind, input buffer ids (inputs[0..*n_in), capacity 2),
+ * output buffer id, GEMM alpha and task component.  Output pointers may be NULL. */
+psc_status psc_kernel_desc(const psc_dag *dag, int32_t id, char *name, int32_t name_cap, int32_t *kind,
+                           int32_t *inputs, int32_t *n_in, int32_t *output, float *alpha, int32_t *component);
+
+/* Edge `e` (in psc_add_edge order): producer kernel and buffer, consumer kernel and buffer. */
+psc_status psc_edge_desc(const psc_dag *dag, int32_t e, int32_t *src_kernel, int32_t *src_buffer,
+                         int32_t *dst_kernel, int32_t *dst_buffer);
+
 /* Puts a kernel in task component `component` (>= 0; all kernels start in component 0).
  * Components drive the classification below and PSC_MAP_COMPONENT. */
 psc_status psc_set_component(psc_dag *dag, int32_t kernel, int32_t component);

@@ -88,6 +88,11 @@ class psc_op_time(C.Structure):
                 ("end_us", C.c_float)]
 
 
+class psc_spec_info(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_kernels", "n_buffers", "n_edges", "n_components", "gpu_queues")] + \
+               [("reserved", C.c_int32 * 3)]
+
+
 class psc_mlp_train_opts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("shuffle_seed", C.c_uint64),
@@ -111,6 +116,12 @@ _SIGS = {
     "psc_set_component": [_P, _I, _I],
     "psc_bind_device": [_P, _S, _P, C.c_size_t],
     "psc_dag_info": [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
+    "psc_dag_from_json": [_S, C.POINTER(_S), C.POINTER(_I64), _I, C.POINTER(_P), C.POINTER(psc_spec_info)],
+    "psc_buffer_desc": [_P, _I, C.c_char_p, _I, C.POINTER(_I), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I),
+                        C.POINTER(_I64), C.POINTER(_I64)],
+    "psc_kernel_desc": [_P, _I, C.c_char_p, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
+                        C.POINTER(C.c_float), C.POINTER(_I)],
+    "psc_edge_desc": [_P, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
     "psc_buffer_id": [_P, _S, C.POINTER(_I)],
     "psc_dag_classify": [_P, _I, C.POINTER(_I), C.POINTER(_I)],
     "psc_schedule": [_P, _I, C.POINTER(psc_sched_opts), C.POINTER(_P)],
@@ -227,6 +238,76 @@ def psc_dag_info(dag):
     a, b, c = _I(), _I(), _I()
     _check(_lib.psc_dag_info(dag, C.byref(a), C.byref(b), C.byref(c)))
     return a.value, b.value, c.value
+
+
+def psc_dag_from_json(text, symbols=None):
+    """The specification file (JSON text) as a new DAG; returns (dag, info dict)."""
+    symbols = dict(symbols or {})
+    names = (_S * max(1, len(symbols)))(*[_b(k) for k in symbols])
+    vals = (_I64 * max(1, len(symbols)))(*[int(v) for v in symbols.values()])
+    h = _P()
+    info = psc_spec_info()
+    _check(_lib.psc_dag_from_json(_b(text), names, vals, len(symbols), C.byref(h), C.byref(info)))
+    return h, {f: getattr(info, f) for f, _ in psc_spec_info._fields_ if f != "reserved"}
+
+
+def psc_buffer_desc(dag, bid):
+    name = C.create_string_buffer(256)
+    dt, par = _I(), _I()
+    r, c, ro, co = _I64(), _I64(), _I64(), _I64()
+    _check(_lib.psc_buffer_desc(dag, int(bid), name, 256, C.byref(dt), C.byref(r), C.byref(c), C.byref(par),
+                                C.byref(ro), C.byref(co)))
+    return {"name": name.value.decode(), "dtype": {PSC_F32: "f32", PSC_BF16: "bf16"}[dt.value], "rows": r.value,
+            "cols": c.value, "parent": par.value, "row_off": ro.value, "col_off": co.value}
+
+
+def psc_kernel_desc(dag, kid):
+    name = C.create_string_buffer(256)
+    kind, n_in, out, comp = _I(), _I(), _I(), _I()
+    ins = (_I * 2)()
+    alpha = C.c_float()
+    _check(_lib.psc_kernel_desc(dag, int(kid), name, 256, C.byref(kind), ins, C.byref(n_in), C.byref(out),
+                                C.byref(alpha), C.byref(comp)))
+    kinds = {v: k for k, v in KINDS.items()}
+    return {"name": name.value.decode(), "kind": kinds[kind.value], "inputs": list(ins)[:n_in.value],
+            "output": out.value, "alpha": alpha.value, "component": comp.value}
+
+
+def psc_edge_desc(dag, e):
+    a, b, c, d = _I(), _I(), _I(), _I()
+    _check(_lib.psc_edge_desc(dag, int(e), C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+    return a.value, b.value, c.value, d.value
+
+
+def spec_from_dag(dag):
+    """The DAG's buffers, kernels, edges and components as a workload spec dict (the form
+    build_dag, run_spec and the oracle take)."""
+    nk, nb, ne = psc_dag_info(dag)
+    bufs = [psc_buffer_desc(dag, i) for i in range(nb)]
+    names = [b["name"] for b in bufs]
+    spec_bufs = [{"name": b["name"], "dtype": b["dtype"], "rows": b["rows"], "cols": b["cols"],
+                  "view_of": names[b["parent"]] if b["parent"] >= 0 else None, "row_off": b["row_off"],
+                  "col_off": b["col_off"]} for b in bufs]
+    kers, comp = [], []
+    for k in range(nk):
+        d = psc_kernel_desc(dag, k)
+        kers.append({"name": d["name"], "kind": d["kind"], "inputs": [names[i] for i in d["inputs"]],
+                     "outputs": [names[d["output"]]], "alpha": d["alpha"], "tile": 0})
+        comp.append(d["component"])
+    edges = []
+    for e in range(ne):
+        sk, sb, dk, db = psc_edge_desc(dag, e)
+        edges.append((sk, names[sb], dk, names[db]))
+    return {"buffers": spec_bufs, "kernels": kers, "edges": edges, "component": comp}
+
+
+def spec_from_json(text, symbols=None):
+    """(spec dict, info dict) of a specification file, lowered by the library."""
+    dag, info = psc_dag_from_json(text, symbols)
+    try:
+        return spec_from_dag(dag), info
+    finally:
+        psc_dag_destroy(dag)
 
 
 def psc_buffer_id(dag, name):

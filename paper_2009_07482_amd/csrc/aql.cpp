@@ -657,7 +657,8 @@ void AqlSchedule::exec(int32_t o) {
   }
   const AqlCopy &c = I.copies[o];
   if (!c.active) {
-    deps.clear();
+    // a skipped copy keeps its stream position: its waits pass to the stream's next op, since
+    // the planner leaves out waits of later ops that this op's waits already imply
     I.dispatched[o] = 1;
     return;
   }

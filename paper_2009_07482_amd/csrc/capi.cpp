@@ -41,6 +41,8 @@ int tile_cache_get(int M, int N, int K, int ab, int c);
 void tile_cache_clear();
 size_t tile_cache_size();
 int gemm_num_tiles();
+psc_dag *dag_from_json(const char *json, const char *const *sym_names, const int64_t *sym_values, int32_t n_sym,
+                       psc_spec_info *info);
 }  // namespace psc
 
 namespace {
@@ -195,6 +197,77 @@ psc_status psc_add_edge(psc_dag *dag, int32_t src_kernel, const char *src_output
     if (!g.bufs[sb].region().overlaps(g.bufs[db].region()))
       psc::fail(PSC_ERR_SHAPE, std::string("edge joins '") + src_output + "' and '" + dst_input + "', which share no storage");
     g.edges.push_back({src_kernel, sb, dst_kernel, db});
+  });
+}
+
+psc_status psc_dag_from_json(const char *json, const char *const *sym_names, const int64_t *sym_values,
+                             int32_t n_sym, psc_dag **out, psc_spec_info *info) {
+  psc_dag *made = nullptr;
+  const psc_status st = guard([&] {
+    need(out != nullptr, PSC_ERR_ARG, "NULL out");
+    psc_spec_info tmp;
+    made = psc::dag_from_json(json, sym_names, sym_values, n_sym, &tmp);
+    *out = made;
+    if (info) *info = tmp;
+  });
+  return st;
+}
+
+psc_status psc_buffer_desc(const psc_dag *dag, int32_t id, char *name, int32_t name_cap, int32_t *dtype,
+                           int64_t *rows, int64_t *cols, int32_t *parent, int64_t *row_off, int64_t *col_off) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    const psc::Dag &g = dag->g;
+    need(id >= 0 && id < int32_t(g.bufs.size()), PSC_ERR_ARG, "buffer id out of range");
+    const psc::Buffer &b = g.bufs[id];
+    if (name && name_cap > 0) {
+      const size_t n = std::min(b.name.size(), size_t(name_cap - 1));
+      std::memcpy(name, b.name.data(), n);
+      name[n] = 0;
+    }
+    if (dtype) *dtype = b.dtype;
+    if (rows) *rows = b.rows;
+    if (cols) *cols = b.cols;
+    if (parent) *parent = b.parent;
+    const psc::Buffer *p = b.parent >= 0 ? &g.bufs[b.parent] : nullptr;
+    if (row_off) *row_off = p ? b.r0 - p->r0 : 0;
+    if (col_off) *col_off = p ? b.c0 - p->c0 : 0;
+  });
+}
+
+psc_status psc_kernel_desc(const psc_dag *dag, int32_t id, char *name, int32_t name_cap, int32_t *kind,
+                           int32_t *inputs, int32_t *n_in, int32_t *output, float *alpha, int32_t *component) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    const psc::Dag &g = dag->g;
+    need(id >= 0 && id < int32_t(g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
+    const psc::Kernel &k = g.kers[id];
+    if (name && name_cap > 0) {
+      const size_t n = std::min(k.name.size(), size_t(name_cap - 1));
+      std::memcpy(name, k.name.data(), n);
+      name[n] = 0;
+    }
+    if (kind) *kind = k.kind;
+    if (inputs)
+      for (size_t i = 0; i < k.ins.size() && i < 2; ++i) inputs[i] = k.ins[i];
+    if (n_in) *n_in = int32_t(k.ins.size());
+    if (output) *output = k.outs.empty() ? -1 : k.outs[0];
+    if (alpha) *alpha = k.alpha;
+    if (component) *component = k.component;
+  });
+}
+
+psc_status psc_edge_desc(const psc_dag *dag, int32_t e, int32_t *src_kernel, int32_t *src_buffer,
+                         int32_t *dst_kernel, int32_t *dst_buffer) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    const psc::Dag &g = dag->g;
+    need(e >= 0 && e < int32_t(g.edges.size()), PSC_ERR_ARG, "edge id out of range");
+    const psc::Edge &x = g.edges[e];
+    if (src_kernel) *src_kernel = x.src;
+    if (src_buffer) *src_buffer = x.src_buf;
+    if (dst_kernel) *dst_kernel = x.dst;
+    if (dst_buffer) *dst_buffer = x.dst_buf;
   });
 }
 

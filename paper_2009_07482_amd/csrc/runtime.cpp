@@ -796,7 +796,11 @@ void run_dynamic(psc_sched &s, const std::vector<CopyDesc> &cd, bool timed) {
       }
       if (st.finished >= nk) break;
       const uint64_t seen = st.updates;
-      st.cv.wait(lk, [&] { return st.updates != seen; });   // sleep_till_cb_update
+      // sleep_till_cb_update; a kernel in flight always ends, so a minute with no callback
+      // means the runtime lost one: fail rather than wait for ever
+      if (!st.cv.wait_for(lk, std::chrono::seconds(60), [&] { return st.updates != seen; }))
+        fail(PSC_ERR_TIMEOUT, "dynamic schedule: no completion callback for 60 s (" +
+                                  std::to_string(st.finished) + " of " + std::to_string(nk) + " kernels finished)");
     }
   } catch (...) {
     // callbacks of what was dispatched still reference the state: let them all run first

@@ -1,0 +1,99 @@
+"""Workloads of the paper beyond the default attention DAG, on the GPU: DAGs lowered from
+specification files (Sec. IV-A), the paper's own head DAG with per-head output weights (Sec. V),
+the add-tree join, and back-to-back inferences whose copies overlap their neighbours' compute."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+import paper_2009_07482_amd as psc
+from gpu_helpers import normwise, oracle_outputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig7_spec.json")
+
+
+@pytest.mark.parametrize("dispatch", ["hip", "aql"])
+def test_fig7_worked_example(dispatch):
+    """The hand-worked values of the fixture, bit-exact (small integers)."""
+    doc = json.load(open(GOLDEN))
+    doc["kernels"][1]["dev"] = "gpu"
+    doc["cq"] = {"gpu": 2}
+    ex = doc["_worked_example"]
+    spec, info = psc.spec_from_json(json.dumps(doc), ex["symbols"])
+    inp = {k: np.array(v, np.float32) for k, v in ex["inputs"].items()}
+    out, _ = psc.run_spec(spec, inp, "fine", n_streams=info["gpu_queues"], mapper="component", dispatch=dispatch)
+    for name, want in ex["expected"].items():
+        np.testing.assert_array_equal(out[name], np.array(want, np.float32))
+
+
+@pytest.mark.parametrize("dt,n,heads", [("float", 256, 4), ("float", 100, 3), ("bfloat16", 256, 4)])
+def test_paper_heads_from_json(dt, n, heads):
+    """The paper's head DAG (Z_h = softmax(Q K^T) V W_h, concatenated) from its specification
+    file, on the file's queue count with one task component per head, against the oracle; the
+    coarse schedule gives the same bits."""
+    print(f"paper heads json {dt} n={n} H={heads}", flush=True)
+    spec, info = psc.spec_from_json(workloads.paper_heads_json(heads, dtype=dt), {"n": n})
+    inp = {k: v for k, v in workloads.paper_heads_inputs(1, heads, n).items() if k in workloads.host_inputs_of(spec)}
+    ref = oracle_outputs(spec, inp)["Z"]
+    fine, _ = psc.run_spec(spec, inp, "fine", n_streams=info["gpu_queues"], mapper="component")
+    coarse, _ = psc.run_spec(spec, inp, "coarse")
+    tol = 1e-4 if dt == "float" else 2e-2
+    assert normwise(fine["Z"], ref) < tol
+    np.testing.assert_array_equal(fine["Z"], coarse["Z"])
+    if dt == "bfloat16":
+        assert normwise(fine["Z"], oracle_outputs(spec, inp, emulate=True)["Z"]) < 5e-3
+
+
+@pytest.mark.parametrize("gd", ["f32", "bf16"])
+def test_addtree_join_matches_concat_join(gd):
+    """The add-tree join (sum of per-head partial projections) against the oracle and against the
+    concatenate-then-project join of the same inputs."""
+    n, d, h = 256, 512, 8
+    spec = workloads.mha_addtree_spec(n, d, h, gemm_dtype=gd)
+    inp = workloads.mha_inputs(2, n, d)
+    ref = oracle_outputs(spec, inp)["Y0"]
+    tree, _ = psc.run_spec(spec, inp, "fine", n_streams=4, mapper="component")
+    cat, _ = psc.run_spec(workloads.mha_spec(n, d, h, gemm_dtype=gd), inp, "fine", n_streams=4, mapper="component")
+    tol = 1e-4 if gd == "f32" else 2e-2
+    assert normwise(tree["Y0"], ref) < tol
+    assert normwise(tree["Y0"], cat["Y0"]) < 2 * tol
+
+
+@pytest.mark.parametrize("dispatch", ["hip", "aql"])
+def test_pipelined_inferences_overlap_copies(dispatch):
+    """Four back-to-back inferences in one schedule with copy streams: every output matches the
+    oracle, and the upload of inference i+1 or the read-back of inference i runs while a kernel
+    of another inference computes."""
+    count, n, d, h = 4, 512, 512, 8
+    spec = workloads.pipeline_spec(count, n, d, h, gemm_dtype="bf16")
+    inp = workloads.pipeline_inputs(0, count, n, d)
+    r = psc.SpecRunner(spec, "fine", n_streams=4, mapper="component", copy_stream=True, record_ops=True,
+                       dispatch=dispatch, timeout_ms=30000)
+    r.set_inputs(inp)
+    r.run()
+    r.run()
+    times = psc.psc_sched_op_times(r.sched)
+    ops = r.export()["ops"]
+    outs = {f"i{i}_Y0": r.result(f"i{i}_Y0") for i in range(count)}
+    r.close()
+    ref = oracle_outputs(spec, inp)
+    for name, want in ref.items():
+        assert normwise(outs[name], want) < 2e-2, name
+    inst = lambda k: int(spec["kernels"][k]["name"].split("_")[0][1:])
+    by_buf = {b["name"]: b for b in spec["buffers"]}
+    kern = [(t[2], t[3], inst(o["kernel"])) for t, o in zip(times, ops) if o["type"] == "kernel" and t[3] > t[2]]
+    cross = 0
+    for t, o in zip(times, ops):
+        if o["type"] == "kernel" or o["buffer"] is None or t[3] <= t[2]:
+            continue
+        name = o["buffer"]
+        if not name.startswith("i"):
+            continue       # shared weights
+        i = int(name.split("_")[0][1:])
+        cross += sum(1 for s, e, j in kern if j != i and s < t[3] and t[2] < e)
+    print(f"{dispatch}: instance copies overlapping another instance's kernels: {cross}", flush=True)
+    assert cross >= 1

@@ -395,3 +395,166 @@ def mlp_init(seed: int, n_features: int, hidden: int = 64) -> dict:
         r = 1.0 / math.sqrt(fan_in)
         out[name] = g.uniform(-r, r, size=shape).astype(np.float32)
     return out
+
+
+# ----------------------------------------------------------------------------------------------
+# The paper's own head DAG as a specification file (Sec. V with the JSON form of Sec. IV-A)
+# ----------------------------------------------------------------------------------------------
+
+def paper_heads_json(heads: int, dtype: str = "float", queues: int = 4) -> str:
+    """JSON text of the transformer layer as the paper draws it (Sec. V): per head h, with X and
+    every per-head weight beta x beta (symbol ``n``),
+      0: Q = X*WQ_h   1: K = X*WK_h   2: V = X*WV_h      (matmul)
+      3: Kt = K^T                                          (transpose)
+      4: A = Q*Kt                                          (matmul, no scaling)
+      5: B = softmax(A)                                    (softmax)
+      6: C = B*V                                           (matmul)
+      7: Z_h = C*W_h, written into columns [h*n, (h+1)*n) of Z, the concatenation (matmul)
+    Kernel ids 8h..8h+7, one task component per head, ``queues`` GPU command queues.  Inputs
+    are the buffers named X, WQ<h>, WK<h>, WV<h>, W<h>; the output is Z (n x heads*n)."""
+    import json as _json
+    t = dtype
+
+    def mm(kid, ins, out, m, nn, k):
+        return {"id": kid, "name": "matmul", "dev": "gpu", "workDimension": 2, "globalWorkSize": [m, nn, 1],
+                "inputBuffers": [dict(b, pos=i) for i, b in enumerate(ins)],
+                "outputBuffers": [dict(out, pos=2)],
+                "varArguments": [{"type": "int", "pos": 3, "value": m}, {"type": "int", "pos": 4, "value": nn},
+                                 {"type": "int", "pos": 5, "value": k}]}
+
+    kernels, edges, tc = [], [], []
+    for h in range(heads):
+        b = 8 * h
+        sq = {"type": t, "size": "n*n"}
+        kernels += [
+            mm(b + 0, [dict(sq, name="X"), dict(sq, name=f"WQ{h}")], sq, "n", "n", "n"),
+            mm(b + 1, [dict(sq, name="X"), dict(sq, name=f"WK{h}")], sq, "n", "n", "n"),
+            mm(b + 2, [dict(sq, name="X"), dict(sq, name=f"WV{h}")], sq, "n", "n", "n"),
+            {"id": b + 3, "name": "transpose", "dev": "gpu", "workDimension": 2, "globalWorkSize": ["n", "n", 1],
+             "inputBuffers": [dict(sq, pos=0)], "outputBuffers": [dict(sq, pos=1)],
+             "varArguments": [{"type": "int", "pos": 2, "value": "n"}, {"type": "int", "pos": 3, "value": "n"}]},
+            mm(b + 4, [sq, sq], dict(sq, type="float"), "n", "n", "n"),
+            {"id": b + 5, "name": "softmax", "dev": "gpu", "workDimension": 1, "globalWorkSize": ["n", 1, 1],
+             "inputBuffers": [{"type": "float", "size": "n*n", "pos": 0}], "outputBuffers": [dict(sq, pos=1)],
+             "varArguments": [{"type": "int", "pos": 2, "value": "n"}, {"type": "int", "pos": 3, "value": "n"}]},
+            mm(b + 6, [sq, sq], sq, "n", "n", "n"),
+            mm(b + 7, [sq, dict(sq, name=f"W{h}")],
+               {"type": "float", "size": "n*n", "name": f"Z{h}", "view_of": "Z", "row_off": 0,
+                "col_off": f"{h}*n"}, "n", "n", "n"),
+        ]
+        edges += [f"{b + 0},2 -> {b + 4},0", f"{b + 1},2 -> {b + 3},0", f"{b + 3},1 -> {b + 4},1",
+                  f"{b + 4},2 -> {b + 5},0", f"{b + 5},1 -> {b + 6},0", f"{b + 2},2 -> {b + 6},1",
+                  f"{b + 6},2 -> {b + 7},0"]
+        tc.append(list(range(b, b + 8)))
+    doc = {"symbols": {"n": 256},
+           "buffers": [{"name": "Z", "type": "float", "rows": "n", "cols": f"{heads}*n"}],
+           "kernels": kernels, "edges": edges, "tc": tc, "cq": {"gpu": queues}}
+    return _json.dumps(doc, indent=1)
+
+
+def paper_heads_inputs(seed: int, heads: int, n: int) -> dict:
+    """X ~ N(0, 1) (n x n), then per head WQ, WK, WV, W ~ N(0, 1/n) (n x n), in that order."""
+    g = rng(seed)
+    out = {"X": g.standard_normal((n, n)).astype(np.float32)}
+    s = 1.0 / math.sqrt(n)
+    for h in range(heads):
+        for w in ("WQ", "WK", "WV", "W"):
+            out[f"{w}{h}"] = (g.standard_normal((n, n)) * s).astype(np.float32)
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Attention with the add-tree join: Y = sum_h O_h * Wo[h*dh:(h+1)*dh, :]
+# ----------------------------------------------------------------------------------------------
+
+def mha_addtree_spec(n: int, d: int, heads: int, gemm_dtype: str = "f32") -> dict:
+    """One attention layer whose join is a sum of per-head projections instead of one projection
+    of the concatenated heads: head h's output O_h (n x dh) times the row window h of Wo
+    (dh x d) gives a partial P_h (n x d, f32); the partials are summed pairwise, in a balanced
+    binary tree of add kernels, into Y (f32).  Heads and their partial projections are one task
+    component each; the adds are one more.  Inputs as ``mha_inputs`` with layers = 1."""
+    assert d % heads == 0
+    dh = d // heads
+    gd = gemm_dtype
+    alpha = 1.0 / math.sqrt(dh)
+    bufs = [_buf("X", gd, n, d)] + [_buf(f"{w}0", gd, d, d) for w in ("Wq", "Wk", "Wv", "Wo")]
+    kers, edges, comp = [], [], []
+    level = []   # (kernel index, buffer name) of each partial
+    for h in range(heads):
+        t = f"L0H{h}"
+        for w in ("Wq", "Wk", "Wv"):
+            bufs.append(_buf(f"{w}0_h{h}", gd, d, dh, view_of=f"{w}0", col_off=h * dh))
+        bufs.append(_buf(f"Wo0_r{h}", gd, dh, d, view_of="Wo0", row_off=h * dh))
+        for b in ("Q", "K", "V", "O"):
+            bufs.append(_buf(f"{t}_{b}", gd, n, dh))
+        bufs += [_buf(f"{t}_Kt", gd, dh, n), _buf(f"{t}_S", "f32", n, n), _buf(f"{t}_P", gd, n, n),
+                 _buf(f"{t}_Y", "f32", n, d)]
+        kq, kk, kv, kkt, ks, kp, ko, ky = range(len(kers), len(kers) + 8)
+        kers += [
+            _ker(f"{t}_q", "gemm", ["X", f"Wq0_h{h}"], [f"{t}_Q"]),
+            _ker(f"{t}_k", "gemm", ["X", f"Wk0_h{h}"], [f"{t}_K"]),
+            _ker(f"{t}_v", "gemm", ["X", f"Wv0_h{h}"], [f"{t}_V"]),
+            _ker(f"{t}_kt", "transpose", [f"{t}_K"], [f"{t}_Kt"]),
+            _ker(f"{t}_s", "gemm", [f"{t}_Q", f"{t}_Kt"], [f"{t}_S"], alpha=alpha),
+            _ker(f"{t}_p", "softmax", [f"{t}_S"], [f"{t}_P"]),
+            _ker(f"{t}_o", "gemm", [f"{t}_P", f"{t}_V"], [f"{t}_O"]),
+            _ker(f"{t}_y", "gemm", [f"{t}_O", f"Wo0_r{h}"], [f"{t}_Y"]),
+        ]
+        comp += [h] * 8
+        edges += [(kk, f"{t}_K", kkt, f"{t}_K"), (kq, f"{t}_Q", ks, f"{t}_Q"), (kkt, f"{t}_Kt", ks, f"{t}_Kt"),
+                  (ks, f"{t}_S", kp, f"{t}_S"), (kp, f"{t}_P", ko, f"{t}_P"), (kv, f"{t}_V", ko, f"{t}_V"),
+                  (ko, f"{t}_O", ky, f"{t}_O")]
+        level.append((ky, f"{t}_Y"))
+    depth = 0
+    while len(level) > 1:
+        nxt = []
+        for i in range(0, len(level) - 1, 2):
+            (ka, a), (kb, b) = level[i], level[i + 1]
+            out = "Y0" if len(level) == 2 else f"sum{depth}_{i // 2}"
+            bufs.append(_buf(out, "f32", n, d))
+            kid = len(kers)
+            kers.append(_ker(f"add{depth}_{i // 2}", "add", [a, b], [out]))
+            comp.append(heads)
+            edges += [(ka, a, kid, a), (kb, b, kid, b)]
+            nxt.append((kid, out))
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+        depth += 1
+    if heads == 1:   # no add: the single partial is the output
+        bufs[-1]["name"] = "Y0"
+        kers[-1]["outputs"] = ["Y0"]
+    return {"buffers": bufs, "kernels": kers, "edges": edges, "component": comp}
+
+
+# ----------------------------------------------------------------------------------------------
+# Back-to-back inferences: several attention instances in one schedule, sharing one weight set
+# ----------------------------------------------------------------------------------------------
+
+def pipeline_spec(count: int, n: int, d: int, heads: int, layers: int = 1, gemm_dtype: str = "f32") -> dict:
+    """``count`` independent inferences of the attention DAG over the same weights, instance i
+    its own X<i>/Y<i> and kernels ("i<i>_" prefix), one task component per instance and head
+    (so a clustering mapper spreads each instance's heads); with copy streams the upload of
+    inference i+1 and the read-back of inference i overlap compute of its neighbours."""
+    bufs, kers, edges, comp = [], [], [], []
+    seen = set()
+    for i in range(count):
+        s = mha_spec(n, d, heads, layers, gemm_dtype=gemm_dtype, prefix=f"i{i}_", weight_prefix="")
+        off = len(kers)
+        for b in s["buffers"]:
+            if b["name"] not in seen:
+                seen.add(b["name"])
+                bufs.append(b)
+        kers += s["kernels"]
+        edges += [(a + off, x, c + off, y) for a, x, c, y in s["edges"]]
+        comp += [i * (heads + 1) + c for c in s["component"]]
+    return {"buffers": bufs, "kernels": kers, "edges": edges, "component": comp}
+
+
+def pipeline_inputs(seed: int, count: int, n: int, d: int, layers: int = 1) -> dict:
+    """The shared weights as ``mha_inputs(seed, ...)`` draws them, then X<i> ~ N(0, 1) per
+    instance from ``default_rng(seed + 1 + i)``."""
+    out = {k: v for k, v in mha_inputs(seed, n, d, layers).items() if k != "X"}
+    for i in range(count):
+        out[f"i{i}_X"] = rng(seed + 1 + i).standard_normal((n, d)).astype(np.float32)
+    return out
