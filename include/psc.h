@@ -52,7 +52,9 @@ typedef enum psc_status {
   PSC_ERR_HIP = -7,      /* a HIP runtime call failed (message names it) */
   PSC_ERR_OOM = -8,      /* device or host allocation failed */
   PSC_ERR_UNSUPPORTED = -9,
-  PSC_ERR_TIMEOUT = -10  /* a run did not finish within psc_sched_opts.timeout_ms */
+  PSC_ERR_TIMEOUT = -10, /* a run did not finish within psc_sched_opts.timeout_ms */
+  PSC_ERR_IO = -11       /* a file could not be read or written, or its contents are truncated,
+                            altered (checksum), malformed or hold non-finite values */
 } psc_status;
 
 typedef enum psc_dtype { PSC_F32 = 0, PSC_BF16 = 1 } psc_dtype;
@@ -414,6 +416,14 @@ psc_status psc_sched_component_times(const psc_sched *sched, float *done_us, int
 psc_status psc_sched_device_ptr(const psc_sched *sched, const char *name, void **dptr,
                                 int64_t *ld);
 
+/* [GPU after prepare] Copies the current device contents of buffer `name` (any buffer or view,
+ * also intermediates that no isolated read brings back) into host memory, rows x cols elements of
+ * its dtype packed row-major (BF16 as bfloat16 bits); bytes must equal that size (PSC_ERR_SHAPE
+ * otherwise).  Waits for all work on the device first.  For inspection and tests: a DAG's
+ * intermediate results live on the device between the kernels of Sec. III's dependent edges.
+ * PSC_ERR_STATE before psc_sched_prepare, PSC_ERR_NAME for an unknown name. */
+psc_status psc_sched_read(const psc_sched *sched, const char *name, void *host, size_t bytes);
+
 /* [GPU] Launches kernel `kernel` of a prepared schedule `iters` times back to back on its own
  * stream, on the storage the schedule uses, and returns the mean duration per launch measured
  * with HIP events on that stream.  For kernel-level timing. */
@@ -492,6 +502,24 @@ psc_status psc_mlp_predict(psc_mlp *m, const float *x, int64_t n, float *y);
  * without changing the parameters.  For gradient checks. */
 psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss);
 
+/* [GPU] Saves the model's full training state to `path`: parameters, Adam first and second
+ * moments and step count, and the feature scaling, with a 64-bit FNV-1a checksum of the contents
+ * (a binary file of fixed size; written to path.tmp and renamed, so a reader never sees half a
+ * file).  psc_mlp_load restores all of it, so psc_mlp_train continues exactly where it stopped
+ * (training 2 passes equals 1 pass, save, load into a new model, 1 pass, bit for bit, with
+ * shuffle_seed 0).  Errors: PSC_ERR_IO (cannot write), PSC_ERR_HIP.
+ * The paper's future work (Sec. VII) names machine-learning assisted scheduling; keeping the
+ * trained model lets a scheduler start from it. */
+psc_status psc_mlp_save(psc_mlp *m, const char *path);
+/* [GPU] Loads a file written by psc_mlp_save into m.  The file is checked whole first -- size,
+ * magic, network shape, checksum, every value finite, scales positive, second moments >= 0 --
+ * and on any failure m is left unchanged and PSC_ERR_IO names the reason.  A caller that cannot
+ * load its model schedules with the heuristic (psc_sched_opts.cost = NULL). */
+psc_status psc_mlp_load(psc_mlp *m, const char *path);
+/* Host-only: the checks of psc_mlp_load without a model; *step (may be NULL) = the saved Adam
+ * step count.  PSC_OK if the file would load. */
+psc_status psc_mlp_file_check(const char *path, int64_t *step);
+
 /* [GPU] Trains on n samples (features x, targets t = ln microseconds): opts->epochs passes of
  * mini-batch Adam steps.  epoch_loss[e] (may be NULL) receives the mean squared error over all n
  * samples after pass e.  Errors: PSC_ERR_ARG (sizes, hyper-parameters), PSC_ERR_HIP. */
@@ -550,6 +578,22 @@ psc_status psc_tile_cache_get(int32_t M, int32_t N, int32_t K, int32_t ab_dtype,
 
 /* Empties the cache; *n_removed (may be NULL) receives the number of entries it held. */
 psc_status psc_tile_cache_clear(int32_t *n_removed);
+/* [GPU] The key a saved tile cache is valid for on `device`: its architecture name (gcnArchName),
+ * compute-unit count, the HIP runtime version, this library's ABI version and tile count, as one
+ * word (e.g. "gfx950:sramecc+:xnack-/cu256/hip70226015/abi1/tiles17").  key gets at most cap
+ * bytes including the NUL; PSC_ERR_ARG if it does not fit. */
+psc_status psc_tile_cache_key(int32_t device, char *key, int32_t cap);
+/* Host-only: writes every cached tile choice to `path` (text: a header, the key, one line per
+ * (M, N, K, operand dtype, output dtype, tile), a checksum line; written to path.tmp and renamed)
+ * under `key` (a word without blanks, normally psc_tile_cache_key's).  PSC_ERR_IO if it cannot
+ * be written. */
+psc_status psc_tile_cache_save(const char *path, const char *key);
+/* Host-only: merges the choices saved in `path` into the cache (a loaded entry replaces the
+ * cached one for its shape).  The file is checked whole before anything is merged: PSC_ERR_IO
+ * if it is missing, malformed, altered (checksum) or names a tile outside 1 .. count-1;
+ * PSC_ERR_STATE if it was saved under another key (another architecture, runtime or library
+ * version: its timings do not apply).  *n_loaded (may be NULL) = entries merged. */
+psc_status psc_tile_cache_load(const char *path, const char *key, int32_t *n_loaded);
 
 /* [GPU] Times every tile configuration for C (M x N) = A (M x K) * B (K x N) on zero-filled
  * device buffers (iters back-to-back launches between HIP events, after 3 warm-up launches),

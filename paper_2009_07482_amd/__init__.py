@@ -31,7 +31,8 @@ _lib = C.CDLL(LIB_PATH)
 PSC_OK = 0
 STATUS = {0: "PSC_OK", -1: "PSC_ERR_ARG", -2: "PSC_ERR_NAME", -3: "PSC_ERR_SHAPE", -4: "PSC_ERR_CYCLE",
           -5: "PSC_ERR_RACE", -6: "PSC_ERR_STATE", -7: "PSC_ERR_HIP", -8: "PSC_ERR_OOM",
-          -9: "PSC_ERR_UNSUPPORTED", -10: "PSC_ERR_TIMEOUT"}
+          -9: "PSC_ERR_UNSUPPORTED", -10: "PSC_ERR_TIMEOUT", -11: "PSC_ERR_IO"}
+PSC_ERR_ARG, PSC_ERR_STATE, PSC_ERR_IO = -1, -6, -11
 PSC_F32, PSC_BF16 = 0, 1
 DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
 PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
@@ -133,6 +134,7 @@ _SIGS = {
     "psc_run": [_P, C.POINTER(psc_host_io), _I, C.POINTER(psc_run_stats)],
     "psc_sched_op_times": [_P, C.POINTER(psc_op_time), _I, C.POINTER(_I)],
     "psc_sched_device_ptr": [_P, _S, C.POINTER(_P), C.POINTER(_I64)],
+    "psc_sched_read": [_P, C.c_char_p, C.c_void_p, C.c_size_t],
     "psc_kernel_time": [_P, _I, _I, C.POINTER(C.c_float)],
     "psc_sched_destroy": [_P],
     "psc_host_alloc": [C.c_size_t, C.POINTER(_P)],
@@ -143,6 +145,12 @@ _SIGS = {
     "psc_tile_cache_set": [_I, _I, _I, _I, _I, _I],
     "psc_tile_cache_get": [_I, _I, _I, _I, _I, C.POINTER(_I)],
     "psc_tile_cache_clear": [C.POINTER(_I)],
+    "psc_tile_cache_key": [_I, C.c_char_p, _I],
+    "psc_tile_cache_save": [C.c_char_p, C.c_char_p],
+    "psc_tile_cache_load": [C.c_char_p, C.c_char_p, C.POINTER(_I)],
+    "psc_mlp_save": [_P, C.c_char_p],
+    "psc_mlp_load": [_P, C.c_char_p],
+    "psc_mlp_file_check": [C.c_char_p, C.POINTER(_I64)],
     "psc_autotune_gemm": [_I, _I, _I, _I, _I, _I, _I, C.POINTER(_I), C.POINTER(C.c_float),
                           C.POINTER(C.c_float), _I],
     "psc_autotune_dag": [_P, _I, _I, C.POINTER(_I)],
@@ -566,6 +574,15 @@ def psc_sched_device_ptr(sched, name):
     return p.value, ld.value
 
 
+def psc_sched_read(sched, name, rows, cols, dtype):
+    """Current device contents of buffer ``name`` (rows x cols of ``dtype``) as float32."""
+    es = 2 if dtype == "bf16" else 4
+    raw = np.empty(int(rows) * int(cols), np.uint16 if es == 2 else np.float32)
+    _check(_lib.psc_sched_read(sched, _b(name), raw.ctypes.data, raw.nbytes))
+    raw = raw.reshape(int(rows), int(cols))
+    return from_bf16_bits(raw) if es == 2 else raw
+
+
 def psc_kernel_time(sched, kernel, iters=20):
     t = C.c_float()
     _check(_lib.psc_kernel_time(sched, int(kernel), int(iters), C.byref(t)))
@@ -606,6 +623,37 @@ def psc_tile_cache_clear():
     n = _I()
     _check(_lib.psc_tile_cache_clear(C.byref(n)))
     return n.value
+
+
+def psc_tile_cache_key(device=0):
+    buf = C.create_string_buffer(256)
+    _check(_lib.psc_tile_cache_key(int(device), buf, 256))
+    return buf.value.decode()
+
+
+def psc_tile_cache_save(path, key):
+    _check(_lib.psc_tile_cache_save(os.fsencode(path), key.encode()))
+
+
+def psc_tile_cache_load(path, key):
+    n = _I()
+    _check(_lib.psc_tile_cache_load(os.fsencode(path), key.encode(), C.byref(n)))
+    return n.value
+
+
+def psc_mlp_save(m, path):
+    _check(_lib.psc_mlp_save(m, os.fsencode(path)))
+
+
+def psc_mlp_load(m, path):
+    _check(_lib.psc_mlp_load(m, os.fsencode(path)))
+
+
+def psc_mlp_file_check(path):
+    """Saved Adam step count of a valid cost-model file; PscError(PSC_ERR_IO) otherwise."""
+    step = _I64()
+    _check(_lib.psc_mlp_file_check(os.fsencode(path), C.byref(step)))
+    return step.value
 
 
 def psc_autotune_gemm(M, N, K, ab="f32", c="f32", iters=50, device=0):
@@ -788,6 +836,11 @@ class SpecRunner:
 
     def result(self, name):
         return self.outputs[name].get()
+
+    def read_device(self, name):
+        """Any buffer's current device contents (intermediates included) as float32."""
+        b = {x["name"]: x for x in self.spec["buffers"]}[name]
+        return psc_sched_read(self.sched, name, b["rows"], b["cols"], b["dtype"])
 
     def export(self):
         return export_schedule(self.spec, self.sched)

@@ -29,7 +29,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-u
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
-SOURCES = ["dag.cpp", "spec.cpp", "sched.cpp", "dispatch.cpp", "capi.cpp", "runtime.cpp", "aql.cpp", "kernels.hip",
+SOURCES = ["dag.cpp", "spec.cpp", "sched.cpp", "dispatch.cpp", "capi.cpp", "runtime.cpp", "aql.cpp", "persist.cpp", "kernels.hip",
            "mlp.hip", "persistent.hip"]
 LLVM = "/opt/rocm/llvm/bin"
 HSACO = os.path.join(PKG, "libpsc_kernels.hsaco")

@@ -53,6 +53,10 @@ class CostModel:
     def predict_us(self, X):
         return psc.psc_cost_predict(X, self.handle)
 
+    def save(self, path):
+        """Parameters, Adam state and feature scaling to ``path`` (psc_mlp_save)."""
+        psc.psc_mlp_save(self.handle, path)
+
     def close(self):
         if self.handle is not None:
             psc.psc_mlp_destroy(self.handle)
@@ -84,6 +88,23 @@ def fit(X, t, epochs=60, batch=256, lr=1e-3, seed=0, device=0):
         psc.psc_mlp_destroy(h)
         raise
     return CostModel(h, mean, std, losses)
+
+
+def load(path, device=0):
+    """(CostModel, None) for a cost-model file that loads, else (None, reason): a missing,
+    truncated, altered or non-finite file is refused whole by the library, and the caller then
+    schedules with the roofline heuristic (``cost=None``)."""
+    try:
+        psc.psc_mlp_file_check(path)
+    except psc.PscError as e:
+        return None, str(e)
+    h = psc.psc_mlp_create(device)
+    try:
+        psc.psc_mlp_load(h, path)
+    except psc.PscError as e:
+        psc.psc_mlp_destroy(h)
+        return None, str(e)
+    return CostModel(h, None, None, None), None
 
 
 def mape(pred_us, t_log_us):

@@ -730,17 +730,13 @@ void AqlSchedule::op_times(std::vector<float> &start_us, std::vector<float> &end
   const size_t n = I.plan->ops.size();
   start_us.assign(n, 0.f);
   end_us.assign(n, 0.f);
+  // dispatch and copy times both come in the HSA system clock domain (no tick conversion)
   uint64_t freq = 0;
   PSC_HSA(hsa_system_get_info(HSA_SYSTEM_INFO_TIMESTAMP_FREQUENCY, &freq));
   const double us_per_tick = 1e6 / double(freq ? freq : 1);
-  auto sys = [&](uint64_t tick) {
-    uint64_t v = 0;
-    PSC_HSA(hsa_amd_profiling_convert_tick_to_system_domain(I.ag->gpu, tick, &v));
-    return v;
-  };
   hsa_amd_profiling_dispatch_time_t t0{};
   PSC_HSA(hsa_amd_profiling_get_dispatch_time(I.ag->gpu, I.start_sig, &t0));
-  const uint64_t base = sys(t0.end);
+  const uint64_t base = t0.end;
   auto rel = [&](uint64_t v) { return float((double(int64_t(v - base))) * us_per_tick); };
   for (size_t o = 0; o < n; ++o) {
     const Op &op = I.plan->ops[o];
@@ -748,8 +744,8 @@ void AqlSchedule::op_times(std::vector<float> &start_us, std::vector<float> &end
       if (!I.kern[o]) continue;
       hsa_amd_profiling_dispatch_time_t t{};
       PSC_HSA(hsa_amd_profiling_get_dispatch_time(I.ag->gpu, I.sig[o], &t));
-      start_us[o] = rel(sys(t.start));
-      end_us[o] = rel(sys(t.end));
+      start_us[o] = rel(t.start);
+      end_us[o] = rel(t.end);
     } else if (I.copies[o].active) {
       hsa_amd_profiling_async_copy_time_t t{};
       PSC_HSA(hsa_amd_profiling_get_async_copy_time(I.sig[o], &t));

@@ -16,6 +16,7 @@
 #include "core.hpp"
 #include "dispatch.hpp"
 #include "mlp.hpp"
+#include "persist.hpp"
 
 namespace psc {
 void prepare(psc_sched &s);
@@ -27,6 +28,7 @@ int32_t aql_check(const psc_sched &s, char *why, int32_t why_cap);
 void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t cap, int32_t *n_tasks,
                   int32_t *work_off);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
+void sched_read(const psc_sched &s, const char *name, void *host, size_t bytes);
 float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
 void host_free(void *p);
@@ -571,6 +573,31 @@ psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, f
   });
 }
 
+psc_status psc_mlp_save(psc_mlp *m, const char *path) {
+  return guard([&] {
+    need(m && path, PSC_ERR_ARG, "NULL argument");
+    psc::MlpState st;
+    psc::mlp_get_state(*m, st);
+    psc::mlp_file_write(path, st);
+  });
+}
+
+psc_status psc_mlp_load(psc_mlp *m, const char *path) {
+  return guard([&] {
+    need(m && path, PSC_ERR_ARG, "NULL argument");
+    const psc::MlpState st = psc::mlp_file_read(path);   // everything checked before any change
+    psc::mlp_put_state(*m, st);
+  });
+}
+
+psc_status psc_mlp_file_check(const char *path, int64_t *step) {
+  return guard([&] {
+    need(path != nullptr, PSC_ERR_ARG, "NULL path");
+    const psc::MlpState st = psc::mlp_file_read(path);
+    if (step) *step = st.step;
+  });
+}
+
 psc_status psc_mlp_train(psc_mlp *m, const float *x, const float *t, int64_t n, const psc_mlp_train_opts *opts,
                          float *epoch_loss) {
   return guard([&] {
@@ -613,6 +640,13 @@ psc_status psc_sched_device_ptr(const psc_sched *sched, const char *name, void *
   return guard([&] {
     need(sched && name, PSC_ERR_ARG, "NULL argument");
     psc::device_ptr(*sched, name, dptr, ld);
+  });
+}
+
+psc_status psc_sched_read(const psc_sched *sched, const char *name, void *host, size_t bytes) {
+  return guard([&] {
+    need(sched && name && (host || bytes == 0), PSC_ERR_ARG, "NULL argument");
+    psc::sched_read(*sched, name, host, bytes);
   });
 }
 
@@ -709,6 +743,30 @@ psc_status psc_tile_cache_get(int32_t M, int32_t N, int32_t K, int32_t ab_dtype,
   return guard([&] {
     need(tile != nullptr, PSC_ERR_ARG, "NULL tile");
     *tile = psc::tile_cache_get(M, N, K, ab_dtype, c_dtype);
+  });
+}
+
+psc_status psc_tile_cache_key(int32_t device, char *key, int32_t cap) {
+  return guard([&] {
+    need(key != nullptr && cap > 0, PSC_ERR_ARG, "NULL key or cap <= 0");
+    const std::string k = psc::tile_cache_key(device);
+    need(int32_t(k.size()) < cap, PSC_ERR_ARG, "key buffer too small (" + std::to_string(k.size() + 1) + " bytes needed)");
+    std::memcpy(key, k.c_str(), k.size() + 1);
+  });
+}
+
+psc_status psc_tile_cache_save(const char *path, const char *key) {
+  return guard([&] {
+    need(path && key, PSC_ERR_ARG, "NULL argument");
+    psc::tile_cache_save(path, key);
+  });
+}
+
+psc_status psc_tile_cache_load(const char *path, const char *key, int32_t *n_loaded) {
+  return guard([&] {
+    need(path && key, PSC_ERR_ARG, "NULL argument");
+    const int n = psc::tile_cache_load(path, key);
+    if (n_loaded) *n_loaded = n;
   });
 }
 

@@ -1,9 +1,11 @@
 // Standalone gfx950 kernels of the DAG (one tile function call per block; the tile functions live
 // in tiles.hpp) and the launch factories that pick a kernel instance for a problem and fill a
 // Launch record that the runtime passes to hipLaunchKernel.
+#include <array>
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "tiles.hpp"
 
@@ -36,6 +38,16 @@ void tile_cache_clear() {
 size_t tile_cache_size() {
   std::lock_guard<std::mutex> lk(g_tile_mu);
   return g_tile_cache.size();
+}
+
+std::vector<std::array<int, 6>> tile_cache_entries() {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  std::vector<std::array<int, 6>> out;
+  for (const auto &kv : g_tile_cache) {
+    const auto &k = kv.first;
+    out.push_back({std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), kv.second});
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
+#include <vector>
 
 namespace psc {
 
@@ -66,6 +68,7 @@ void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
 int tile_cache_get(int M, int N, int K, int ab, int c);
 void tile_cache_clear();
 size_t tile_cache_size();
+std::vector<std::array<int, 6>> tile_cache_entries();   // (M, N, K, operand dtype, output dtype, tile)
 int gemm_auto_tile(int M, int N, int K, int dtype);
 
 }  // namespace psc

@@ -188,22 +188,35 @@ void check_n(int64_t n) {
   if (n < 1 || n > (int64_t(1) << 30)) fail(PSC_ERR_ARG, "sample count must be in [1, 2^30]");
 }
 
+// Device memory of one forward / backward pass: the samples (x, t), the per-sample activations
+// (z1, z2, y) and the back-propagated errors (dz1, dz2, dy).  The model's own buffers (grown on
+// demand) or the fixed scratch array of the allocation-free entry point.
+struct Work {
+  const float *x, *t;
+  float *z1, *z2, *y, *dz1, *dz2, *dy;
+};
+
+Work work_of(psc_mlp &m) { return Work{m.x, m.t, m.z1, m.z2, m.y, m.dz1, m.dz2, m.dy}; }
+
 // fwd over the first n uploaded samples (rows idx[0..n) if idx, else 0..n)
-void launch_fwd(psc_mlp &m, const int32_t *idx, int64_t n) {
-  const float *P = m.params, *norm = m.norm, *X = m.x;
+void launch_fwd(psc_mlp &m, const Work &w, const int32_t *idx, int64_t n) {
+  const float *P = m.params, *norm = m.norm, *X = w.x;
   int32_t nn = int32_t(n);
-  float *Z1 = m.z1, *Z2 = m.z2, *Y = m.y;
+  float *Z1 = w.z1, *Z2 = w.z2, *Y = w.y;
   void *args[] = {&P, &norm, &X, &idx, &nn, &Z1, &Z2, &Y};
   MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_fwd), dim3(blocks_for(n)), dim3(256), args, 0, m.stream));
 }
 
-void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const MlpTrainOpts &o, float *G) {
-  launch_fwd(m, idx, n);
+void launch_fwd(psc_mlp &m, const int32_t *idx, int64_t n) { launch_fwd(m, work_of(m), idx, n); }
+
+void launch_step(psc_mlp &m, const Work &w, const int32_t *idx, int64_t n, bool update, const MlpTrainOpts &o,
+                 float *G) {
+  launch_fwd(m, w, idx, n);
   {
-    const float *P = m.params, *T = m.t, *Z1 = m.z1, *Z2 = m.z2, *Y = m.y;
+    const float *P = m.params, *T = w.t, *Z1 = w.z1, *Z2 = w.z2, *Y = w.y;
     int32_t nn = int32_t(n);
     float scale = float(2.0 / double(n));
-    float *DZ1 = m.dz1, *DZ2 = m.dz2, *DY = m.dy;
+    float *DZ1 = w.dz1, *DZ2 = w.dz2, *DY = w.dy;
     void *args[] = {&P, &T, &idx, &nn, &scale, &Z1, &Z2, &Y, &DZ1, &DZ2, &DY};
     MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_delta), dim3(blocks_for(n)), dim3(256), args, 0,
                             m.stream));
@@ -214,13 +227,13 @@ void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const M
   a.V = m.v;
   a.G = G;
   a.norm = m.norm;
-  a.X = m.x;
+  a.X = w.x;
   a.idx = idx;
-  a.Z1 = m.z1;
-  a.Z2 = m.z2;
-  a.DZ1 = m.dz1;
-  a.DZ2 = m.dz2;
-  a.DY = m.dy;
+  a.Z1 = w.z1;
+  a.Z2 = w.z2;
+  a.DZ1 = w.dz1;
+  a.DZ2 = w.dz2;
+  a.DY = w.dy;
   a.n = int32_t(n);
   a.update = update ? 1 : 0;
   if (update) {
@@ -235,6 +248,10 @@ void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const M
   void *uargs[] = {&a};
   MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_update), dim3((kMlpP + 255) / 256), dim3(256), uargs, 0,
                           m.stream));
+}
+
+void launch_step(psc_mlp &m, const int32_t *idx, int64_t n, bool update, const MlpTrainOpts &o, float *G) {
+  launch_step(m, work_of(m), idx, n, update, o, G);
 }
 
 double mse_of(const std::vector<float> &y, const float *t, int64_t n) {
@@ -361,6 +378,32 @@ void mlp_train(psc_mlp &m, const float *x, const float *t, int64_t n, const MlpT
     }
   }
   MLP_HIP(hipStreamSynchronize(m.stream));
+}
+
+void mlp_get_state(psc_mlp &m, MlpState &st) {
+  std::lock_guard<std::mutex> lk(m.mu);
+  MLP_HIP(hipSetDevice(m.device));
+  MLP_HIP(hipStreamSynchronize(m.stream));
+  st.params.resize(kMlpP);
+  st.m.resize(kMlpP);
+  st.v.resize(kMlpP);
+  MLP_HIP(hipMemcpy(st.params.data(), m.params, kMlpP * 4, hipMemcpyDeviceToHost));
+  MLP_HIP(hipMemcpy(st.m.data(), m.m, kMlpP * 4, hipMemcpyDeviceToHost));
+  MLP_HIP(hipMemcpy(st.v.data(), m.v, kMlpP * 4, hipMemcpyDeviceToHost));
+  std::copy(m.h_mean, m.h_mean + kMlpF, st.mean);
+  std::copy(m.h_std, m.h_std + kMlpF, st.std_);
+  st.step = m.step;
+}
+
+void mlp_put_state(psc_mlp &m, const MlpState &st) {
+  mlp_set_norm(m, st.mean, st.std_);
+  std::lock_guard<std::mutex> lk(m.mu);
+  MLP_HIP(hipSetDevice(m.device));
+  MLP_HIP(hipStreamSynchronize(m.stream));
+  MLP_HIP(hipMemcpy(m.params, st.params.data(), kMlpP * 4, hipMemcpyHostToDevice));
+  MLP_HIP(hipMemcpy(m.m, st.m.data(), kMlpP * 4, hipMemcpyHostToDevice));
+  MLP_HIP(hipMemcpy(m.v, st.v.data(), kMlpP * 4, hipMemcpyHostToDevice));
+  m.step = st.step;
 }
 
 namespace {

@@ -33,6 +33,13 @@ struct MlpTrainOpts {
   uint64_t shuffle_seed = 0;  // 0: samples in their given order every epoch
 };
 
+// Everything training needs to resume: parameters, Adam moments and step count, feature scaling.
+struct MlpState {
+  std::vector<float> params, m, v;   // kMlpP each
+  float mean[kMlpF], std_[kMlpF];
+  int64_t step = 0;
+};
+
 }  // namespace psc
 
 struct psc_mlp {
@@ -59,6 +66,8 @@ void mlp_get_params(psc_mlp &m, float *p);
 void mlp_set_norm(psc_mlp &m, const float *mean, const float *std_);
 void mlp_predict(psc_mlp &m, const float *x, int64_t n, float *y);
 double mlp_grad(psc_mlp &m, const float *x, const float *t, int64_t n, float *grads);
+void mlp_get_state(psc_mlp &m, MlpState &st);
+void mlp_put_state(psc_mlp &m, const MlpState &st);   // state already validated
 void mlp_train(psc_mlp &m, const float *x, const float *t, int64_t n, const MlpTrainOpts &o, float *epoch_loss);
 
 

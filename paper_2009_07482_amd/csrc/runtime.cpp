@@ -1151,6 +1151,23 @@ void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld) 
   if (ld) *ld = buffer_ld(g, it->second);
 }
 
+void sched_read(const psc_sched &s, const char *name, void *host, size_t bytes) {
+  if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
+  const Dag &g = s.dag->g;
+  auto it = g.buf_by_name.find(name);
+  if (it == g.buf_by_name.end()) fail(PSC_ERR_NAME, std::string("unknown buffer '") + name + "'");
+  const Buffer &b = g.bufs[it->second];
+  const size_t es = size_t(elem_size(b.dtype)), row = size_t(b.cols) * es;
+  if (bytes != row * size_t(b.rows))
+    fail(PSC_ERR_SHAPE, std::string("buffer '") + name + "' holds " + std::to_string(row * size_t(b.rows)) +
+                            " bytes, not " + std::to_string(bytes));
+  if (!bytes) return;
+  PSC_HIP(hipSetDevice(s.dev->device));
+  PSC_HIP(hipDeviceSynchronize());   // whatever is in flight on the schedule's streams lands first
+  PSC_HIP(hipMemcpy2D(host, row, buffer_ptr(g, *s.dev, it->second), size_t(buffer_ld(g, it->second)) * es, row,
+                      size_t(b.rows), hipMemcpyDeviceToHost));
+}
+
 // Autotuner: times every GEMM tile configuration on device buffers of the given shape (seeded
 // values uniform in [-1, 1)) with back-to-back launches between HIP events, records the fastest in the tile cache and
 // returns it.  us_per_tile[t] (t < cap) receives each configuration's mean time (0 for t = 0).

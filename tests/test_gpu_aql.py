@@ -125,9 +125,13 @@ def test_component_marks():
         done = psc.psc_sched_component_times(r.sched)
         assert done.shape == (len(lengths),) and np.all(done > 0)
         assert done.max() <= st["makespan_ms"] * 1000 + 100
+    # BF16 GEMMs (the batch workload's dtype): 2e-2 against the exact oracle, tight against the
+    # storage-emulating one (two layers: no room for the chain to amplify rounding differences)
     want = oracle_outputs(spec, inp)
+    emul = oracle_outputs(spec, inp, emulate=True)
     for name, w in want.items():
-        assert normwise(r.result(name), w) < 1e-4
+        assert normwise(r.result(name), w) < 2e-2, name
+        assert normwise(r.result(name), emul[name]) < 5e-3, name
     r.close()
 
 

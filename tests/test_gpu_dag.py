@@ -223,14 +223,34 @@ def test_device_executor_node_times_respect_dependencies():
 @pytest.fixture(scope="module")
 def mha12():
     """12 stacked layers, 16 heads, d_model = n = 1024, BF16 GEMM operands (FP32 accumulation),
-    FP32 softmax: the last layer's output from the exact and the storage-emulating oracle."""
+    FP32 softmax: the last layer's output from the exact FP64 oracle."""
     n, d, h, L = 1024, 1024, 16, 12
     spec = workloads.mha_spec(n, d, h, L, gemm_dtype="bf16")
     inp = workloads.mha_inputs(0, n, d, L)
     y = f"Y{L - 1}"
     exact = odag.read_buffer(spec, odag.run_dag(spec, inp), y)
-    emul = odag.read_buffer(spec, odag.run_dag(spec, inp, emulate=True), y)
-    return spec, inp, y, exact, emul, {}
+    return spec, inp, (n, d, h, L), exact, {}
+
+
+# Layers checked one at a time against the storage-emulating oracle.  The stacked layers have no
+# residual or normalisation and amplify rounding-order differences: two valid emulations of the
+# BF16 storage (the oracle's FP64 accumulation, and FP32 accumulation like the GPU's) differ by
+# 1.0e-3 normwise after one layer but 9.7e-3 after twelve.  So the emulating oracle is a tight
+# reference only layer by layer, fed the GPU's own output of the previous layer.
+CHECK_LAYERS = (0, 5, 11)
+LAYER_TOL = 3e-3
+
+
+def _layer_errors(r, inp, shape):
+    n, d, h, L = shape
+    errs = {}
+    for l in CHECK_LAYERS:
+        x = inp["X"] if l == 0 else r.read_device(f"Y{l - 1}")
+        one = workloads.mha_spec(n, d, h, 1, gemm_dtype="bf16", final_dtype="f32" if l == L - 1 else "bf16")
+        oinp = {"X": x, **{f"{w}0": inp[f"{w}{l}"] for w in ("Wq", "Wk", "Wv", "Wo")}}
+        ref = oracle_outputs(one, oinp, emulate=True)["Y0"]
+        errs[l] = normwise(r.read_device(f"Y{l}"), ref)
+    return errs
 
 
 @pytest.mark.timeout(900)
@@ -239,22 +259,30 @@ def mha12():
                                        ("device", {})],
                          ids=["coarse", "fine-rr", "fine-component-copystream", "device"])
 def test_mha_12_layers_bf16_full_size(mha12, policy, kw):
-    """The full-size 12-layer DAG under each schedule: the final output Y11 (the only isolated
-    read; intermediate layers stay on the device) within 2e-2 of the exact FP64 oracle and within
-    5e-3 of the storage-emulating oracle; the stream schedules bit-identical to each other (same
-    kernels, no atomics, fixed reduction order).  The device executor picks its own GEMM tiles,
-    so it is held to the oracles only."""
-    spec, inp, y, exact, emul, seen = mha12
+    """The full-size 12-layer DAG under each schedule: the final output Y11 within 2e-2 of the
+    exact FP64 oracle; layers 0, 5 and 11, each recomputed by the storage-emulating oracle from
+    the GPU's own input to that layer, within 3e-3; the stream schedules bit-identical to each
+    other (same kernels, no atomics, fixed reduction order).  The device executor picks its own
+    GEMM tiles, so it is held to the oracles only."""
+    spec, inp, shape, exact, seen = mha12
+    y = f"Y{shape[3] - 1}"
     print(f"mha 12x1024 bf16 {policy} {kw}", flush=True)
     r = psc.SpecRunner(spec, policy, **kw)
-    r.set_inputs(inp)
-    st = r.run()
-    got = r.result(y)
-    r.close()
-    e1, e2 = normwise(got, exact), normwise(got, emul)
-    print(f"makespan with copies {st['makespan_ms']:.3f} ms; {y} error vs exact {e1:.3e}, "
-          f"vs emulating {e2:.3e}", flush=True)
-    assert e1 < 2e-2 and e2 < 5e-3
+    try:
+        r.set_inputs(inp)
+        st = r.run()
+        got = r.result(y)
+        np.testing.assert_array_equal(r.read_device(y), got)
+        # per-layer checks once for the stream schedules (they are bit-identical), and for the executor
+        layer = _layer_errors(r, inp, shape) if policy in ("coarse", "device") else None
+    finally:
+        r.close()
+    e1 = normwise(got, exact)
+    print(f"makespan with copies {st['makespan_ms']:.3f} ms; {y} error vs exact {e1:.3e}; "
+          f"per-layer vs emulating {layer}", flush=True)
+    assert e1 < 2e-2
+    if layer is not None:
+        assert all(v < LAYER_TOL for v in layer.values()), layer
     if policy != "device":
         if "streams" in seen:
             np.testing.assert_array_equal(got, seen["streams"])

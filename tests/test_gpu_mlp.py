@@ -8,7 +8,7 @@ import paper_2009_07482_amd as psc
 from paper_2009_07482_amd import costmodel
 from oracle import mlp as omlp
 from oracle import validator
-from gpu_helpers import normwise
+from gpu_helpers import normwise, oracle_outputs
 
 pytestmark = pytest.mark.gpu
 
@@ -172,5 +172,92 @@ def test_learned_model_beats_heuristic_on_held_out_dags():
         want, _ = psc.run_spec(spec, inp, "coarse")
         for k in want:
             assert np.array_equal(got[k], want[k]), k
+        # what the learned model changes in measured makespan: EFT under each model and round
+        # robin on held-out random DAGs and on attention DAGs (many small kernels), device-resident,
+        # the three schedules' runs interleaved, median of 9 each
+        dags = [workloads.random_dag_spec(sd, n_nodes=(40, 120), dim=(64, 1024)) for sd in range(1000, 1006)]
+        dags += [workloads.mha_spec(512, 512, 8), workloads.mha_spec(512, 512, 8, gemm_dtype="bf16")]
+        ratios_h, ratios_rr = [], []
+        for spec in dags:
+            rs = [psc.SpecRunner(spec, "fine", n_streams=4, mapper="eft", cost=cm.handle),
+                  psc.SpecRunner(spec, "fine", n_streams=4, mapper="eft", cost=None),
+                  psc.SpecRunner(spec, "fine", n_streams=4, mapper="rr")]
+            try:
+                for r in rs:
+                    r.run(with_inputs=False, with_outputs=False)
+                mk = [[], [], []]
+                for _ in range(9):
+                    for i, r in enumerate(rs):
+                        mk[i].append(r.run(with_inputs=False, with_outputs=False)["makespan_ms"])
+            finally:
+                for r in rs:
+                    r.close()
+            med = [float(np.median(m)) for m in mk]
+            ratios_h.append(med[0] / med[1])
+            ratios_rr.append(med[0] / med[2])
+            print(f"  {len(spec['kernels'])} kernels: eft-mlp {med[0]:.3f} ms, eft-heuristic {med[1]:.3f}, "
+                  f"rr {med[2]:.3f}", flush=True)
+        gm_h = float(np.exp(np.mean(np.log(ratios_h))))
+        gm_rr = float(np.exp(np.mean(np.log(ratios_rr))))
+        print(f"makespan eft-mlp / eft-heuristic: geometric mean {gm_h:.3f} (min {min(ratios_h):.3f}, "
+              f"max {max(ratios_h):.3f}); eft-mlp / rr {gm_rr:.3f}", flush=True)
     finally:
         cm.close()
+
+
+def test_save_load_resumes_training(tmp_path):
+    """Two passes of Adam equal one pass, save, load into a fresh model, one more pass -- bit for
+    bit: the file carries the parameters, both moments, the step count and the feature scaling."""
+    p = workloads.mlp_init(21, F)
+    x, t = _data(22, 300)
+    mean = np.linspace(-0.5, 0.5, F).astype(np.float32)
+    std = np.linspace(0.5, 1.5, F).astype(np.float32)
+    a, b, c = (psc.psc_mlp_create(0) for _ in range(3))
+    try:
+        for mm in (a, b):
+            psc.psc_mlp_set_norm(mm, mean, std)
+            psc.psc_mlp_set_params(mm, psc.mlp_flatten(p))
+        psc.psc_mlp_train(a, x, t, epochs=2, batch=64, lr=1e-2, shuffle_seed=0)
+        psc.psc_mlp_train(b, x, t, epochs=1, batch=64, lr=1e-2, shuffle_seed=0)
+        path = str(tmp_path / "model.bin")
+        psc.psc_mlp_save(b, path)
+        assert psc.psc_mlp_file_check(path) == 5          # ceil(300 / 64) Adam steps
+        psc.psc_mlp_load(c, path)
+        np.testing.assert_array_equal(psc.psc_mlp_predict(c, x), psc.psc_mlp_predict(b, x))
+        psc.psc_mlp_train(c, x, t, epochs=1, batch=64, lr=1e-2, shuffle_seed=0)
+        np.testing.assert_array_equal(psc.psc_mlp_get_params(c), psc.psc_mlp_get_params(a))
+    finally:
+        for mm in (a, b, c):
+            psc.psc_mlp_destroy(mm)
+
+
+def test_damaged_model_file_changes_nothing_and_falls_back(tmp_path):
+    p = workloads.mlp_init(23, F)
+    m = psc.psc_mlp_create(0)
+    try:
+        psc.psc_mlp_set_params(m, psc.mlp_flatten(p))
+        path = str(tmp_path / "model.bin")
+        psc.psc_mlp_save(m, path)
+        raw = bytearray(open(path, "rb").read())
+        raw[4321] ^= 0x01
+        bad = str(tmp_path / "bad.bin")
+        open(bad, "wb").write(bytes(raw))
+        psc.psc_mlp_set_params(m, psc.mlp_flatten(workloads.mlp_init(24, F)))
+        before = psc.psc_mlp_get_params(m)
+        with pytest.raises(psc.PscError) as e:
+            psc.psc_mlp_load(m, bad)
+        assert e.value.status == psc.PSC_ERR_IO
+        np.testing.assert_array_equal(psc.psc_mlp_get_params(m), before)
+        model, why = costmodel.load(bad)
+        assert model is None and "checksum" in why
+        # the heuristic schedules the DAG instead, and the result is still right
+        spec = workloads.mha_spec(128, 128, 2)
+        inp = workloads.mha_inputs(0, 128, 128)
+        out, _ = psc.run_spec(spec, inp, "fine", n_streams=2, mapper="eft", cost=None)
+        assert normwise(out["Y0"], oracle_outputs(spec, inp)["Y0"]) < 1e-4
+        good, why = costmodel.load(path)
+        assert why is None
+        np.testing.assert_array_equal(psc.psc_mlp_get_params(good.handle), psc.mlp_flatten(p))
+        good.close()
+    finally:
+        psc.psc_mlp_destroy(m)
