@@ -502,6 +502,21 @@ psc_status psc_mlp_predict(psc_mlp *m, const float *x, int64_t n, float *y);
  * without changing the parameters.  For gradient checks. */
 psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss);
 
+/* [GPU] psc_mlp_grad without any device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as psc_mlp_grad (the gradient is bit-identical to it; the
+ * loss is reduced on the device in float64, so it may differ from psc_mlp_grad's in the last
+ * bits), but the samples, activations, errors and gradient of the pass live in one fixed array
+ * of ~4.4 MB per GPU, held from the first call on that GPU until the process ends, so n is
+ * limited to PSC_MLP_STATIC_MAX rows: larger n gives PSC_ERR_ARG.  No hipMalloc or hipFree is
+ * made (the model's parameters were allocated by psc_mlp_create).  Every call on one GPU uses
+ * that GPU's array and leaves its last contents there; calls on one GPU are serialised by a lock
+ * in the library, so overlapping calls from several threads wait for each other rather than
+ * race.  x and t are host memory (n x PSC_FEATURES and n floats); grads (PSC_MLP_PARAMS floats)
+ * and loss may be NULL. */
+#define PSC_MLP_STATIC_MAX 4096
+psc_status psc_mlp_grad_static(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss);
+
 /* [GPU] Saves the model's full training state to `path`: parameters, Adam first and second
  * moments and step count, and the feature scaling, with a 64-bit FNV-1a checksum of the contents
  * (a binary file of fixed size; written to path.tmp and renamed, so a reader never sees half a

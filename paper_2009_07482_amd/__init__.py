@@ -102,6 +102,7 @@ class psc_mlp_train_opts(C.Structure):
 
 PSC_FEATURES = 12
 PSC_MLP_PARAMS = 5057
+PSC_MLP_STATIC_MAX = 4096
 
 _P = C.c_void_p
 _I = C.c_int32
@@ -162,6 +163,7 @@ _SIGS = {
     "psc_mlp_set_norm": [_P, C.c_void_p, C.c_void_p],
     "psc_mlp_predict": [_P, C.c_void_p, _I64, C.c_void_p],
     "psc_mlp_grad": [_P, C.c_void_p, C.c_void_p, _I64, C.c_void_p, C.POINTER(C.c_double)],
+    "psc_mlp_grad_static": [_P, C.c_void_p, C.c_void_p, _I64, C.c_void_p, C.POINTER(C.c_double)],
     "psc_mlp_train": [_P, C.c_void_p, C.c_void_p, _I64, C.POINTER(psc_mlp_train_opts), C.c_void_p],
     "psc_cost_predict": [_P, C.c_void_p, _I64, C.c_void_p],
     "psc_kernel_features": [_P, _I, _I, C.c_void_p],
@@ -517,6 +519,18 @@ def psc_mlp_grad(m, x, t):
     g = np.zeros(PSC_MLP_PARAMS, np.float32)
     loss = C.c_double()
     _check(_lib.psc_mlp_grad(m, x.ctypes.data, t.ctypes.data, x.shape[0], g.ctypes.data, C.byref(loss)))
+    return g, loss.value
+
+
+def psc_mlp_grad_static(m, x, t):
+    """psc_mlp_grad through the entry point that allocates no device memory (its scratch is a
+    fixed per-GPU array; at most PSC_MLP_STATIC_MAX rows)."""
+    import numpy as np
+    x = _f32(x, (-1, PSC_FEATURES))
+    t = _f32(t, (-1,))
+    g = np.zeros(PSC_MLP_PARAMS, np.float32)
+    loss = C.c_double()
+    _check(_lib.psc_mlp_grad_static(m, x.ctypes.data, t.ctypes.data, x.shape[0], g.ctypes.data, C.byref(loss)))
     return g, loss.value
 
 

@@ -573,6 +573,15 @@ psc_status psc_mlp_grad(psc_mlp *m, const float *x, const float *t, int64_t n, f
   });
 }
 
+psc_status psc_mlp_grad_static(psc_mlp *m, const float *x, const float *t, int64_t n, float *grads, double *loss) {
+  return guard([&] {
+    need(m && x && t, PSC_ERR_ARG, "NULL argument");
+    static_assert(PSC_MLP_STATIC_MAX == psc::kMlpStaticMax, "scratch size");
+    const double l = psc::mlp_grad_static(*m, x, t, n, grads);
+    if (loss) *loss = l;
+  });
+}
+
 psc_status psc_mlp_save(psc_mlp *m, const char *path) {
   return guard([&] {
     need(m && path, PSC_ERR_ARG, "NULL argument");

@@ -348,6 +348,97 @@ double mlp_grad(psc_mlp &m, const float *x, const float *t, int64_t n, float *gr
   return mse_of(y, t, n);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Allocation-free gradient (psc_mlp_grad_static): the same kernels as mlp_grad, with every
+// buffer of the pass in one fixed device array instead of memory the model allocates.
+// ---------------------------------------------------------------------------------------------
+
+namespace {
+
+// Layout of the scratch array, in floats: x (max x F), t, z1, z2, y, dz1, dz2, dy, the gradient
+// (kMlpP, padded) and the loss (one double).
+constexpr int64_t kSMax = kMlpStaticMax;
+constexpr int64_t kOffX = 0;
+constexpr int64_t kOffT = kOffX + kSMax * kMlpF;
+constexpr int64_t kOffZ1 = kOffT + kSMax;
+constexpr int64_t kOffZ2 = kOffZ1 + kSMax * kMlpH;
+constexpr int64_t kOffY = kOffZ2 + kSMax * kMlpH;
+constexpr int64_t kOffDZ1 = kOffY + kSMax;
+constexpr int64_t kOffDZ2 = kOffDZ1 + kSMax * kMlpH;
+constexpr int64_t kOffDY = kOffDZ2 + kSMax * kMlpH;
+constexpr int64_t kOffG = kOffDY + kSMax;
+constexpr int64_t kOffLoss = kOffG + ((kMlpP + 63) / 64) * 64;
+constexpr int64_t kScratchFloats = kOffLoss + 64;
+
+// One copy per GPU, held until the process ends.  Host code never passes this name to a kernel or
+// a copy: it is the host-side stand-in, and the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];   // one call at a time per GPU: every call shares its array
+float *g_scratch_ptr[kMaxDevices] = {};
+
+float *scratch_of(int device) {
+  if (g_scratch_ptr[device]) return g_scratch_ptr[device];
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    fail(PSC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<float *>(p);
+  return g_scratch_ptr[device];
+}
+
+// Mean squared error of y against t over n samples in float64: 256 threads, thread i sums samples
+// i, i + 256, ... in order, then a fixed-order tree over the threads.
+__global__ __launch_bounds__(256) void mlp_mse(const float *__restrict__ Y, const float *__restrict__ T, int32_t n,
+                                               double *__restrict__ out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int32_t s = threadIdx.x; s < n; s += 256) {
+    const double d = double(Y[s]) - double(T[s]);
+    acc = fma(d, d, acc);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0] / double(n);
+}
+
+}  // namespace
+
+double mlp_grad_static(psc_mlp &m, const float *x, const float *t, int64_t n, float *grads) {
+  if (n < 1 || n > kMlpStaticMax)
+    fail(PSC_ERR_ARG, "sample count must be in [1, " + std::to_string(kMlpStaticMax) + "] (the fixed scratch size)");
+  if (m.device < 0 || m.device >= kMaxDevices) fail(PSC_ERR_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(m.mu);
+  std::lock_guard<std::mutex> sk(g_scratch_mu[m.device]);
+  MLP_HIP(hipSetDevice(m.device));
+  float *base = scratch_of(m.device);
+  float *xs = base + kOffX, *ts = base + kOffT;
+  const Work w{xs, ts, base + kOffZ1, base + kOffZ2, base + kOffY, base + kOffDZ1, base + kOffDZ2, base + kOffDY};
+  float *G = base + kOffG;
+  double *L = reinterpret_cast<double *>(base + kOffLoss);
+  MLP_HIP(hipMemcpyAsync(xs, x, size_t(n) * kMlpF * 4, hipMemcpyHostToDevice, m.stream));
+  MLP_HIP(hipMemcpyAsync(ts, t, size_t(n) * 4, hipMemcpyHostToDevice, m.stream));
+  // every element the kernels read is written first in this call (x, t above; z, y, deltas by
+  // the passes; G and the loss entirely), so nothing left by an earlier call is seen
+  launch_step(m, w, nullptr, n, false, MlpTrainOpts{}, G);
+  {
+    const float *Y = w.y, *T = ts;
+    int32_t nn = int32_t(n);
+    void *args[] = {&Y, &T, &nn, &L};
+    MLP_HIP(hipLaunchKernel(reinterpret_cast<const void *>(&mlp_mse), dim3(1), dim3(256), args, 0, m.stream));
+  }
+  double loss = 0.0;
+  MLP_HIP(hipMemcpyAsync(&loss, L, sizeof(double), hipMemcpyDeviceToHost, m.stream));
+  if (grads) MLP_HIP(hipMemcpyAsync(grads, G, kMlpP * 4, hipMemcpyDeviceToHost, m.stream));
+  MLP_HIP(hipStreamSynchronize(m.stream));
+  return loss;
+}
+
 void mlp_train(psc_mlp &m, const float *x, const float *t, int64_t n, const MlpTrainOpts &o, float *epoch_loss) {
   check_n(n);
   if (o.epochs < 1 || o.batch < 1) fail(PSC_ERR_ARG, "epochs and batch must be >= 1");

@@ -25,6 +25,8 @@ constexpr int kMlpB2 = kMlpW2 + kMlpH * kMlpH;
 constexpr int kMlpW3 = kMlpB2 + kMlpH;
 constexpr int kMlpB3 = kMlpW3 + kMlpH;
 constexpr int kMlpP = kMlpB3 + 1;
+// Largest sample count of the allocation-free gradient (its fixed scratch holds this many).
+constexpr int64_t kMlpStaticMax = 4096;
 
 struct MlpTrainOpts {
   int32_t epochs = 50;
@@ -66,6 +68,7 @@ void mlp_get_params(psc_mlp &m, float *p);
 void mlp_set_norm(psc_mlp &m, const float *mean, const float *std_);
 void mlp_predict(psc_mlp &m, const float *x, int64_t n, float *y);
 double mlp_grad(psc_mlp &m, const float *x, const float *t, int64_t n, float *grads);
+double mlp_grad_static(psc_mlp &m, const float *x, const float *t, int64_t n, float *grads);
 void mlp_get_state(psc_mlp &m, MlpState &st);
 void mlp_put_state(psc_mlp &m, const MlpState &st);   // state already validated
 void mlp_train(psc_mlp &m, const float *x, const float *t, int64_t n, const MlpTrainOpts &o, float *epoch_loss);
