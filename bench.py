@@ -55,9 +55,13 @@ def parse():
     p.add_argument("--heldout", type=int, default=20, help="--config costmodel: held-out DAGs")
     p.add_argument("--epochs", type=int, default=100, help="--config costmodel: training passes")
     p.add_argument("--dump-samples", default=None, help="--config costmodel: save the samples (.npz)")
-    p.add_argument("--kernel-profile", choices=["dominant", "executor"], default=None,
-                   help="launch sequence for rocprofv3 counter runs (no timing line): the dominant "
-                        "kernel of the stream schedule, or the device executor, then a calibration copy")
+    p.add_argument("--kernel-profile", choices=["dominant", "executor", "timeline"], default=None,
+                   help="launch sequence for rocprofv3 runs (no timing line): the dominant kernel of the "
+                        "stream schedule, or the device executor, then a calibration copy; or "
+                        "(timeline) runs of one fine schedule, device-resident and with host copies")
+    p.add_argument("--fine-opts", default=None,
+                   help="--kernel-profile timeline: the fine schedule's options as JSON (default: "
+                        "the schedule autotuner's choice)")
     p.add_argument("--profile-tile", type=int, default=0,
                    help="with --kernel-profile: GEMM tile of the shape --profile-shape (0 = autotune)")
     p.add_argument("--profile-shape", default="512x64x512", help="MxNxK pinned by --profile-tile")
@@ -266,6 +270,35 @@ def kernel_profile(a):
                            "grid": (CAL_N // 64) * (CAL_N // 64), "read_bytes": CAL_N * CAL_N * 4,
                            "write_bytes": CAL_N * CAL_N * 4, "launches": 20}
     print(json.dumps(info), flush=True)
+
+
+def timeline_profile(a):
+    """Runs for a kernel and memory-copy trace of one fine schedule: 3 device-resident runs, then
+    3 runs that upload the inputs and weights and read the output back (page-locked memory)."""
+    import paper_2009_07482_amd as psc
+    spec, inp, desc = workload(a.config)
+    if not a.no_tune:
+        d0 = psc.build_dag(spec)
+        psc.psc_autotune_dag(d0, iters=20)
+        psc.psc_dag_destroy(d0)
+    if a.fine_opts:
+        opts = dict(json.loads(a.fine_opts), copy_roots=True)
+    else:
+        d1 = psc.build_dag(spec)
+        bi, _ = psc.psc_autotune_schedule(d1, "fine", FINE_CANDIDATES, iters=5)
+        psc.psc_dag_destroy(d1)
+        opts = FINE_CANDIDATES[bi]
+    r = psc.SpecRunner(spec, "fine", **opts)
+    r.set_inputs(inp)
+    r.run()
+    res = {"resident_ms": [], "with_copies_ms": []}
+    for _ in range(3):
+        res["resident_ms"].append(r.run(with_inputs=False, with_outputs=False)["makespan_ms"])
+    for _ in range(3):
+        res["with_copies_ms"].append(r.run()["makespan_ms"])
+    r.close()
+    print(json.dumps({"config": a.config, "target": "timeline", "fine_opts": opts, "schedule": describe(opts),
+                      "source_digest": source_digest(), **res}), flush=True)
 
 
 def stored_traffic(kernel_key, tile):
@@ -577,8 +610,12 @@ def batch_cpu_baseline(lengths, d, h, L, inp, seconds):
                       f"scaled to the batch by FLOPs"}
 
 
-FINE_CANDIDATES = [dict(n_streams=s_, mapper=m_, host_threads=t_, dispatch=d_)
-                   for d_ in ("aql", "hip") for s_ in (2, 4, 8, 16) for m_ in ("component", "rr") for t_ in (1, 0)]
+# every schedule uploads a read-only weight matrix as one dense copy (copy_roots), not one
+# strided rectangle per attention head
+FINE_CANDIDATES = ([dict(n_streams=s_, mapper=m_, host_threads=t_, dispatch=d_, copy_roots=True)
+                    for d_ in ("aql", "hip") for s_ in (2, 4, 8, 16) for m_ in ("component", "rr") for t_ in (1, 0)]
+                   + [dict(n_streams=s_, mapper=m_, host_threads=1, dispatch="aql", out_of_order=True, copy_roots=True)
+                      for s_ in (1, 2, 4, 8) for m_ in ("component", "rr")])
 
 
 def measure_runner(r, steps, warmup, copies_runs=5):
@@ -602,7 +639,9 @@ def describe(opts):
     m = {"component": "clustering (one task component per head per stream)", "rr": "round robin per kernel",
          "eft": "EFT list scheduling"}[opts.get("mapper", "rr")]
     th = "one enqueue thread" if opts.get("host_threads") == 1 else "one enqueue thread per stream"
-    return f"fine: {opts['n_streams']} streams, {m}, {th}; {how}"
+    q = ("out-of-order queues (kernels of one queue run concurrently; every precedence a barrier-AND)"
+         if opts.get("out_of_order") else "in-order queues")
+    return f"fine: {opts['n_streams']} streams, {m}, {th}; {how}; {q}"
 
 
 def dag_bench(spec, inp, a, tune=True, with_device=True, label=""):
@@ -621,12 +660,14 @@ def dag_bench(spec, inp, a, tune=True, with_device=True, label=""):
     hip_idx = [i for i, c in enumerate(FINE_CANDIDATES) if c["dispatch"] == "hip"]
     hip_opts = FINE_CANDIDATES[min(hip_idx, key=lambda i: cms[i] if cms[i] > 0 else 1e30)]
     print(f"# {label} schedule autotuner: chose {fine_opts} ({cms[bi]:.3f} ms/run); " +
-          ", ".join(f"{c['dispatch']}/{c['n_streams']}/{c['mapper'][0]}/{'1t' if c['host_threads'] == 1 else 'mt'}={m:.3f}"
+          ", ".join(f"{c['dispatch']}{'-ooo' if c.get('out_of_order') else ''}/{c['n_streams']}/{c['mapper'][0]}/"
+                    f"{'1t' if c['host_threads'] == 1 else 'mt'}={m:.3f}"
                     for c, m in zip(FINE_CANDIDATES, cms)), file=sys.stderr, flush=True)
-    plan = {"coarse_hip": ("coarse", dict(dispatch="hip")), "coarse_aql": ("coarse", dict(dispatch="aql")),
+    plan = {"coarse_hip": ("coarse", dict(dispatch="hip", copy_roots=True)),
+            "coarse_aql": ("coarse", dict(dispatch="aql", copy_roots=True)),
             "fine": ("fine", fine_opts), "fine_hip": ("fine", hip_opts)}
     if with_device:
-        plan["device_executor"] = ("device", {})
+        plan["device_executor"] = ("device", dict(copy_roots=True))
     res, keep = {}, {}
     for name, (policy, kw) in plan.items():
         r = psc.SpecRunner(spec, policy, **kw)
@@ -678,6 +719,9 @@ def main():
         return
     if a.config == "costmodel":
         costmodel_main(a)
+        return
+    if a.kernel_profile == "timeline":
+        timeline_profile(a)
         return
     if a.kernel_profile:
         kernel_profile(a)

@@ -175,7 +175,28 @@ typedef struct psc_sched_opts {
                            flight: the next psc_run of the schedule, and psc_sched_destroy, first
                            wait for it to finish.  Outputs of a timed-out run are unspecified. */
   int32_t dispatch;     /* psc_dispatch (PSC_FINE and PSC_COARSE) */
-  int32_t reserved[3];
+  int32_t out_of_order; /* 0: every stream is an in-order queue (Def. 4): an op starts after the
+                           previous op of its stream has completed.
+                           1 (PSC_FINE with PSC_DISPATCH_AQL only): out-of-order queues, as in
+                           OpenCL's out-of-order execution mode -- a kernel may start while
+                           earlier kernels of its queue still run (AQL dispatch packets without
+                           the barrier bit), so one queue runs independent kernels concurrently
+                           without more hardware queues.  Every precedence, within a queue too,
+                           is then an explicit wait (a barrier-AND packet on the producer's
+                           completion signal); each queue's kernels are issued by DAG level
+                           (longest path from a root), earlier ops of the mapper's order first
+                           within a level, so a wait holds back only kernels of later levels.
+                           psc_sched_export lists every direct precedence of each op, and
+                           psc_sched_queue_order reports the mode: stream position then orders
+                           nothing.  Copies stay in order on their stream. */
+  int32_t copy_roots;   /* 0: one upload per isolated write, a window of a larger buffer copied
+                           as a strided rectangle (Sec. III: each isolated write its own command);
+                           1: isolated writes that are windows of a root buffer no kernel writes
+                           are uploaded together as one dense copy of the whole root, before the
+                           first kernel that reads any of them (e.g. one copy of a d x d weight
+                           matrix instead of one 128-byte-row rectangle per attention head).  The
+                           host then gives the root's array (psc_host_io names the root). */
+  int32_t reserved[1];
 } psc_sched_opts;
 
 /* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..
@@ -410,6 +431,10 @@ psc_status psc_sched_aql_check(const psc_sched *sched, int32_t *n_kernels, char 
  * (largest component id + 1).  Needs mark_components (or PSC_DEVICE).  PSC_ERR_STATE without
  * such a run; PSC_ERR_ARG if cap < *n (done_us may be NULL to query *n). */
 psc_status psc_sched_component_times(const psc_sched *sched, float *done_us, int32_t cap, int32_t *n);
+
+/* 1 if the schedule's queues are out of order (psc_sched_opts.out_of_order), else 0: in an
+ * exported out-of-order schedule the precedences are the waits alone. */
+psc_status psc_sched_queue_order(const psc_sched *sched, int32_t *out_of_order);
 
 /* [GPU after prepare] Device address of buffer `name` (a view's address is inside its root's
  * storage) and its leading dimension in elements.  PSC_ERR_STATE before psc_sched_prepare. */

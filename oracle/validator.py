@@ -11,7 +11,10 @@ An exported schedule is ``{"n_streams": S, "ops": [op, ...]}`` with each op a di
 "stream", "pos", "host_order", "waits": [op ids]}``: ``pos`` is the op's place in its in-order
 stream, ``waits`` its cross-stream precedences, ``host_order`` the order in which the host
 enqueues it.  The happens-before relation (HB) is the transitive closure of stream order and
-waits.
+waits.  A schedule may also say ``"in_order": False``: its queues run out of order (OpenCL's
+out-of-order execution mode, a relaxation of Def. 4's in-order queues), a command may start
+before earlier commands of its queue complete, and HB is the transitive closure of the waits
+alone.
 
 ``check_schedule`` is the polynomial checker: the schedule is valid iff
   1. its structure is well formed (positions, host order, waits refer to ops enqueued earlier,
@@ -92,8 +95,9 @@ def hb_closure(sched):
     prev = {}
     for s, lst in by_stream.items():
         lst.sort(key=lambda o: o["pos"])
-        for a, b in zip(lst, lst[1:]):
-            prev[b["id"]] = a["id"]
+        if sched.get("in_order", True):   # out-of-order queues: position orders nothing
+            for a, b in zip(lst, lst[1:]):
+                prev[b["id"]] = a["id"]
     anc = [0] * len(ops)
     for o in sorted(ops, key=lambda o: o["host_order"]):
         m = 0

@@ -32,7 +32,8 @@ PSC_OK = 0
 STATUS = {0: "PSC_OK", -1: "PSC_ERR_ARG", -2: "PSC_ERR_NAME", -3: "PSC_ERR_SHAPE", -4: "PSC_ERR_CYCLE",
           -5: "PSC_ERR_RACE", -6: "PSC_ERR_STATE", -7: "PSC_ERR_HIP", -8: "PSC_ERR_OOM",
           -9: "PSC_ERR_UNSUPPORTED", -10: "PSC_ERR_TIMEOUT", -11: "PSC_ERR_IO"}
-PSC_ERR_ARG, PSC_ERR_STATE, PSC_ERR_IO = -1, -6, -11
+(PSC_ERR_ARG, PSC_ERR_NAME, PSC_ERR_SHAPE, PSC_ERR_CYCLE, PSC_ERR_RACE, PSC_ERR_STATE, PSC_ERR_HIP, PSC_ERR_OOM,
+ PSC_ERR_UNSUPPORTED, PSC_ERR_TIMEOUT, PSC_ERR_IO) = range(-1, -12, -1)
 PSC_F32, PSC_BF16 = 0, 1
 DTYPES = {"f32": PSC_F32, "bf16": PSC_BF16}
 PSC_GEMM, PSC_TRANSPOSE, PSC_SOFTMAX, PSC_ADD = 0, 1, 2, 3
@@ -66,7 +67,7 @@ class psc_sched_opts(C.Structure):
                 ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
                 ("cost", C.c_void_p), ("host_threads", C.c_int32), ("mark_components", C.c_int32),
                 ("fault_inject_op", C.c_int32), ("timeout_ms", C.c_int32), ("dispatch", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("out_of_order", C.c_int32), ("copy_roots", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class psc_op(C.Structure):
@@ -135,6 +136,7 @@ _SIGS = {
     "psc_run": [_P, C.POINTER(psc_host_io), _I, C.POINTER(psc_run_stats)],
     "psc_sched_op_times": [_P, C.POINTER(psc_op_time), _I, C.POINTER(_I)],
     "psc_sched_device_ptr": [_P, _S, C.POINTER(_P), C.POINTER(_I64)],
+    "psc_sched_queue_order": [_P, C.POINTER(_I)],
     "psc_sched_read": [_P, C.c_char_p, C.c_void_p, C.c_size_t],
     "psc_kernel_time": [_P, _I, _I, C.POINTER(C.c_float)],
     "psc_sched_destroy": [_P],
@@ -336,7 +338,7 @@ def psc_dag_classify(dag, component):
 
 def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
               device=0, cost=None, host_threads=0, mark_components=False, fault_inject_op=0,
-              timeout_ms=0, dispatch="hip"):
+              timeout_ms=0, dispatch="hip", out_of_order=False, copy_roots=False):
     o = psc_sched_opts()
     o.n_streams = int(n_streams)
     o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
@@ -350,6 +352,8 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
     o.fault_inject_op = int(fault_inject_op)
     o.timeout_ms = int(timeout_ms)
     o.dispatch = DISPATCH[dispatch] if isinstance(dispatch, str) else int(dispatch)
+    o.out_of_order = int(bool(out_of_order))
+    o.copy_roots = int(bool(copy_roots))
     return o
 
 
@@ -737,7 +741,9 @@ def export_schedule(spec, sched):
     ops = psc_sched_export(sched)
     for o in ops:
         o["buffer"] = names[o["buffer"]] if o["buffer"] >= 0 else None
-    return {"n_streams": psc_sched_streams(sched), "ops": ops}
+    ooo = _I()
+    _check(_lib.psc_sched_queue_order(sched, C.byref(ooo)))
+    return {"n_streams": psc_sched_streams(sched), "ops": ops, "in_order": not ooo.value}
 
 
 def to_bf16_bits(arr):

@@ -265,8 +265,10 @@ void fill_kernarg(const AqlKernel &k, const Launch &L, unsigned char *seg) {
 constexpr uint16_t kScopeShiftA = HSA_PACKET_HEADER_SCACQUIRE_FENCE_SCOPE;
 constexpr uint16_t kScopeShiftR = HSA_PACKET_HEADER_SCRELEASE_FENCE_SCOPE;
 
-uint16_t header(hsa_packet_type_t type, hsa_fence_scope_t acq, hsa_fence_scope_t rel) {
-  return uint16_t(type << HSA_PACKET_HEADER_TYPE) | uint16_t(1 << HSA_PACKET_HEADER_BARRIER) |
+// barrier: the packet starts only after every earlier packet of its queue has completed (the
+// in-order queue); without it a dispatch may start while earlier ones still run
+uint16_t header(hsa_packet_type_t type, hsa_fence_scope_t acq, hsa_fence_scope_t rel, bool barrier = true) {
+  return uint16_t(type << HSA_PACKET_HEADER_TYPE) | uint16_t((barrier ? 1 : 0) << HSA_PACKET_HEADER_BARRIER) |
          uint16_t(acq << kScopeShiftA) | uint16_t(rel << kScopeShiftR);
 }
 
@@ -316,6 +318,9 @@ struct AqlSchedule::Impl {
   std::vector<uint64_t> mark_off;
   std::vector<Launch> marks;
   std::vector<char> acq_sys, rel_sys;      // per op: system-scope fences where kernels meet copies
+  bool ooo = false;                        // out-of-order queues (plan.out_of_order)
+  std::vector<hsa_signal_t> qend;          // out of order: per queue, completes after all its packets
+  std::vector<std::vector<char>> covered;  // out of order, per run: per queue, ops already awaited there
   const AqlKernel *clock_kern = nullptr;   // start and end clock marks
   Launch clock_launch[2];
   uint64_t clock_off[2] = {0, 0};
@@ -359,6 +364,8 @@ struct AqlSchedule::Impl {
     for (hsa_queue_t *q : queues)
       if (q) (void)hsa_queue_destroy(q);
     for (hsa_signal_t x : sig)
+      if (x.handle) (void)hsa_signal_destroy(x);
+    for (hsa_signal_t x : qend)
       if (x.handle) (void)hsa_signal_destroy(x);
     if (start_sig.handle) (void)hsa_signal_destroy(start_sig);
     if (end_sig.handle) (void)hsa_signal_destroy(end_sig);
@@ -409,18 +416,23 @@ struct AqlSchedule::Impl {
     uint64_t off;
     hsa_signal_t done;
     bool acq_sys, rel_sys;
+    bool barrier = true;  // wait for every earlier packet of the queue
   };
+  // Barrier-AND packets wait for their signals and hold back every later packet of the queue;
+  // in an in-order queue they also wait for every earlier packet, in an out-of-order one only
+  // when `all_before` asks for it (the queue's closing barrier).
   void emit(int32_t stream, std::vector<hsa_signal_t> &deps, hsa_signal_t done_if_no_kernel, const Kd *kd,
-            int nk) {
+            int nk, bool all_before = false) {
     int nb = int((deps.size() + 4) / 5);
     if (nk == 0 && nb == 0 && done_if_no_kernel.handle) nb = 1;  // a no-op that completes in order
     const int n = nb + nk;
     if (n == 0) return;
     std::vector<uint16_t> H(n), S(n, 0);
-    for (int i = 0; i < nb; ++i) H[i] = header(HSA_PACKET_TYPE_BARRIER_AND, HSA_FENCE_SCOPE_AGENT, HSA_FENCE_SCOPE_AGENT);
+    for (int i = 0; i < nb; ++i)
+      H[i] = header(HSA_PACKET_TYPE_BARRIER_AND, HSA_FENCE_SCOPE_AGENT, HSA_FENCE_SCOPE_AGENT, !ooo || all_before);
     for (int j = 0; j < nk; ++j) {
       H[nb + j] = header(HSA_PACKET_TYPE_KERNEL_DISPATCH, kd[j].acq_sys ? HSA_FENCE_SCOPE_SYSTEM : HSA_FENCE_SCOPE_AGENT,
-                         kd[j].rel_sys ? HSA_FENCE_SCOPE_SYSTEM : HSA_FENCE_SCOPE_AGENT);
+                         kd[j].rel_sys ? HSA_FENCE_SCOPE_SYSTEM : HSA_FENCE_SCOPE_AGENT, !ooo || kd[j].barrier);
       S[nb + j] = uint16_t(3 << HSA_KERNEL_DISPATCH_PACKET_SETUP_DIMENSIONS);
     }
     write(stream, n, H.data(), S.data(), [&](int i, hsa_kernel_dispatch_packet_t *pkt) {
@@ -460,6 +472,7 @@ AqlSchedule::AqlSchedule(int device, const SchedPlan &plan, const std::vector<La
   I.device = device;
   I.plan = &plan;
   I.record = record;
+  I.ooo = plan.out_of_order;
   I.ag = &agent_for(device);
   Agent &ag = *I.ag;
   const size_t n = plan.ops.size();
@@ -470,7 +483,7 @@ AqlSchedule::AqlSchedule(int device, const SchedPlan &plan, const std::vector<La
   for (const Op &op : plan.ops)
     if (op.type == PSC_OP_KERNEL) has_kernel[op.stream] = 1;
   // packets per queue per run, an upper bound: start, per op its barriers, dispatch and mark, join
-  std::vector<uint64_t> need(T, 4);
+  std::vector<uint64_t> need(T, 6);
   need[0] += uint64_t(T) / 5 + 8;
   for (const Op &op : plan.ops) need[op.stream] += 3 + (op.waits.size() + 1 + 4) / 5;
   I.queues.assign(T, nullptr);
@@ -487,6 +500,11 @@ AqlSchedule::AqlSchedule(int device, const SchedPlan &plan, const std::vector<La
   I.sig.assign(n, hsa_signal_t{0});
   for (size_t o = 0; o < n; ++o) PSC_HSA(hsa_amd_signal_create(1, 0, nullptr, HSA_AMD_SIGNAL_AMD_GPU_ONLY, &I.sig[o]));
   PSC_HSA(hsa_amd_signal_create(1, 0, nullptr, HSA_AMD_SIGNAL_AMD_GPU_ONLY, &I.start_sig));
+  if (I.ooo) {
+    I.qend.assign(T, hsa_signal_t{0});
+    for (int32_t s = 0; s < T; ++s)
+      if (I.queues[s]) PSC_HSA(hsa_amd_signal_create(1, 0, nullptr, HSA_AMD_SIGNAL_AMD_GPU_ONLY, &I.qend[s]));
+  }
   PSC_HSA(hsa_signal_create(1, 0, nullptr, &I.end_sig));
   // kernel argument segments in one device block, written once
   I.kern.assign(n, nullptr);
@@ -604,6 +622,9 @@ void AqlSchedule::begin(const std::vector<AqlCopy> &copies) {
   }
   hsa_signal_store_relaxed(I.start_sig, 1);
   hsa_signal_store_relaxed(I.end_sig, 1);
+  for (hsa_signal_t x : I.qend)
+    if (x.handle) hsa_signal_store_relaxed(x, 1);
+  if (I.ooo) I.covered.assign(T, std::vector<char>(n, 0));
   I.clocks[0] = I.clocks[1] = 0;
   I.pending.assign(T, {});
   I.tail.assign(T, I.start_sig);
@@ -617,6 +638,11 @@ void AqlSchedule::begin(const std::vector<AqlCopy> &copies) {
                      I.cstart_kern ? hsa_signal_t{0} : I.start_sig, false, true},
                     {I.cstart_kern, &I.cstart_launch, I.cstart_off, I.start_sig, false, false}};
   I.emit(0, none, hsa_signal_t{0}, k0, I.cstart_kern ? 2 : 1);
+  if (I.ooo) {
+    // the marks do not hold back later dispatches of an out-of-order queue: wait for them
+    std::vector<hsa_signal_t> d{I.start_sig};
+    I.emit(0, d, hsa_signal_t{0}, nullptr, 0);
+  }
   I.tail_copy[0] = 0;
   for (int32_t s = 1; s < T; ++s)
     if (I.queues[s]) {
@@ -630,7 +656,14 @@ void AqlSchedule::wait(int32_t op, int32_t awaited) {
   Impl &I = *p_;
   const Op &a = I.plan->ops[awaited];
   if (a.type != PSC_OP_KERNEL && !I.copies[awaited].active) return;   // a skipped copy
-  I.pending[I.plan->ops[op].stream].push_back(I.sig[awaited]);
+  const int32_t s = I.plan->ops[op].stream;
+  if (I.ooo && I.plan->ops[op].type == PSC_OP_KERNEL) {
+    // a barrier-AND holds back every later packet of its queue, so an op awaited once there is
+    // complete for everything after it
+    if (I.covered[s][awaited]) return;
+    I.covered[s][awaited] = 1;
+  }
+  I.pending[s].push_back(I.sig[awaited]);
 }
 
 void AqlSchedule::exec(int32_t o) {
@@ -639,7 +672,7 @@ void AqlSchedule::exec(int32_t o) {
   const int32_t s = op.stream;
   std::vector<hsa_signal_t> &deps = I.pending[s];
   if (op.type == PSC_OP_KERNEL) {
-    if (I.tail_copy[s]) deps.push_back(I.tail[s]);
+    if (I.tail_copy[s] && !I.ooo) deps.push_back(I.tail[s]);
     // a component mark that follows the kernel carries the op's completion, so the end of the run
     // (which waits for every stream's last op) also waits for the mark
     Impl::Kd kd[2];
@@ -647,8 +680,10 @@ void AqlSchedule::exec(int32_t o) {
     const bool mark = I.mark_kern[o] != nullptr;
     if (I.kern[o])
       kd[nk++] = {I.kern[o], &I.launches[o], I.kernarg_off[o], mark ? hsa_signal_t{0} : I.sig[o], I.acq_sys[o] != 0,
-                  I.rel_sys[o] != 0};
-    if (mark) kd[nk++] = {I.mark_kern[o], &I.marks[o], I.mark_off[o], I.sig[o], false, I.rel_sys[o] != 0};
+                  I.rel_sys[o] != 0, false};
+    // a mark stamps the clock after its kernel: in an out-of-order queue it waits for every
+    // earlier packet (its kernel included)
+    if (mark) kd[nk++] = {I.mark_kern[o], &I.marks[o], I.mark_off[o], I.sig[o], false, I.rel_sys[o] != 0, true};
     I.emit(s, deps, I.sig[o], kd, nk);
     I.tail[s] = I.sig[o];
     I.tail_copy[s] = 0;
@@ -692,8 +727,21 @@ void AqlSchedule::end() {
   Impl &I = *p_;
   const int32_t T = I.plan->total_streams;
   std::vector<hsa_signal_t> deps;
-  for (int32_t s = 1; s < T; ++s)
-    if (I.tail[s].handle != I.start_sig.handle) deps.push_back(I.tail[s]);
+  if (I.ooo) {
+    // a queue's last packet says nothing about its earlier kernels: each queue ends with a
+    // barrier over all of its packets, and the end mark waits for those
+    for (int32_t s = 1; s < T; ++s)
+      if (I.queues[s]) {
+        std::vector<hsa_signal_t> none;
+        I.emit(s, none, I.qend[s], nullptr, 0, true);
+        deps.push_back(I.qend[s]);
+      } else if (I.tail[s].handle != I.start_sig.handle) {
+        deps.push_back(I.tail[s]);   // a copy stream: in order
+      }
+  } else {
+    for (int32_t s = 1; s < T; ++s)
+      if (I.tail[s].handle != I.start_sig.handle) deps.push_back(I.tail[s]);
+  }
   if (I.tail_copy[0] && I.tail[0].handle != I.start_sig.handle) deps.push_back(I.tail[0]);
   Impl::Kd k1{I.clock_kern, &I.clock_launch[1], I.clock_off[1], I.end_sig, true, true};
   I.emit(0, deps, hsa_signal_t{0}, &k1, 1);

@@ -348,6 +348,11 @@ std::unique_ptr<psc_sched> new_sched(psc_dag *dag, int32_t policy, const psc_sch
   need(o.fault_inject_op >= 0, PSC_ERR_ARG, "negative fault_inject_op");
   need(!(policy == PSC_DEVICE && o.fault_inject_op), PSC_ERR_ARG, "fault_inject_op does not apply to PSC_DEVICE");
   need(o.dispatch == PSC_DISPATCH_HIP || o.dispatch == PSC_DISPATCH_AQL, PSC_ERR_ARG, "unknown dispatch");
+  need(o.out_of_order == 0 || o.out_of_order == 1, PSC_ERR_ARG, "out_of_order must be 0 or 1");
+  need(o.copy_roots == 0 || o.copy_roots == 1, PSC_ERR_ARG, "copy_roots must be 0 or 1");
+  if (o.out_of_order)
+    need(policy == PSC_FINE && o.dispatch == PSC_DISPATCH_AQL, PSC_ERR_UNSUPPORTED,
+         "out-of-order queues need PSC_FINE with PSC_DISPATCH_AQL (HIP streams are in order)");
   if (o.dispatch == PSC_DISPATCH_AQL) {
     need(policy != PSC_DEVICE, PSC_ERR_ARG, "PSC_DEVICE runs one kernel; dispatch does not apply");
     need(!o.use_graph, PSC_ERR_ARG, "use_graph applies to PSC_DISPATCH_HIP only");
@@ -642,6 +647,13 @@ psc_status psc_cost_predict(psc_mlp *m, const float *x, int64_t n, float *us) {
     std::vector<double> d(n);
     cost->predict_us(x, n, d.data());
     for (int64_t i = 0; i < n; ++i) us[i] = float(d[i]);
+  });
+}
+
+psc_status psc_sched_queue_order(const psc_sched *sched, int32_t *out_of_order) {
+  return guard([&] {
+    need(sched && out_of_order, PSC_ERR_ARG, "NULL argument");
+    *out_of_order = sched->plan.out_of_order ? 1 : 0;
   });
 }
 

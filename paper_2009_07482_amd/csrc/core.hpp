@@ -103,6 +103,7 @@ struct SchedPlan {
   bool realized = false;       // a dynamic schedule has run at least once
   std::vector<double> dyn_us;    // per kernel: predicted microseconds (the cost model)
   std::vector<double> dyn_rank;  // per kernel: bottom-level rank on those predictions
+  bool out_of_order = false;   // queues run kernels out of order: precedences are the waits alone
   int32_t n_streams = 1;       // compute streams
   int32_t total_streams = 1;   // + upload and read-back streams (copy_stream)
   std::vector<Op> ops;         // index = op id; host order = id order
@@ -118,6 +119,8 @@ struct SchedPlan {
 //   [10]    1 if the first operand (or the copied buffer) is BF16, else 0
 //   [11]    other streams with an op in flight when this op starts
 constexpr int kFeatures = 12;
+// Per buffer, the buffer its isolated write is uploaded as (psc_sched_opts.copy_roots).
+std::vector<int32_t> upload_buffers(const Dag &g, bool copy_roots);
 void kernel_features(const Dag &g, int32_t kernel, int32_t in_flight, float *f);
 void copy_features(const Dag &g, int32_t buffer, bool h2d, int32_t in_flight, float *f);
 

@@ -710,6 +710,7 @@ void run_dynamic(psc_sched &s, const std::vector<CopyDesc> &cd, bool timed) {
   std::vector<int32_t> upload_of(g.bufs.size(), -1);
   for (int32_t k = 0; k < nk; ++k)
     for (int32_t o : ups[k]) upload_of[plan.ops[o].buffer] = o;
+  const std::vector<int32_t> upload_as = upload_buffers(g, s.opts.copy_roots != 0);
   std::vector<int32_t> up_stream(plan.ops.size(), -1);
   st.g = &g;
   st.plan = &plan;
@@ -769,7 +770,7 @@ void run_dynamic(psc_sched &s, const std::vector<CopyDesc> &cd, bool timed) {
         hipStream_t hs = d.streams[q];
         const int32_t kop = plan.kernel_op[k];
         for (int32_t b : g.iso_in[k]) {
-          const int32_t uo = upload_of[b];
+          const int32_t uo = upload_of[upload_as[b]];
           if (uo < 0) continue;
           if (up_stream[uo] < 0) {
             timed_op(uo, hs, [&] { do_copy(cd[uo], hs); });

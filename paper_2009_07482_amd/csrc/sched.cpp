@@ -150,12 +150,28 @@ void copy_features(const Dag &g, int32_t buffer, bool h2d, int32_t in_flight, fl
   f[11] = float(in_flight);
 }
 
+// The buffer an isolated write is uploaded as: itself, or (copy_roots) its root when no kernel
+// writes any part of that root, so one dense copy serves every window of it.
+std::vector<int32_t> upload_buffers(const Dag &g, bool copy_roots) {
+  std::vector<int32_t> as(g.bufs.size());
+  for (size_t b = 0; b < g.bufs.size(); ++b) as[b] = int32_t(b);
+  if (copy_roots) {
+    std::vector<char> written(g.bufs.size(), 0);
+    for (const Kernel &k : g.kers)
+      for (int32_t b : k.outs) written[g.bufs[b].root] = 1;
+    for (size_t b = 0; b < g.bufs.size(); ++b)
+      if (!written[g.bufs[b].root]) as[b] = g.bufs[b].root;
+  }
+  return as;
+}
+
 namespace {
 
 // PSC_DEVICE: every H2D first on queue 0, then each kernel on a queue of its own waiting for its
 // predecessor kernels and its inputs' H2D, then every D2H on queue 0 waiting for its producer.
-SchedPlan build_device_plan(const Dag &g) {
+SchedPlan build_device_plan(const Dag &g, bool copy_roots) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
+  const std::vector<int32_t> upload_as = upload_buffers(g, copy_roots);
   SchedPlan plan;
   plan.device = true;
   plan.n_streams = plan.total_streams = 1 + nk;
@@ -180,12 +196,12 @@ SchedPlan build_device_plan(const Dag &g) {
   };
   for (int32_t k : order)
     for (int32_t b : g.iso_in[k])
-      if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, 0, pos0++, {});
+      if (h2d_op[upload_as[b]] < 0) h2d_op[upload_as[b]] = emit(PSC_OP_H2D, -1, upload_as[b], 0, pos0++, {});
   plan.kernel_op.assign(nk, -1);
   for (int32_t k : order) {
     std::vector<int32_t> w;
     for (int32_t p : g.pred[k]) w.push_back(plan.kernel_op[p]);
-    for (int32_t b : g.iso_in[k]) w.push_back(h2d_op[b]);
+    for (int32_t b : g.iso_in[k]) w.push_back(h2d_op[upload_as[b]]);
     plan.kernel_op[k] = emit(PSC_OP_KERNEL, k, -1, 1 + k, 0, w);
   }
   for (int32_t k : order)
@@ -227,7 +243,7 @@ SchedPlan build_dynamic_plan(const Dag &g, int policy, const psc_sched_opts &o) 
 }
 
 SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
-  if (policy == PSC_DEVICE) return build_device_plan(g);
+  if (policy == PSC_DEVICE) return build_device_plan(g, o.copy_roots != 0);
   if (policy == PSC_EAGER || policy == PSC_HEFT) return build_dynamic_plan(g, policy, o);
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   SchedPlan plan;
@@ -258,6 +274,20 @@ SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
     fail(PSC_ERR_ARG, "unknown mapper");
   }
 
+  // out-of-order queues: kernels by DAG level (longest path from a root), the mapper's order
+  // within a level, so that a queue's wait for one kernel's producers holds back only kernels of
+  // later levels -- every kernel of a level can be in flight together
+  const bool ooo = policy == PSC_FINE && o.out_of_order;
+  plan.out_of_order = ooo;
+  if (ooo) {
+    std::vector<int32_t> level(nk, 0);
+    for (int32_t k : g.bfs_order())
+      for (int32_t q : g.succ[k]) level[q] = std::max(level[q], level[k] + 1);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return level[a] < level[b]; });
+  }
+
+  const std::vector<int32_t> upload_as = upload_buffers(g, o.copy_roots != 0);
+
   // emit ops with their dependencies (ids of earlier ops)
   std::vector<std::vector<int32_t>> deps;
   std::vector<int32_t> h2d_op(g.bufs.size(), -1);
@@ -279,23 +309,34 @@ SchedPlan build_plan(const Dag &g, int policy, const psc_sched_opts &o) {
   if (cs)
     for (int32_t k : order)
       for (int32_t b : g.iso_in[k])
-        if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, copy_s, {});
+        if (h2d_op[upload_as[b]] < 0) h2d_op[upload_as[b]] = emit(PSC_OP_H2D, -1, upload_as[b], copy_s, {});
   for (int32_t k : order) {
     const int32_t s = stream_of[k];
     if (!cs)
       for (int32_t b : g.iso_in[k])
-        if (h2d_op[b] < 0) h2d_op[b] = emit(PSC_OP_H2D, -1, b, s, {});
+        if (h2d_op[upload_as[b]] < 0) h2d_op[upload_as[b]] = emit(PSC_OP_H2D, -1, upload_as[b], s, {});
     std::vector<int32_t> d;
     for (int32_t p : g.pred[k]) d.push_back(plan.kernel_op[p]);
-    for (int32_t b : g.iso_in[k]) d.push_back(h2d_op[b]);
+    for (int32_t b : g.iso_in[k]) d.push_back(h2d_op[upload_as[b]]);
     const int32_t kop = emit(PSC_OP_KERNEL, k, -1, s, d);
     plan.kernel_op[k] = kop;
     for (int32_t b : g.iso_out[k]) emit(PSC_OP_D2H, -1, b, read_s >= 0 ? read_s : s, {kop});
   }
 
-  // waits: vector clocks over streams; vc[i][t] = last position on stream t known to precede op i
   const int32_t T = plan.total_streams;
   const size_t n = plan.ops.size();
+  if (ooo) {
+    // stream order implies nothing: every direct precedence is a wait
+    for (size_t i = 0; i < n; ++i) {
+      std::vector<int32_t> d = deps[i];
+      std::sort(d.begin(), d.end());
+      d.erase(std::unique(d.begin(), d.end()), d.end());
+      for (int32_t dep : d) plan.ops[dep].recorded = true;
+      plan.ops[i].waits = std::move(d);
+    }
+    return plan;
+  }
+  // waits: vector clocks over streams; vc[i][t] = last position on stream t known to precede op i
   std::vector<int32_t> vc(n * T, -1);
   std::vector<int32_t> last_on(T, -1);
   std::vector<int32_t> cur(T);

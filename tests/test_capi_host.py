@@ -101,7 +101,12 @@ def _schedules(spec, configs):
 
 CONFIGS = [("coarse", {}), ("device", {})] + [
     ("fine", dict(n_streams=s, mapper=m, copy_stream=c))
-    for s in (1, 2, 3, 4, 8) for m in ("rr", "eft", "component") for c in (False, True)]
+    for s in (1, 2, 3, 4, 8) for m in ("rr", "eft", "component") for c in (False, True)] + [
+    ("fine", dict(n_streams=s, mapper=m, copy_stream=c, dispatch="aql", out_of_order=True))
+    for s in (1, 2, 4) for m in ("rr", "eft", "component") for c in (False, True)] + [
+    ("coarse", dict(copy_roots=True)), ("device", dict(copy_roots=True)),
+    ("fine", dict(n_streams=4, mapper="component", copy_stream=True, copy_roots=True)),
+    ("fine", dict(n_streams=2, mapper="rr", dispatch="aql", out_of_order=True, copy_roots=True))]
 
 
 @pytest.mark.parametrize("name,spec", [
@@ -420,3 +425,85 @@ def test_dynamic_policies_validate_options_on_the_host():
                 psc.psc_schedule(d, pol, **kw)
             assert e.value.name == want, (pol, kw)
     psc.psc_dag_destroy(d)
+
+
+def test_out_of_order_queues_issue_kernels_by_level_with_every_wait():
+    """Out-of-order queues: each stream's kernels by DAG level, every direct precedence a wait
+    (same stream included), and the export marked out of order and valid under that reading."""
+    spec = workloads.mha_spec(64, 64, 4, layers=2)
+    dag = psc.build_dag(spec)
+    try:
+        sched = psc.psc_schedule(dag, "fine", n_streams=2, mapper="component", dispatch="aql", out_of_order=True)
+        exp = psc.export_schedule(spec, sched)
+        psc.psc_sched_destroy(sched)
+    finally:
+        psc.psc_dag_destroy(dag)
+    assert exp["in_order"] is False
+    ok, errs, _ = validator.check_schedule(spec, exp)
+    assert ok, errs[:5]
+    # levels: longest path from a root
+    n = len(spec["kernels"])
+    pred = [set() for _ in range(n)]
+    for (a, _, b, _) in spec["edges"]:
+        pred[b].add(a)
+    level = [None] * n
+    def lv(k):
+        if level[k] is None:
+            level[k] = 1 + max((lv(p) for p in pred[k]), default=-1)
+        return level[k]
+    kops = sorted((o for o in exp["ops"] if o["type"] == "kernel"), key=lambda o: (o["stream"], o["pos"]))
+    for a, b in zip(kops, kops[1:]):
+        if a["stream"] == b["stream"]:
+            assert lv(a["kernel"]) <= lv(b["kernel"])
+    # every DAG edge is a wait of the consumer's op
+    kop = {o["kernel"]: o["id"] for o in kops}
+    for (a, _, b, _) in spec["edges"]:
+        assert kop[a] in exp["ops"][kop[b]]["waits"]
+    # one stream: all 12 projections of layer 0 come first, before any transpose
+    dag = psc.build_dag(spec)
+    try:
+        sched = psc.psc_schedule(dag, "fine", n_streams=1, mapper="rr", dispatch="aql", out_of_order=True)
+        one = psc.export_schedule(spec, sched)
+        psc.psc_sched_destroy(sched)
+    finally:
+        psc.psc_dag_destroy(dag)
+    first = [spec["kernels"][o["kernel"]]["name"] for o in sorted(one["ops"], key=lambda o: o["pos"])
+             if o["type"] == "kernel"][:12]
+    assert all(nm.endswith(("_q", "_k", "_v")) for nm in first)
+    ok, errs, _ = validator.check_schedule(spec, one)
+    assert ok, errs[:5]
+
+
+def test_out_of_order_needs_fine_aql():
+    spec = workloads.forkjoin_spec(16)
+    dag = psc.build_dag(spec)
+    try:
+        for policy, kw in (("fine", dict(dispatch="hip")), ("coarse", dict(dispatch="aql")),
+                           ("device", {}), ("eager", dict(n_streams=2))):
+            with pytest.raises(psc.PscError) as e:
+                psc.psc_schedule(dag, policy, out_of_order=True, **kw)
+            assert e.value.status in (psc.PSC_ERR_UNSUPPORTED, psc.PSC_ERR_ARG)
+    finally:
+        psc.psc_dag_destroy(dag)
+
+
+def test_copy_roots_uploads_each_read_only_root_once():
+    """copy_roots: the per-head weight windows of an attention layer are uploaded as one dense
+    copy of each weight matrix (and X once), every reader of a window waiting for it."""
+    spec = workloads.mha_spec(64, 64, 4, layers=2)
+    for policy, kw in (("coarse", {}), ("fine", dict(n_streams=4, mapper="component", copy_stream=True)),
+                       ("eager", dict(n_streams=2))):
+        dag = psc.build_dag(spec)
+        try:
+            sched = psc.psc_schedule(dag, policy, copy_roots=True, **kw)
+            if policy == "eager":
+                psc.psc_sched_destroy(sched)
+                continue       # its structure is known after a run only
+            exp = psc.export_schedule(spec, sched)
+            psc.psc_sched_destroy(sched)
+        finally:
+            psc.psc_dag_destroy(dag)
+        ups = sorted(o["buffer"] for o in exp["ops"] if o["type"] == "h2d")
+        assert ups == sorted(["X"] + [f"{w}{l}" for l in range(2) for w in ("Wq", "Wk", "Wv", "Wo")]), ups
+        ok, errs, _ = validator.check_schedule(spec, exp)
+        assert ok, errs[:5]

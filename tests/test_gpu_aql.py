@@ -17,7 +17,11 @@ POLICIES = [("coarse", {}), ("fine", dict(n_streams=2, mapper="rr")), ("fine", d
             ("fine", dict(n_streams=4, mapper="eft")), ("fine", dict(n_streams=4, mapper="component")),
             ("fine", dict(n_streams=4, mapper="rr", copy_stream=True)),
             ("fine", dict(n_streams=4, mapper="component", host_threads=1)),
-            ("fine", dict(n_streams=8, mapper="rr", copy_stream=True, mark_components=True))]
+            ("fine", dict(n_streams=8, mapper="rr", copy_stream=True, mark_components=True)),
+            ("fine", dict(n_streams=1, mapper="rr", out_of_order=True)),
+            ("fine", dict(n_streams=2, mapper="eft", out_of_order=True)),
+            ("fine", dict(n_streams=4, mapper="component", copy_stream=True, out_of_order=True)),
+            ("fine", dict(n_streams=3, mapper="rr", mark_components=True, out_of_order=True))]
 IDS = ["-".join([p] + [f"{k}{int(v) if isinstance(v, bool) else v}" for k, v in kw.items()]) for p, kw in POLICIES]
 
 
@@ -43,7 +47,7 @@ def test_mha_matches_oracle_and_hip_dispatch(mha512, policy, kw):
     print(f"aql mha512 {policy} {kw}", flush=True)
     spec, inp, ref = mha512
     a, _ = psc.run_spec(spec, inp, policy, **kw, **AQL)
-    b, _ = psc.run_spec(spec, inp, policy, **kw)
+    b, _ = psc.run_spec(spec, inp, policy, **{k: v for k, v in kw.items() if k != "out_of_order"})
     assert normwise(a["Y0"], ref) < 1e-4
     np.testing.assert_array_equal(a["Y0"], b["Y0"])
 
@@ -178,3 +182,40 @@ def test_options_rejected_on_the_host():
     with pytest.raises(psc.PscError):
         psc.psc_schedule(d, "device", dispatch="aql")
     psc.psc_dag_destroy(d)
+
+
+@pytest.mark.parametrize("n_streams", [1, 4])
+def test_out_of_order_queue_timeline(n_streams):
+    """Out-of-order queues: per-op times (queue profiler) show every DAG edge and every copy
+    precedence respected; the export validates as out-of-order queues; the results equal the
+    in-order AQL schedule's bit for bit."""
+    spec = workloads.mha_spec(512, 512, 8, layers=3, gemm_dtype="bf16")
+    inp = workloads.mha_inputs(2, 512, 512, 3)
+    r = psc.SpecRunner(spec, "fine", n_streams=n_streams, mapper="component", record_ops=True,
+                       out_of_order=True, **AQL)
+    r.set_inputs(inp)
+    r.run()
+    r.run()
+    times = psc.psc_sched_op_times(r.sched)
+    exp = r.export()
+    got = r.result("Y2")
+    r.close()
+    assert exp["in_order"] is False
+    t = {o["id"]: (tt[2], tt[3]) for tt, o in zip(times, exp["ops"])}
+    for o in exp["ops"]:
+        for w in o["waits"]:
+            assert t[w][1] <= t[o["id"]][0] + 0.5, (w, o["id"])
+    same_queue_overlaps = 0
+    by_stream = {}
+    for o in exp["ops"]:
+        if o["type"] == "kernel":
+            by_stream.setdefault(o["stream"], []).append(t[o["id"]])
+    for iv in by_stream.values():
+        iv.sort()
+        same_queue_overlaps += sum(1 for a, b in zip(iv, iv[1:]) if b[0] < a[1])
+    print(f"out-of-order, {n_streams} queue(s): {same_queue_overlaps} overlapping kernel pairs within a queue",
+          flush=True)
+    ok, errs, _ = validator.check_schedule(spec, exp)
+    assert ok, errs
+    ref, _ = psc.run_spec(spec, inp, "fine", n_streams=n_streams, mapper="component", **AQL)
+    np.testing.assert_array_equal(got, ref["Y2"])

@@ -120,3 +120,56 @@ def test_coarse_single_stream_schedule_needs_no_waits():
     assert all(not o["waits"] for o in sched["ops"])
     ok, errs, _ = validator.check_schedule(spec, sched)
     assert ok, errs
+
+
+def _with_every_direct_wait(spec, sched):
+    """The same ops, each waiting for every op it reads from (same stream included)."""
+    out = copy.deepcopy(sched)
+    ops = out["ops"]
+    kop = {o["kernel"]: o["id"] for o in ops if o["type"] == "kernel"}
+    h2d = {o["buffer"]: o["id"] for o in ops if o["type"] == "h2d"}
+    writes, _ = validator.isolated_io(spec)
+    producer = {}
+    for (src, sb, _, _) in spec["edges"]:
+        producer[sb] = src
+    for k in spec["kernels"]:
+        for b in k["outputs"]:
+            producer.setdefault(b, spec["kernels"].index(k))
+    for o in ops:
+        if o["type"] == "kernel":
+            k = o["kernel"]
+            w = [kop[src] for (src, _, dst, _) in spec["edges"] if dst == k]
+            w += [h2d[validator._region(spec, b)[0]] for (ki, b) in writes if ki == k]
+        elif o["type"] == "d2h":
+            w = [kop[producer[o["buffer"]]]]
+        else:
+            w = []
+        o["waits"] = sorted(set(w))
+    return out
+
+
+@pytest.mark.parametrize("n_streams", [1, 2])
+def test_out_of_order_queues_need_every_precedence_as_a_wait(n_streams):
+    """Out-of-order queues (OpenCL's out-of-order execution mode): a queue position orders
+    nothing, so the in-order schedules that lean on stream order become invalid, and adding every
+    direct precedence as a wait makes them valid again; brute force agrees every time."""
+    spec = workloads.forkjoin_spec(4)
+    assigns = list(_all_assignments(4, n_streams))
+    if n_streams > 1:
+        assigns = [(0, 0, 1, 0), (0, 1, 0, 1), (1, 0, 1, 1)]   # a kernel on each side of every edge
+    for assign in assigns:
+        sched = naive_schedule(spec, list(assign), n_streams)
+        ooo = dict(copy.deepcopy(sched), in_order=False)
+        ok, _, bad = validator.check_schedule(spec, ooo)
+        assert not ok and bad == validator.brute_force(spec, ooo) != set()
+        full = dict(_with_every_direct_wait(spec, sched), in_order=False)
+        ok, errs, bad = validator.check_schedule(spec, full)
+        assert ok, errs
+        assert validator.brute_force(spec, full) == set()
+        # and then dropping any one wait breaks it
+        for o in full["ops"]:
+            for w in o["waits"]:
+                mut = copy.deepcopy(full)
+                mut["ops"][o["id"]]["waits"].remove(w)
+                ok2, _, bad2 = validator.check_schedule(spec, mut)
+                assert not ok2 and bad2 == validator.brute_force(spec, mut)
