@@ -599,7 +599,9 @@ psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32
  * 1..5 large-tile kernels (128x128, 64x64, 32x32, 128x64, 64x128), 6..12 K-split small-tile
  * kernels staging operands through LDS (64x64, 32x64, 64x32, 32x32, 16x32, 32x16, 16x16), 13..15
  * K-split 16-row kernels reading operands directly into matrix-core registers (16x16, 16x32,
- * 16x64).  A GEMM whose params leave tile at
+ * 16x64), 16 a 256x256 BF16 tile of eight wavefronts, 17..19 BF16 K-split kernels that load each
+ * wavefront's whole share of K at once (16x16, 16x32, 32x32; for FP32 operands they mean 12, 10
+ * and 9).  A GEMM whose params leave tile at
  * 0 takes the process-wide cache entry for its (M, N, K, operand dtype, output dtype) when there
  * is one, and a size heuristic otherwise; the choice is made when a schedule is prepared.  The
  * cache is thread safe.  (The paper leaves autotuning to future work, Sec. VII.)
@@ -648,6 +650,18 @@ psc_status psc_autotune_gemm(int32_t device, int32_t M, int32_t N, int32_t K, in
  * *n_tuned (may be NULL) receives the number of shapes tuned.  Schedules prepared afterwards
  * use the tuned tiles. */
 psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t *n_tuned);
+
+/* [GPU] Tile choice by the schedule itself: isolated kernel times do not predict a GEMM's time
+ * beside the concurrent kernels of a fine schedule (a tile that wins alone can lose in the DAG
+ * by holding more LDS and registers).  For every GEMM shape class of the DAG (operand and output
+ * dtype included; kernels with a fixed tile are left alone) this first runs psc_autotune_gemm,
+ * then, heaviest class first (isolated time x kernels), schedules the DAG with `policy` and
+ * `opts` once per candidate among the class's top_k isolated tiles -- the other classes at their
+ * current choice -- and times `iters` device-resident runs on seeded inputs; the tile with the
+ * lowest median makespan goes into the tile cache.  *n_changed (may be NULL) = classes whose
+ * choice differs from the isolated winner.  The DAG must be schedulable with these options. */
+psc_status psc_autotune_dag_in_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, int32_t top_k,
+                                        int32_t iters, int32_t *n_changed);
 
 /* [GPU] Schedule autotuner: builds a `policy` schedule of the DAG for each of the n candidate
  * option sets, runs each `iters` times on device-resident data (after 2 warm-up runs) and returns

@@ -174,6 +174,7 @@ _SIGS = {
     "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
     "psc_sched_aql_check": [_P, C.POINTER(_I), C.c_char_p, _I],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
+    "psc_autotune_dag_in_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I)],
     "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
                               C.POINTER(C.c_float)],
 }
@@ -687,6 +688,16 @@ def psc_autotune_gemm(M, N, K, ab="f32", c="f32", iters=50, device=0):
 def psc_autotune_dag(dag, iters=50, device=0):
     n = _I()
     _check(_lib.psc_autotune_dag(dag, int(device), int(iters), C.byref(n)))
+    return n.value
+
+
+def psc_autotune_dag_in_schedule(dag, policy, top_k=3, iters=5, **opts):
+    """Tiles chosen by the schedule's makespan; returns the number of shape classes whose choice
+    differs from the isolated winner."""
+    pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    o = make_opts(**opts)
+    n = _I()
+    _check(_lib.psc_autotune_dag_in_schedule(dag, pol, C.byref(o), int(top_k), int(iters), C.byref(n)))
     return n.value
 
 

@@ -29,6 +29,8 @@ void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t c
                   int32_t *work_off);
 void device_ptr(const psc_sched &s, const char *name, void **dptr, int64_t *ld);
 void sched_read(const psc_sched &s, const char *name, void *host, size_t bytes);
+void fill_inputs(psc_sched &s);
+void prepare(psc_sched &s);
 float kernel_time(psc_sched &s, int32_t kernel, int32_t iters);
 void *host_alloc(size_t bytes);
 void host_free(void *p);
@@ -827,6 +829,85 @@ psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t
       psc::autotune_gemm(device, M, N, K, ab, c, iters, nullptr, nullptr, 0);
     }
     if (n_tuned) *n_tuned = int32_t(seen.size());
+  });
+}
+
+psc_status psc_autotune_dag_in_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, int32_t top_k,
+                                        int32_t iters, int32_t *n_changed) {
+  return guard([&] {
+    need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
+    need(top_k >= 1 && iters >= 1, PSC_ERR_ARG, "top_k and iters must be >= 1");
+    const psc::Dag &g = dag->g;
+    const int device = opts ? opts->device : 0;
+    // GEMM classes and how many kernels of the DAG each has
+    std::map<std::tuple<int, int, int, int, int>, int> count;
+    for (const psc::Kernel &k : g.kers) {
+      if (k.kind != PSC_GEMM || k.tile > 0) continue;
+      const psc::Buffer &a = g.bufs[k.ins[0]], &b = g.bufs[k.ins[1]], &c = g.bufs[k.outs[0]];
+      if (a.rows == 0 || b.cols == 0) continue;
+      ++count[{int(a.rows), int(b.cols), int(a.cols), a.dtype, c.dtype}];
+    }
+    struct Cls {
+      std::tuple<int, int, int, int, int> key;
+      double weight;               // isolated best time x kernels of the class
+      std::vector<int> candidates; // tiles by isolated time, fastest first
+    };
+    std::vector<Cls> cls;
+    const int nt = psc::gemm_num_tiles();
+    for (const auto &kv : count) {
+      const auto &[M, N, K, ab, c] = kv.first;
+      std::vector<float> us(nt, 0.f);
+      float best_us = 0;
+      psc::autotune_gemm(device, M, N, K, ab, c, iters, &best_us, us.data(), nt);   // caches the fastest
+      std::vector<int> order;
+      for (int t = 1; t < nt; ++t)
+        if (us[t] > 0) order.push_back(t);
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return us[x] < us[y]; });
+      if (int(order.size()) > top_k) order.resize(top_k);
+      cls.push_back({kv.first, double(best_us) * kv.second, order});
+    }
+    std::stable_sort(cls.begin(), cls.end(), [](const Cls &x, const Cls &y) { return x.weight > y.weight; });
+    auto makespan = [&]() {
+      psc_sched *s = nullptr;
+      psc_status st = psc_schedule(dag, policy, opts, &s);
+      if (st != PSC_OK) psc::fail(st, psc_last_error());
+      std::vector<double> mk;
+      try {
+        psc::fill_inputs(*s);
+        psc_run_stats rs{};
+        psc::run(*s, nullptr, 0, &rs);
+        for (int32_t it = 0; it < iters; ++it) {
+          psc::run(*s, nullptr, 0, &rs);
+          mk.push_back(rs.makespan_ms);
+        }
+      } catch (...) {
+        psc_sched_destroy(s);
+        throw;
+      }
+      psc_sched_destroy(s);
+      std::nth_element(mk.begin(), mk.begin() + mk.size() / 2, mk.end());
+      return mk[mk.size() / 2];
+    };
+    int32_t changed = 0;
+    // coordinate descent, heaviest class first: each class's candidates timed in the schedule
+    // with every other class at its current choice
+    for (const Cls &c : cls) {
+      if (c.candidates.size() < 2) continue;
+      const auto &[M, N, K, ab, cd] = c.key;
+      int best_t = c.candidates[0];
+      double best_ms = -1;
+      for (int t : c.candidates) {
+        psc::tile_cache_set(M, N, K, ab, cd, t);
+        const double ms = makespan();
+        if (best_ms < 0 || ms < best_ms) {
+          best_ms = ms;
+          best_t = t;
+        }
+      }
+      psc::tile_cache_set(M, N, K, ab, cd, best_t);
+      changed += best_t != c.candidates[0];
+    }
+    if (n_changed) *n_changed = changed;
   });
 }
 

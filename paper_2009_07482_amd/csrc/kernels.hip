@@ -77,6 +77,12 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(GemmArgs p) {
   gemm_bf16_splitk_tile<TM, TN, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
+template <int TM, int TN, int D, bool VEC, bool OUT_BF16>
+__global__ __launch_bounds__(256) void gemm_bf16_deep_kernel(GemmArgs p) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_deep_smem<TM, TN, D>()];
+  gemm_bf16_deep_tile<TM, TN, D, VEC, OUT_BF16>(p, xcd_tile(blockIdx.x, gridDim.x), smem);
+}
+
 template <bool OUT_BF16>
 __global__ __launch_bounds__(512) void gemm_bf16_big_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_big_smem()];
@@ -148,14 +154,17 @@ struct TileCfg {
 };
 // 1..5: large tiles; 6..12: K split over the wavefronts, operands through LDS; 13..15: K split
 // over the wavefronts, operands read directly into matrix-core registers (16-row tiles);
-// 16: 256 x 256 BF16 tile, eight wavefronts, 512 threads (for FP32 operands it means tile 1).
+// 16: 256 x 256 BF16 tile, eight wavefronts, 512 threads (for FP32 operands it means tile 1);
+// 17..19: BF16 K split over the wavefronts with each wavefront's K share loaded at once (16 x 16
+// and 16 x 32 with four 64-deep chunks in flight, 32 x 32 with two); for FP32 operands they mean
+// the staged split-K tiles of the same shape (12, 10, 9).
 
 // GEMM tile configurations (index = psc_kernel_params.tile; 0 = automatic)
 constexpr TileCfg kTiles[] = {{0, 0, false},     {128, 128, false}, {64, 64, false},  {32, 32, false},
                               {128, 64, false},  {64, 128, false},  {64, 64, true},   {32, 64, true},
                               {64, 32, true},    {32, 32, true},    {16, 32, true},   {32, 16, true},
                               {16, 16, true},    {16, 16, true},    {16, 32, true},   {16, 64, true},
-                              {256, 256, false}};
+                              {256, 256, false}, {16, 16, true},    {16, 32, true},   {32, 32, true}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 #define PSC_VO(KERNEL, ...)                                                                     \
@@ -199,6 +208,9 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 14: return PSC_VO(gemm_bf16_direct_kernel, 2);
       case 15: return PSC_VO(gemm_bf16_direct_kernel, 4);
       case 16: return obf ? (const void *)&gemm_bf16_big_kernel<true> : (const void *)&gemm_bf16_big_kernel<false>;
+      case 17: return PSC_VO(gemm_bf16_deep_kernel, 16, 16, 4);
+      case 18: return PSC_VO(gemm_bf16_deep_kernel, 16, 32, 4);
+      case 19: return PSC_VO(gemm_bf16_deep_kernel, 32, 32, 2);
     }
   }
   return nullptr;
@@ -277,6 +289,7 @@ bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
   if (tile == 16 && ab_dtype == 0) tile = 1;  // the 256 x 256 tile exists for BF16 operands only
+  if (ab_dtype == 0 && tile >= 17 && tile <= 19) tile = tile == 17 ? 12 : tile == 18 ? 10 : 9;  // BF16 only
   if (tile == 16) {  // whole tiles, aligned operands only
     const bool fits = a.M % 256 == 0 && a.N % 256 == 0 && a.K % 64 == 0 && a.K > 0 && aligned16(a.A) &&
                       aligned16(a.B) && a.lda % 8 == 0 && a.ldb % 8 == 0;

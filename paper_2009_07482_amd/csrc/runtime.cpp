@@ -1169,6 +1169,28 @@ void sched_read(const psc_sched &s, const char *name, void *host, size_t bytes) 
                       size_t(b.rows), hipMemcpyDeviceToHost));
 }
 
+// Seeded values (uniform in [-1, 1)) in the device storage of every root buffer that holds an
+// isolated write, so that a schedule can be timed on realistic data without host inputs.
+void fill_inputs(psc_sched &s) {
+  if (!s.dev) prepare(s);
+  const Dag &g = s.dag->g;
+  Device &d = *s.dev;
+  PSC_HIP(hipSetDevice(d.device));
+  std::vector<char> done(g.bufs.size(), 0);
+  uint32_t seed = 11u;
+  for (int32_t b : g.h2d_bufs) {
+    const int32_t r = g.bufs[b].root;
+    if (done[r]) continue;
+    done[r] = 1;
+    const Buffer &rb = g.bufs[r];
+    Launch L;
+    make_fill(L, buffer_ptr(g, d, r), (rb.rows * rb.cols * elem_size(rb.dtype)) & ~int64_t(3), rb.dtype == PSC_BF16,
+              seed++);
+    if (!L.empty) launch(L, nullptr);
+  }
+  PSC_HIP(hipDeviceSynchronize());
+}
+
 // Autotuner: times every GEMM tile configuration on device buffers of the given shape (seeded
 // values uniform in [-1, 1)) with back-to-back launches between HIP events, records the fastest in the tile cache and
 // returns it.  us_per_tile[t] (t < cap) receives each configuration's mean time (0 for t = 0).

@@ -578,6 +578,144 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Latency-bound BF16 GEMM with K split over the block's four wavefronts, each wavefront's whole
+// share of K in flight at once.  Wavefront w owns the contiguous K chunks (64 deep) [w q, (w+1) q),
+// q = ceil(chunks / 4); it loads D of them into registers in one go -- for K up to 256 D one
+// memory round trip in all -- stages them in its own LDS region (A as rows, B as (k, k + 1) pairs
+// per column, as in the tile above), then multiplies them in order.  The four partial tiles are
+// summed through LDS in the order w = 0, 1, 2, 3.  Trip counts are uniform across wavefronts
+// (chunks past the end are zero-filled), so every __syncthreads is reached by all of them.
+// For the attention projections (1024 x 64 x 1024: few output tiles, a long K) the staged tile
+// above pays four memory round trips and eight barriers per block instead of one and two.
+// ---------------------------------------------------------------------------------------------
+template <int TM, int TN, int D>
+constexpr int gemm_bf16_deep_smem() {
+  return 4 * D * (TM + TN) * 72 * 2 > 4 * TM * TN * 4 ? 4 * D * (TM + TN) * 72 * 2 : 4 * TM * TN * 4;
+}
+
+template <int TM, int TN, int D, bool VEC, bool OUT_BF16>
+__device__ __forceinline__ void gemm_bf16_deep_tile(const GemmArgs &p, int bid, unsigned char *smem) {
+  constexpr int BK = 64, KP = BK + 8, FM = TM / 16, FN = TN / 16;
+  constexpr int UA = TM * (BK / 8) / 64;        // uint4 (8 x bf16) A loads per lane per chunk
+  constexpr int UB = (BK / 2) * (TN / 8) / 64;  // (k, k+1) x 8-column B units per lane per chunk
+  static_assert(UA >= 1 && UB >= 1, "tile too small for one load per lane");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint16_t *const region = reinterpret_cast<uint16_t *>(smem) + w * D * (TM + TN) * KP;
+  const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
+  const int m0 = tm * TM, n0 = tn * TN;
+  const uint16_t *A = static_cast<const uint16_t *>(p.A);
+  const uint16_t *B = static_cast<const uint16_t *>(p.B);
+  const int nchunks = (p.K + BK - 1) / BK;
+  const int q = (nchunks + 3) / 4;                // chunks per wavefront
+  const int c_begin = w * q, c_end = min(nchunks, c_begin + q);
+  const int rounds = (q + D - 1) / D;
+
+  uint4 ra[D][UA], rb0[D][UB], rb1[D][UB];
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int rd = 0; rd < rounds; ++rd) {
+    // every load of the round first
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int chunk = c_begin + rd * D + d;
+      const bool live = chunk < c_end;
+      const int k0 = chunk * BK;
+#pragma unroll
+      for (int j = 0; j < UA; ++j) {
+        const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
+        const int gr = m0 + r, gc = k0 + c;
+        if (VEC && live && gr < p.M && gc + 7 < p.K) {
+          ra[d][j] = *reinterpret_cast<const uint4 *>(A + int64_t(gr) * p.lda + gc);
+        } else {
+          uint16_t v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (live && gr < p.M && gc + e < p.K) ? A[int64_t(gr) * p.lda + gc + e] : 0;
+          memcpy(&ra[d][j], v, 16);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < UB; ++j) {
+        const int u = lane + 64 * j, kp = u / (TN / 8), c = (u % (TN / 8)) * 8;
+        const int gk = k0 + 2 * kp, gc = n0 + c;
+        if (VEC && live && gk + 1 < p.K && gc + 7 < p.N) {
+          rb0[d][j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk) * p.ldb + gc);
+          rb1[d][j] = *reinterpret_cast<const uint4 *>(B + int64_t(gk + 1) * p.ldb + gc);
+        } else {
+          uint16_t lo[8], hi[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            lo[e] = (live && gk < p.K && gc + e < p.N) ? B[int64_t(gk) * p.ldb + gc + e] : 0;
+            hi[e] = (live && gk + 1 < p.K && gc + e < p.N) ? B[int64_t(gk + 1) * p.ldb + gc + e] : 0;
+          }
+          memcpy(&rb0[d][j], lo, 16);
+          memcpy(&rb1[d][j], hi, 16);
+        }
+      }
+    }
+    __syncthreads();   // the previous round's products are done with the LDS regions
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      uint16_t *As = region + d * (TM + TN) * KP;
+      uint16_t *Bt = As + TM * KP;
+#pragma unroll
+      for (int j = 0; j < UA; ++j) {
+        const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
+        *reinterpret_cast<uint4 *>(&As[r * KP + c]) = ra[d][j];
+      }
+#pragma unroll
+      for (int j = 0; j < UB; ++j) {
+        const int u = lane + 64 * j, kp = u / (TN / 8), c = (u % (TN / 8)) * 8;
+        uint16_t lo[8], hi[8];
+        memcpy(lo, &rb0[d][j], 16);
+        memcpy(hi, &rb1[d][j], 16);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          *reinterpret_cast<uint32_t *>(&Bt[(c + e) * KP + 2 * kp]) = uint32_t(lo[e]) | (uint32_t(hi[e]) << 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const uint16_t *As = region + d * (TM + TN) * KP;
+      const uint16_t *Bt = As + TM * KP;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 32) {
+        const int kq = kk + 8 * (lane >> 4);
+        bf16x8 a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[(i * 16 + (lane & 15)) * KP + kq]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bt[(j * 16 + (lane & 15)) * KP + kq]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+  float *red = reinterpret_cast<float *>(smem);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[w * TM * TN + (i * 16 + (lane >> 4) * 4 + r) * TN + j * 16 + (lane & 15)] = acc[i][j][r];
+  __syncthreads();
+  for (int e = tid; e < TM * TN; e += 256) {
+    const int row = m0 + e / TN, col = n0 + e % TN;
+    const float v = ((red[e] + red[TM * TN + e]) + red[2 * TM * TN + e]) + red[3 * TM * TN + e];
+    if (row < p.M && col < p.N) store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * v);
+  }
+}
+
 // Eight consecutive bf16 at p[0..8), element e only if ok_e(e), packed into one uint4.
 template <typename F>
 __device__ __forceinline__ uint4 pack8_guarded(const uint16_t *p, F ok_e) {

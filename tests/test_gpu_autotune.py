@@ -59,3 +59,29 @@ def test_autotune_schedule_returns_the_fastest_candidate_and_keeps_parity():
     assert ms[best] == pytest.approx(min(ms))
     out, _ = psc.run_spec(spec, inp, "fine", **cands[best])
     assert normwise(out["Y0"], oracle_outputs(spec, inp)["Y0"]) < 1e-4
+
+
+@pytest.mark.parametrize("dispatch", ["hip", "aql"])
+def test_tiles_chosen_in_the_schedule_are_cached_and_keep_parity(dispatch):
+    """Tile choice by makespan: every GEMM class ends with a valid cached tile among its isolated
+    top three, prepared schedules use it, and the results still match the oracle."""
+    spec = workloads.mha_spec(512, 512, 8, gemm_dtype="bf16")
+    inp = workloads.mha_inputs(2, 512, 512)
+    dag = psc.build_dag(spec)
+    opts = dict(n_streams=4, mapper="component", dispatch=dispatch)
+    changed = psc.psc_autotune_dag_in_schedule(dag, "fine", top_k=3, iters=3, **opts)
+    assert 0 <= changed <= 3
+    by = {b["name"]: b for b in spec["buffers"]}
+    s = psc.psc_schedule(dag, "fine", **opts)
+    psc.psc_sched_prepare(s)
+    for ki, k in enumerate(spec["kernels"]):
+        if k["kind"] == "gemm":
+            a, b, c = by[k["inputs"][0]], by[k["inputs"][1]], by[k["outputs"][0]]
+            t = psc.psc_tile_cache_get(a["rows"], b["cols"], a["cols"], "bf16", c["dtype"])
+            assert 1 <= t < psc.psc_gemm_tile_count()
+            assert psc.psc_sched_kernel_tile(s, ki) == t
+    psc.psc_sched_destroy(s)
+    psc.psc_dag_destroy(dag)
+    out, _ = psc.run_spec(spec, inp, "fine", **opts)
+    assert normwise(out["Y0"], oracle_outputs(spec, inp)["Y0"]) < 2e-2
+    assert normwise(out["Y0"], oracle_outputs(spec, inp, emulate=True)["Y0"]) < 5e-3

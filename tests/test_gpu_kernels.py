@@ -41,7 +41,8 @@ def test_gemm_f32_ternary_exact(m, n, k, tile):
     np.testing.assert_array_equal(got, oracle_outputs(spec, inp)["C"])
 
 
-@pytest.mark.parametrize("m,n,k", GEMM_SHAPES + [(1024, 64, 1024), (1024, 1024, 64), (512, 256, 512), (256, 256, 192), (512, 512, 320)])
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES + [(1024, 64, 1024), (1024, 1024, 64), (512, 256, 512), (256, 256, 192),
+                                   (512, 512, 320), (80, 48, 2112)])
 @pytest.mark.parametrize("tile", list(range(psc.psc_gemm_tile_count())))
 @pytest.mark.parametrize("cdt", ["f32", "bf16"])
 def test_gemm_bf16(m, n, k, tile, cdt):
@@ -58,11 +59,12 @@ def test_gemm_bf16(m, n, k, tile, cdt):
     assert normwise(got, emul) < (5e-3 if cdt == "bf16" else 1e-5)
 
 
-def test_gemm_bf16_ternary_exact():
+@pytest.mark.parametrize("tile", [0, 12, 16, 17, 18, 19])
+def test_gemm_bf16_ternary_exact(tile):
     # integer products and sums below 2^8 in magnitude are exact in bf16 storage and fp32 sums
     g = np.random.default_rng(6)
     m, n, k = 96, 160, 200
-    spec = one_kernel_spec("gemm", [(m, k), (k, n), (m, n)], ["bf16", "bf16", "f32"])
+    spec = one_kernel_spec("gemm", [(m, k), (k, n), (m, n)], ["bf16", "bf16", "f32"], tile=tile)
     inp = {"A": g.integers(-1, 2, (m, k)).astype(np.float32), "B": g.integers(-1, 2, (k, n)).astype(np.float32)}
     np.testing.assert_array_equal(_run(spec, inp), oracle_outputs(spec, inp)["C"])
 
