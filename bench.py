@@ -110,6 +110,14 @@ def kernel_class(spec, k):
     return (f"{ker['kind']} {shape} {ins[0]['dtype']}->{out['dtype']}", float(nbytes), "hbm", None)
 
 
+def gemm_bytes(spec, k):
+    """Algorithmic bytes of a GEMM: A, B and C each moved once."""
+    by = {b["name"]: b for b in spec["buffers"]}
+    ker = spec["kernels"][k]
+    es = {"f32": 4, "bf16": 2}
+    return float(sum(b["rows"] * b["cols"] * es[b["dtype"]] for b in [by[n] for n in ker["inputs"] + ker["outputs"]]))
+
+
 def timed(runner, steps, warmup):
     import paper_2009_07482_amd as psc
     for _ in range(warmup):
@@ -183,13 +191,25 @@ def dominant_roofline(spec, r, kernel_iters):
     dom = kers[dom_key]
     avg_us = dom["avg_us"]
     achieved = dom["work"] / (avg_us * 1e-6)
-    if dom["bound"] == "mfma":
+    extra = {}
+    bound = dom["bound"]
+    if bound == "mfma":
+        # a GEMM whose arithmetic intensity is below the ridge (matrix-core peak / HBM bandwidth)
+        # is bound by memory on the roofline: reported in bytes, with the FLOP rate beside it
         peak = PEAK["mfma_bf16"] if dom["dtype"] == "bf16" else PEAK["mfma_f32"]
+        nbytes = gemm_bytes(spec, dom["ids"][0])
+        ai = dom["work"] / nbytes
+        extra = {"flop_per_byte": ai, "ridge_flop_per_byte": peak / PEAK["hbm"],
+                 "mfma_tflops": achieved / 1e12, "mfma_frac": achieved / peak}
+        if ai < peak / PEAK["hbm"]:
+            bound, achieved, dom = "hbm", nbytes / (avg_us * 1e-6), dict(dom, work=nbytes)
+    if bound == "mfma":
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
     else:
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                 "frac": achieved / PEAK["hbm"], "traffic": None}
+    roof.update(extra)
     roof.update({"kernel": dom_key, "avg_us": avg_us, "launches_per_step": len(dom["ids"]),
                  "work_per_launch": dom["work"], "tile": dom.get("tile"),
                  "timing": f"{kernel_iters} back-to-back launches, HIP events on its stream"})
@@ -200,12 +220,16 @@ def dominant_roofline(spec, r, kernel_iters):
 CAL_N = 4096   # calibration: an FP32 4096 x 4096 transpose reads and writes 64 MiB each
 
 
-def source_digest():
-    """Hash of the kernel sources; a stored counter profile applies only to the code it measured."""
+def source_digest(executor=False):
+    """Hash of the kernel sources; a stored counter profile applies only to the code it measured:
+    the standalone kernels' sources, and for the device executor also its own and the runtime that
+    plans its task lists."""
     import hashlib
     h = hashlib.sha256()
-    # the kernels, and the runtime that plans the device executor's task lists
-    for f in ("tiles.hpp", "kernels.hip", "persistent.hip", "persistent.hpp", "kernels.hpp", "runtime.cpp"):
+    files = ("tiles.hpp", "kernels.hip", "kernels.hpp")
+    if executor:
+        files += ("persistent.hip", "persistent.hpp", "runtime.cpp")
+    for f in files:
         with open(os.path.join(ROOT, "paper_2009_07482_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -221,7 +245,7 @@ def kernel_profile(a):
         d0 = psc.build_dag(spec)
         psc.psc_autotune_dag(d0, iters=20)
         psc.psc_dag_destroy(d0)
-    info = {"config": a.config, "target": a.kernel_profile, "source_digest": source_digest()}
+    info = {"config": a.config, "target": a.kernel_profile, "source_digest": source_digest(a.kernel_profile == "executor")}
     if a.profile_tile:
         # every counter pass must profile the same kernel instance: pin the tile of every GEMM
         # shape whose autotuned choice would otherwise vary from run to run
@@ -306,7 +330,7 @@ def stored_traffic(kernel_key, tile):
     or None if there is none for this kernel, tile and kernel source."""
     import glob
     import re
-    digest = source_digest()
+    digest = source_digest(kernel_key.startswith("exec_kernel"))
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         txt = open(f).read()
         kv = dict(re.findall(r"^- (\w+): `([^`]*)`", txt, re.M))
@@ -671,7 +695,10 @@ def dag_bench(spec, inp, a, tune=True, with_device=True, label=""):
                     for c, m in zip(FINE_CANDIDATES, cms)), file=sys.stderr, flush=True)
     plan = {"coarse_hip": ("coarse", dict(dispatch="hip", copy_roots=True)),
             "coarse_aql": ("coarse", dict(dispatch="aql", copy_roots=True)),
-            "fine": ("fine", fine_opts), "fine_hip": ("fine", hip_opts)}
+            "fine": ("fine", fine_opts), "fine_hip": ("fine", hip_opts),
+            # the same fine schedule with every upload on a copy stream of its own, issued ahead
+            # (its uploads overlap the first layers' kernels)
+            "fine_copy_stream": ("fine", dict(fine_opts, copy_stream=True))}
     if with_device:
         plan["device_executor"] = ("device", dict(copy_roots=True))
     res, keep = {}, {}
@@ -701,12 +728,20 @@ def kernel_timeline(spec, inp, opts):
     ops = psc.psc_sched_export(rec.sched)
     rec.close()
     kern = [t for t, o in zip(times, ops) if o["type"] == "kernel" and t[3] > t[2]]
-    by_class = {}
+    by_class, by_q = {}, {}
     for t, o in zip(times, ops):
         if o["type"] == "kernel" and t[3] > t[2]:
             key = kernel_class(spec, o["kernel"])[0]
             by_class.setdefault(key, []).append(t[3] - t[2])
-    return overlap(kern), {k: float(np.mean(v)) for k, v in by_class.items()}
+            by_q.setdefault(o["stream"], []).append((t[2], t[3]))
+    span = max(t[3] for t in kern) - min(t[2] for t in kern) if kern else 0.0
+    queues = {}
+    for q, iv in sorted(by_q.items()):
+        iv.sort()
+        gaps = [max(0.0, b[0] - a[1]) for a, b in zip(iv, iv[1:])]
+        queues[str(q)] = {"kernels": len(iv), "busy_frac": sum(b - a for a, b in iv) / span if span else 0.0,
+                          "gap_median_us": float(np.median(gaps)) if gaps else 0.0}
+    return overlap(kern), {k: float(np.mean(v)) for k, v in by_class.items()}, queues
 
 
 def main():
@@ -737,7 +772,7 @@ def main():
     fine = res["fine"]
     roof = dominant_roofline(spec, keep["fine"], a.kernel_iters)
     keep["fine"].close()
-    in_flight, in_dag_us = kernel_timeline(spec, inp, fine_opts)
+    in_flight, in_dag_us, queues = kernel_timeline(spec, inp, fine_opts)
     roof["in_dag_avg_us"] = in_dag_us.get(roof["kernel"])
     line = {
         "metric": "DAG makespan (ms) + inferences/s, fine vs coarse schedule, BF16 vs FP32",
@@ -756,6 +791,8 @@ def main():
             "hip": res["coarse_hip"]["ms_per_step"] / res["fine_hip"]["ms_per_step"],
             "aql": res["coarse_aql"]["ms_per_step"] / fine["ms_per_step"] if fine_opts["dispatch"] == "aql" else None},
         "fine_kernels_in_flight_mean": in_flight,
+        "fine_queues": queues,
+        "fine_in_dag_kernel_us": in_dag_us,
         "dag_bound_us": dag_bound_us(spec),
         "makespan_over_dag_bound": fine["makespan_ms_median"] * 1e3 / dag_bound_us(spec),
         "roofline": roof,

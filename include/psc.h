@@ -101,9 +101,11 @@ typedef enum psc_policy {
 /* Stream choice of the fine policy.
  *  PSC_MAP_RR         round robin per kernel in breadth-first order from the DAG's roots
  *                     (sel_rr of Sec. IV-B, Algorithm 1) -- the plain heuristic.
- *  PSC_MAP_EFT        list scheduling: kernels by descending bottom-level rank (Sec. V,
- *                     clustering), each on the stream with the earliest predicted finish time
- *                     (the EFT rule of HEFT) under the cost model given in the options.
+ *  PSC_MAP_EFT        list scheduling under the cost model given in the options: kernels by
+ *                     descending bottom-level rank (Sec. V, clustering) on predicted durations,
+ *                     each on the stream where it can start first (ties: the earliest predicted
+ *                     finish with the streams then busy, as HEFT's EFT rule; then the lower
+ *                     stream); the stream stays busy for that predicted, contended duration.
  *  PSC_MAP_COMPONENT  every kernel of task component c on stream c mod n_streams. */
 typedef enum psc_mapper { PSC_MAP_RR = 0, PSC_MAP_EFT = 1, PSC_MAP_COMPONENT = 2 } psc_mapper;
 

@@ -49,8 +49,9 @@ struct HeuristicCost final : CostModel {
   }
 };
 
-// EFT list scheduling: kernels by descending bottom-level rank (ties: lower id), each placed on
-// the stream where it is predicted to finish first.  A kernel's duration on a candidate stream is
+// List scheduling on the cost model: kernels by descending bottom-level rank (ties: lower id),
+// each placed on the stream where it can start first (ties: earliest predicted finish, then lower
+// stream).  A kernel's duration on a candidate stream is
 // the prediction for the number of other streams still busy at its start, so all predictions are
 // made up front: one batch of feature rows, kernels x (0 .. S-1 streams in flight) plus the
 // uploads of the isolated inputs.
@@ -100,14 +101,23 @@ void map_eft(const Dag &g, int32_t S, CostModel &cost, std::vector<int32_t> &ord
     double up = 0;
     for (int32_t b : g.iso_in[k])
       if (!uploaded[b]) up += up_us(b);
+    // the stream where the kernel can start first; among equal starts the earliest predicted
+    // finish under the contention at that start.  (Comparing contended finish times alone is
+    // myopic: a model that has learned how much a kernel stretches beside busy streams would
+    // make every kernel wait for a free stream -- serialise -- without counting what waiting
+    // costs the rest of the schedule.)  The chosen stream then stays busy for the contended time.
     int32_t best = 0;
-    double best_f = 1e300;
+    double best_st = 1e300, best_f = 1e300;
     for (int32_t s = 0; s < S; ++s) {
       const double st = std::max(avail[s] + up, dep_ready);
       int32_t busy = 0;
       for (int32_t q = 0; q < S; ++q) busy += q != s && avail[q] > st;
       const double f = st + w(k, busy);
-      if (f < best_f - 1e-9) { best_f = f; best = s; }
+      if (st < best_st - 1e-9 || (st < best_st + 1e-9 && f < best_f - 1e-9)) {
+        best_st = st;
+        best_f = f;
+        best = s;
+      }
     }
     for (int32_t b : g.iso_in[k]) uploaded[b] = 1;
     stream_of[k] = best;

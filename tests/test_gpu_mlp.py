@@ -174,33 +174,38 @@ def test_learned_model_beats_heuristic_on_held_out_dags():
             assert np.array_equal(got[k], want[k]), k
         # what the learned model changes in measured makespan: EFT under each model and round
         # robin on held-out random DAGs and on attention DAGs (many small kernels), device-resident,
-        # the three schedules' runs interleaved, median of 9 each
+        # median of 9 runs each.  The schedules run on AQL queues -- one hardware queue per stream:
+        # HIP streams share the runtime's four hardware queues round robin in creation order, so
+        # which of a schedule's streams end up on one queue (and run serially) would depend on what
+        # the process created before, not on the mapping under test
         dags = [workloads.random_dag_spec(sd, n_nodes=(40, 120), dim=(64, 1024)) for sd in range(1000, 1006)]
         dags += [workloads.mha_spec(512, 512, 8), workloads.mha_spec(512, 512, 8, gemm_dtype="bf16")]
         ratios_h, ratios_rr = [], []
         for spec in dags:
-            rs = [psc.SpecRunner(spec, "fine", n_streams=4, mapper="eft", cost=cm.handle),
-                  psc.SpecRunner(spec, "fine", n_streams=4, mapper="eft", cost=None),
-                  psc.SpecRunner(spec, "fine", n_streams=4, mapper="rr")]
-            try:
-                for r in rs:
+            med, exps = [], []
+            for kw in (dict(mapper="eft", cost=cm.handle), dict(mapper="eft", cost=None), dict(mapper="rr")):
+                r = psc.SpecRunner(spec, "fine", n_streams=4, dispatch="aql", host_threads=1, timeout_ms=30000, **kw)
+                try:
+                    exps.append(r.export())
                     r.run(with_inputs=False, with_outputs=False)
-                mk = [[], [], []]
-                for _ in range(9):
-                    for i, r in enumerate(rs):
-                        mk[i].append(r.run(with_inputs=False, with_outputs=False)["makespan_ms"])
-            finally:
-                for r in rs:
+                    med.append(float(np.median([r.run(with_inputs=False, with_outputs=False)["makespan_ms"]
+                                                for _ in range(9)])))
+                finally:
                     r.close()
-            med = [float(np.median(m)) for m in mk]
+            use = [np.bincount([o["stream"] for o in e["ops"] if o["type"] == "kernel"], minlength=4).tolist()
+                   for e in exps]
             ratios_h.append(med[0] / med[1])
             ratios_rr.append(med[0] / med[2])
             print(f"  {len(spec['kernels'])} kernels: eft-mlp {med[0]:.3f} ms, eft-heuristic {med[1]:.3f}, "
-                  f"rr {med[2]:.3f}", flush=True)
+                  f"rr {med[2]:.3f}; kernels per stream {use}", flush=True)
         gm_h = float(np.exp(np.mean(np.log(ratios_h))))
         gm_rr = float(np.exp(np.mean(np.log(ratios_rr))))
         print(f"makespan eft-mlp / eft-heuristic: geometric mean {gm_h:.3f} (min {min(ratios_h):.3f}, "
               f"max {max(ratios_h):.3f}); eft-mlp / rr {gm_rr:.3f}", flush=True)
+        # the learned model predicts op times better; whether it shortens these schedules is
+        # within run-to-run noise (the design notes give the measured ratios) -- what is asserted
+        # is that it makes them no worse
+        assert gm_h < 1.08 and gm_rr < 1.08, (ratios_h, ratios_rr)
     finally:
         cm.close()
 
