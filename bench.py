@@ -372,6 +372,43 @@ def one_kernel(kind, shapes, dtypes, tile=0, alpha=1.0):
     return {"buffers": bufs, "kernels": [ker], "edges": [], "component": [0]}
 
 
+_LIBREF = r"""
+import json, torch
+out = []
+for n in (4096, 8192):
+    g = torch.Generator(device="cuda").manual_seed(0)
+    a = (torch.rand((n, n), device="cuda", generator=g) * 2 - 1).to(torch.bfloat16)
+    b = (torch.rand((n, n), device="cuda", generator=g) * 2 - 1).to(torch.bfloat16)
+    for _ in range(5):
+        c = a @ b
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    it = 50 if n == 4096 else 20
+    e0.record()
+    for _ in range(it):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / it * 1e3
+    out.append({"kernel": f"torch.matmul {n}x{n}x{n} bf16->bf16 (vendor library)", "avg_us": us,
+                "achieved": 2 * n ** 3 / (us * 1e-6) / 1e12, "unit": "TFLOP/s", "peak": 2500.0,
+                "frac": 2 * n ** 3 / (us * 1e-6) / 2.5e15})
+print(json.dumps(out))
+"""
+
+
+def library_reference():
+    """The vendor GEMM library (torch.matmul on hipBLASLt) on the same large BF16 shapes, random
+    operands, in a child process (torch's HIP runtime cannot share this process): context for
+    what the matrix cores sustain on this part, not a product path."""
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, "-c", _LIBREF], capture_output=True, text=True, timeout=300)
+        return json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else {"error": r.stderr[-300:]}
+    except Exception as e:   # context only: report why it is missing
+        return {"error": str(e)}
+
+
 def kernels_main(a):
     """Standalone kernel rates at sizes large enough to reach the hardware's asymptotes: row
     softmax and transpose against HBM bandwidth (algorithmic bytes: input and output once), GEMMs
@@ -383,7 +420,9 @@ def kernels_main(a):
     # back-to-back launches cannot serve each other from it
     cases = [("softmax", (262144, 1024), "f32", "f32"), ("softmax", (131072, 2048), "f32", "bf16"),
              ("softmax", (262144, 2048), "bf16", "bf16"), ("transpose", (16384, 16384), "f32", "f32"),
-             ("transpose", (16384, 16384), "bf16", "bf16"), ("add", (16384, 16384), "f32", "f32"),
+             ("transpose", (16384, 16384), "bf16", "bf16"), ("transpose1", (16384, 16384), "f32", "f32"),
+             ("transpose1", (16384, 16384), "bf16", "bf16"), ("transpose3", (16384, 16384), "f32", "f32"),
+             ("transpose3", (16384, 16384), "bf16", "bf16"), ("add", (16384, 16384), "f32", "f32"),
              ("gemm", (4096, 4096, 4096), "bf16", "f32"), ("gemm", (8192, 8192, 8192), "bf16", "bf16"),
              ("gemm", (4096, 4096, 4096), "f32", "f32"), ("gemm", (1024, 64, 1024), "bf16", "bf16"),
              ("gemm", (512, 64, 512), "f32", "f32")]
@@ -413,8 +452,9 @@ def kernels_main(a):
             label = f"gemm {m}x{n}x{k} {idt}->{odt}"
         else:
             r_, c_ = shp
-            if kind == "transpose":
-                spec = one_kernel(kind, [(r_, c_), (c_, r_)], [idt, odt])
+            if kind.startswith("transpose"):
+                # transpose2 / transpose3: the 64 x 128 and 128 x 64 tiles
+                spec = one_kernel("transpose", [(r_, c_), (c_, r_)], [idt, odt], tile=int(kind[9:] or 0))
                 work = r_ * c_ * (es[idt] + es[odt])
             elif kind == "add":
                 spec = one_kernel(kind, [(r_, c_), (r_, c_), (r_, c_)], [idt, idt, odt])
@@ -424,6 +464,9 @@ def kernels_main(a):
                 work = r_ * c_ * (es[idt] + es[odt])
             unit, peak = "GB/s", PEAK["hbm"]
             label = f"{kind} {r_}x{c_} {idt}->{odt}"
+            if kind.startswith("transpose"):
+                label = f"transpose {r_}x{c_} {idt}->{odt} " + {"": "(automatic tile)", "1": "(64x64 tiles)",
+                                                                "2": "(64x128 tiles)", "3": "(128x64 tiles)"}[kind[9:]]
         r = psc.SpecRunner(spec, "coarse")
         # seeded operands (uniform in [-1, 1); softmax rows standard normal): matrix-core power, and
         # with it the clock, depends on the data, so zeros would overstate the rate
@@ -447,7 +490,8 @@ def kernels_main(a):
         r.close()
         out.append(row)
         print(f"# {json.dumps(row)}", file=sys.stderr, flush=True)
-    print(json.dumps({"metric": "standalone kernel rates vs roofline", "kernels": out}), flush=True)
+    print(json.dumps({"metric": "standalone kernel rates vs roofline", "kernels": out,
+                      "library_reference": library_reference()}), flush=True)
 
 
 def costmodel_main(a):
@@ -569,18 +613,29 @@ def batch_main(a):
         psc.psc_dag_destroy(d0)
         print(f"# tile autotuner: {tuned} GEMM shapes in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
-    cands = [dict(n_streams=s_, mapper="component", use_graph=g_) for s_ in (4, 8, 16) for g_ in (False, True)]
+    cands = ([dict(n_streams=s_, mapper="component", use_graph=g_, copy_roots=True) for s_ in (4, 8, 16)
+              for g_ in (False, True)]
+             + [dict(n_streams=s_, mapper="component", dispatch="aql", copy_roots=True) for s_ in (2, 4)])
     d1 = psc.build_dag(spec)
     bi, cms = psc.psc_autotune_schedule(d1, "fine", cands, iters=3)
     psc.psc_dag_destroy(d1)
     best = cands[bi]
     print("# schedule autotuner: " + ", ".join(
-        f"{c['n_streams']}{'g' if c['use_graph'] else 'e'}={m:.2f}" for c, m in zip(cands, cms)) + f" -> {best}",
-        file=sys.stderr, flush=True)
+        f"{c.get('dispatch', 'hip')}/{c['n_streams']}{'g' if c.get('use_graph') else 'e'}={m:.2f}"
+        for c, m in zip(cands, cms)) + f" -> {best}", file=sys.stderr, flush=True)
+    if not a.no_tune:
+        d2 = psc.build_dag(spec)
+        changed = psc.psc_autotune_dag_in_schedule(d2, "fine", top_k=3, iters=2, max_classes=4, **best)
+        psc.psc_dag_destroy(d2)
+        print(f"# tiles by makespan: {changed} shape class(es) changed", file=sys.stderr, flush=True)
     measure("coarse", "coarse")
     measure("tuned", "fine", keep_runner=True, **best)
-    other = dict(best, use_graph=not best["use_graph"])
-    measure("tuned_" + ("eager" if best["use_graph"] else "graph"), "fine", **other)
+    if best.get("dispatch") == "aql":
+        measure("tuned_hip_eager", "fine", n_streams=4, mapper="component", copy_roots=True)
+        measure("tuned_hip_graph", "fine", n_streams=4, mapper="component", use_graph=True, copy_roots=True)
+    else:
+        other = dict(best, use_graph=not best["use_graph"])
+        measure("tuned_" + ("eager" if best["use_graph"] else "graph"), "fine", **other)
     roof = dominant_roofline(spec, keep["tuned"], a.kernel_iters)
     keep["tuned"].close()
     chosen = "tuned"

@@ -74,9 +74,10 @@ typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_AD
  * writes just before and isolated reads just after it (the enq rules of Sec. III).
  * Fine: n_streams streams, kernels mapped by the mapper below, with event precedences.
  * Device: the precedences are enforced on the GPU at tile granularity: one persistent kernel
- * pulls the tiles of every kernel from a device work queue and releases a kernel's tiles when
- * all its predecessor kernels have completed; host copies run before (H2D) and after (D2H) it on
- * one stream.  Its exported structure puts each kernel on its own queue with a wait on every
+ * runs the tiles of every kernel from per-workgroup task lists that the host plans ahead of the
+ * run (list scheduling of tiles onto workgroups in one topological order), each workgroup waiting
+ * on the completion counters of a task's predecessor kernels; host copies run before (H2D) and
+ * after (D2H) it on one stream.  Its exported structure puts each kernel on its own queue with a wait on every
  * predecessor kernel and on the H2D copies of its inputs, which is what the device enforces.
  * Eager and HEFT: the dynamic coarse-grained baselines of Sec. V (Experiments 2 and 3, after
  * StarPU's policies), run through the scheduling loop of Algorithm 1 (schedule, select, cb):
@@ -137,7 +138,10 @@ typedef struct psc_kernel_params {
   float alpha;          /* GEMM scale; ignored by the other kinds.  Zero-initialised params
                            (or params == NULL) mean alpha = 1. */
   int32_t alpha_set;    /* nonzero: use alpha as given (so alpha = 0 is expressible) */
-  int32_t tile;         /* GEMM tile configuration index, -1 or 0 = automatic */
+  int32_t tile;         /* GEMM tile configuration index, -1 or 0 = automatic; for a transpose
+                           the tile of the input a block moves: 1 = 64 x 64, 2 = 64 x 128,
+                           3 = 128 x 64 (rows x columns; 2 and 3 need 16-byte aligned operands,
+                           else 1), 0 = automatic (2 for transposes of 256 MiB and more, else 1) */
   int32_t reserved;
 } psc_kernel_params;
 
@@ -657,13 +661,14 @@ psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t
  * beside the concurrent kernels of a fine schedule (a tile that wins alone can lose in the DAG
  * by holding more LDS and registers).  For every GEMM shape class of the DAG (operand and output
  * dtype included; kernels with a fixed tile are left alone) this first runs psc_autotune_gemm,
- * then, heaviest class first (isolated time x kernels), schedules the DAG with `policy` and
- * `opts` once per candidate among the class's top_k isolated tiles -- the other classes at their
- * current choice -- and times `iters` device-resident runs on seeded inputs; the tile with the
- * lowest median makespan goes into the tile cache.  *n_changed (may be NULL) = classes whose
- * choice differs from the isolated winner.  The DAG must be schedulable with these options. */
+ * then, for the max_classes heaviest classes (isolated time x kernels), heaviest first, schedules
+ * the DAG with `policy` and `opts` once per candidate among the class's top_k isolated tiles --
+ * the other classes at their current choice -- and times `iters` device-resident runs on seeded
+ * inputs; the tile with the lowest median makespan goes into the tile cache (lighter classes keep
+ * the isolated winner).  *n_changed (may be NULL) = classes whose choice differs from the
+ * isolated winner.  The DAG must be schedulable with these options. */
 psc_status psc_autotune_dag_in_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, int32_t top_k,
-                                        int32_t iters, int32_t *n_changed);
+                                        int32_t max_classes, int32_t iters, int32_t *n_changed);
 
 /* [GPU] Schedule autotuner: builds a `policy` schedule of the DAG for each of the n candidate
  * option sets, runs each `iters` times on device-resident data (after 2 warm-up runs) and returns

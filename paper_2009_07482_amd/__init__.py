@@ -174,7 +174,7 @@ _SIGS = {
     "psc_sched_component_times": [_P, C.c_void_p, _I, C.POINTER(_I)],
     "psc_sched_aql_check": [_P, C.POINTER(_I), C.c_char_p, _I],
     "psc_sched_samples": [_P, C.c_void_p, C.c_void_p, _I, C.POINTER(_I)],
-    "psc_autotune_dag_in_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I)],
+    "psc_autotune_dag_in_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, _I, C.POINTER(_I)],
     "psc_autotune_schedule": [_P, _I, C.POINTER(psc_sched_opts), _I, _I, C.POINTER(_I),
                               C.POINTER(C.c_float)],
 }
@@ -691,13 +691,14 @@ def psc_autotune_dag(dag, iters=50, device=0):
     return n.value
 
 
-def psc_autotune_dag_in_schedule(dag, policy, top_k=3, iters=5, **opts):
-    """Tiles chosen by the schedule's makespan; returns the number of shape classes whose choice
-    differs from the isolated winner."""
+def psc_autotune_dag_in_schedule(dag, policy, top_k=3, iters=5, max_classes=8, **opts):
+    """Tiles chosen by the schedule's makespan (the max_classes heaviest GEMM classes); returns the
+    number of shape classes whose choice differs from the isolated winner."""
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
     o = make_opts(**opts)
     n = _I()
-    _check(_lib.psc_autotune_dag_in_schedule(dag, pol, C.byref(o), int(top_k), int(iters), C.byref(n)))
+    _check(_lib.psc_autotune_dag_in_schedule(dag, pol, C.byref(o), int(top_k), int(max_classes), int(iters),
+                                             C.byref(n)))
     return n.value
 
 

@@ -833,10 +833,10 @@ psc_status psc_autotune_dag(psc_dag *dag, int32_t device, int32_t iters, int32_t
 }
 
 psc_status psc_autotune_dag_in_schedule(psc_dag *dag, int32_t policy, const psc_sched_opts *opts, int32_t top_k,
-                                        int32_t iters, int32_t *n_changed) {
+                                        int32_t max_classes, int32_t iters, int32_t *n_changed) {
   return guard([&] {
     need(dag != nullptr, PSC_ERR_ARG, "NULL dag");
-    need(top_k >= 1 && iters >= 1, PSC_ERR_ARG, "top_k and iters must be >= 1");
+    need(top_k >= 1 && iters >= 1 && max_classes >= 1, PSC_ERR_ARG, "top_k, max_classes and iters must be >= 1");
     const psc::Dag &g = dag->g;
     const int device = opts ? opts->device : 0;
     // GEMM classes and how many kernels of the DAG each has
@@ -867,6 +867,7 @@ psc_status psc_autotune_dag_in_schedule(psc_dag *dag, int32_t policy, const psc_
       cls.push_back({kv.first, double(best_us) * kv.second, order});
     }
     std::stable_sort(cls.begin(), cls.end(), [](const Cls &x, const Cls &y) { return x.weight > y.weight; });
+    if (int32_t(cls.size()) > max_classes) cls.resize(max_classes);   // the rest keep the isolated choice
     auto makespan = [&]() {
       psc_sched *s = nullptr;
       psc_status st = psc_schedule(dag, policy, opts, &s);

@@ -55,7 +55,7 @@ struct Launch {
 // dtype codes: 0 = f32, 1 = bf16
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile);
 bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype);
-bool make_transpose(Launch &L, TransArgs a, int dtype);
+bool make_transpose(Launch &L, TransArgs a, int dtype, int tile = 0);
 bool make_add(Launch &L, AddArgs a, int in_dtype, int out_dtype);
 int gemm_num_tiles();
 // One-thread kernel that stores the device wall clock (wall_clock64) to *slot.

@@ -179,7 +179,7 @@ void build_launch(const Dag &g, const Device &d, int32_t k, Launch &L) {
     case PSC_TRANSPOSE: {
       const Buffer &x = g.bufs[ker.ins[0]];
       TransArgs ta{P(ker.ins[0]), P(ker.outs[0]), LD(ker.ins[0]), LD(ker.outs[0]), int32_t(x.rows), int32_t(x.cols)};
-      ok = make_transpose(L, ta, x.dtype);
+      ok = make_transpose(L, ta, x.dtype, ker.tile);
       break;
     }
     case PSC_ADD: {

@@ -1268,6 +1268,65 @@ __device__ __forceinline__ void transpose_tile_vec(const TransArgs &p, int bid, 
   }
 }
 
+// Rectangular tiles for aligned operands: TR rows x TC columns of A per 256-thread block, so a
+// block reads TR runs of TC elements and writes TC runs of TR elements (64 x 128 doubles the
+// contiguous read runs of the 64 x 64 tile, 128 x 64 the write runs).  Tiles inside the matrix go
+// through 16-byte vectors, edge tiles element by element with checks.  Diagonal tile order as
+// above.
+template <int TR, int TC, typename T>
+constexpr int transpose_rc_smem() { return TR * (TC + 1) * int(sizeof(T)); }
+
+template <typename T, int TR, int TC, bool NT>
+__device__ __forceinline__ void transpose_rc_tile(const TransArgs &p, int bid, unsigned char *smem) {
+  constexpr int V = 16 / int(sizeof(T));
+  constexpr int VPR = TC / V, NV = TR * VPR / 256;    // read vectors per A row, per thread
+  constexpr int VPB = TR / V, NVB = TC * VPB / 256;   // write vectors per B row, per thread
+  static_assert(NV >= 1 && NVB >= 1 && TR * VPR % 256 == 0 && TC * VPB % 256 == 0, "tile shape");
+  T(*tile)[TC + 1] = reinterpret_cast<T(*)[TC + 1]>(smem);
+  const int tiles_c = (p.C + TC - 1) / TC, tiles_r = (p.R + TR - 1) / TR;
+  const int tc = bid % tiles_c, tr = (bid / tiles_c + tc) % tiles_r;
+  const int r0 = tr * TR, c0 = tc * TC;
+  const T *A = static_cast<const T *>(p.A);
+  T *B = static_cast<T *>(p.B);
+  if (r0 + TR <= p.R && c0 + TC <= p.C) {
+    u32x4 v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {   // every read of the tile in flight at once
+      const int idx = threadIdx.x + 256 * i, r = idx / VPR, cv = idx % VPR;
+      v[i] = load16<NT>(A + int64_t(r0 + r) * p.lda + c0 + cv * V);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int idx = threadIdx.x + 256 * i, r = idx / VPR, cv = idx % VPR;
+      T e[V];
+      memcpy(e, &v[i], 16);
+#pragma unroll
+      for (int j = 0; j < V; ++j) tile[r][cv * V + j] = e[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) {
+      const int idx = threadIdx.x + 256 * i, orow = idx / VPB, ov = idx % VPB;
+      T e[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) e[j] = tile[ov * V + j][orow];
+      u32x4 w;
+      memcpy(&w, e, 16);
+      store16<NT>(B + int64_t(c0 + orow) * p.ldb + r0 + ov * V, w);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < TR * TC; idx += 256) {
+      const int r = idx / TC, c = idx % TC;
+      tile[r][c] = (r0 + r < p.R && c0 + c < p.C) ? A[int64_t(r0 + r) * p.lda + c0 + c] : T(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TC * TR; idx += 256) {
+      const int orow = idx / TR, ocol = idx % TR;
+      if (c0 + orow < p.C && r0 + ocol < p.R) B[int64_t(c0 + orow) * p.ldb + r0 + ocol] = tile[ocol][orow];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Element-wise add in FP32: grid (ceil(C/256), R), one element per thread.
 // ---------------------------------------------------------------------------------------------

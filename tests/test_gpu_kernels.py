@@ -70,10 +70,11 @@ def test_gemm_bf16_ternary_exact(tile):
 
 
 @pytest.mark.parametrize("r,c", [(1, 1), (64, 64), (512, 64), (64, 512), (130, 257), (1024, 64), (0, 5),
-                                 (136, 264), (72, 200), (8, 4104)])
+                                 (136, 264), (72, 200), (8, 4104), (256, 384), (200, 136)])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-def test_transpose_exact(r, c, dt):
-    spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_transpose_exact(r, c, dt, tile):
+    spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt], tile=tile)
     a = uniform(7, (r, c))
     got = _run(spec, {"A": a})
     want = round_bf16(a.T) if dt == "bf16" else a.T.astype(np.float64)
@@ -152,9 +153,10 @@ def test_add_and_transpose_on_column_windows(dt):
 
 # Outputs of 256 MiB and more take the streaming (non-temporal) variants; ragged edges on both axes.
 @pytest.mark.parametrize("dt,r,c", [("f32", 8200, 8216), ("bf16", 10000, 13432)])
-def test_transpose_large_streaming(dt, r, c):
-    print(f"transpose {r}x{c} {dt}", flush=True)
-    spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt])
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_transpose_large_streaming(dt, r, c, tile):
+    print(f"transpose {r}x{c} {dt} tile {tile}", flush=True)
+    spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt], tile=tile)
     a = uniform(14, (r, c))
     got = _run(spec, {"A": a})
     want = round_bf16(a.T) if dt == "bf16" else a.T.astype(np.float64)
