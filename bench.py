@@ -306,13 +306,14 @@ def timeline_profile(a):
         psc.psc_autotune_dag(d0, iters=20)
         psc.psc_dag_destroy(d0)
     if a.fine_opts:
-        opts = dict(json.loads(a.fine_opts), copy_roots=True)
+        opts = dict(json.loads(a.fine_opts), copy_roots=True)   # may name a "policy" (default fine)
     else:
         d1 = psc.build_dag(spec)
         bi, _ = psc.psc_autotune_schedule(d1, "fine", FINE_CANDIDATES, iters=5)
         psc.psc_dag_destroy(d1)
         opts = FINE_CANDIDATES[bi]
-    r = psc.SpecRunner(spec, "fine", **opts)
+    policy = opts.pop("policy", "fine")
+    r = psc.SpecRunner(spec, policy, **opts)
     r.set_inputs(inp)
     r.run()
     res = {"resident_ms": [], "with_copies_ms": []}
@@ -321,7 +322,8 @@ def timeline_profile(a):
     for _ in range(3):
         res["with_copies_ms"].append(r.run()["makespan_ms"])
     r.close()
-    print(json.dumps({"config": a.config, "target": "timeline", "fine_opts": opts, "schedule": describe(opts),
+    print(json.dumps({"config": a.config, "target": "timeline", "policy": policy, "fine_opts": opts,
+                      "schedule": describe(opts) if policy == "fine" else policy,
                       "source_digest": source_digest(), **res}), flush=True)
 
 
@@ -799,6 +801,46 @@ def kernel_timeline(spec, inp, opts):
     return overlap(kern), {k: float(np.mean(v)) for k, v in by_class.items()}, queues
 
 
+def dynamic_rows(spec, inp, a, static_opts):
+    """The paper's dynamic coarse-grained baselines (eager, HEFT: one kernel per task component,
+    host callbacks on completion, Sec. V) beside the static fine-grained schedule: makespan and
+    the median gap between consecutive kernels of one stream, which is where the callbacks show."""
+    import paper_2009_07482_amd as psc
+
+    def gaps(r):
+        times = psc.psc_sched_op_times(r.sched)
+        ops = r.export()["ops"]
+        by = {}
+        for t, o in zip(times, ops):
+            if o["type"] == "kernel" and t[3] > t[2]:
+                by.setdefault(o["stream"], []).append((t[2], t[3]))
+        g = []
+        for iv in by.values():
+            iv.sort()
+            g += [b[0] - a_[1] for a_, b in zip(iv, iv[1:])]
+        return float(np.median(g)) if g else 0.0
+
+    out = {}
+    for name, policy, kw in (("eager", "eager", dict(n_streams=4)), ("heft", "heft", dict(n_streams=4)),
+                             ("static_fine", "fine", dict(static_opts))):
+        kw = dict(kw, copy_roots=True)
+        r = psc.SpecRunner(spec, policy, **kw)
+        r.set_inputs(inp)
+        r.run()
+        steps = max(3, min(a.steps, 10))
+        mk = [r.run(with_inputs=False, with_outputs=False)["makespan_ms"] for _ in range(steps)]
+        r.close()
+        rec = psc.SpecRunner(spec, policy, record_ops=True, **kw)
+        rec.set_inputs(inp)
+        rec.run()
+        rec.run(with_inputs=False, with_outputs=False)
+        g = gaps(rec)
+        rec.close()
+        out[name] = {"makespan_ms": float(np.median(mk)), "median_gap_between_kernels_us": g}
+        print(f"# dynamic {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -845,6 +887,7 @@ def main():
         "fine_vs_coarse_speedup_same_dispatch": {
             "hip": res["coarse_hip"]["ms_per_step"] / res["fine_hip"]["ms_per_step"],
             "aql": res["coarse_aql"]["ms_per_step"] / fine["ms_per_step"] if fine_opts["dispatch"] == "aql" else None},
+        "dynamic_baselines": dynamic_rows(spec, inp, a, fine_opts),
         "fine_kernels_in_flight_mean": in_flight,
         "fine_queues": queues,
         "fine_in_dag_kernel_us": in_dag_us,
