@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--profile-tile", type=int, default=0,
                    help="with --kernel-profile: GEMM tile of the shape --profile-shape (0 = autotune)")
     p.add_argument("--profile-shape", default="512x64x512", help="MxNxK pinned by --profile-tile")
+    p.add_argument("--gemm-tile", type=int, default=0,
+                   help="--config kernels: run the large GEMMs (above 1e10 MNK) on this tile, untuned")
     a = p.parse_args()
     big = a.config in ("mha1024x12", "batch64")
     if a.steps is None:
@@ -429,21 +431,38 @@ def kernels_main(a):
              ("gemm", (4096, 4096, 4096), "f32", "f32"), ("gemm", (1024, 64, 1024), "bf16", "bf16"),
              ("gemm", (512, 64, 512), "f32", "f32")]
     out = []
+
+    def seeded_inputs(spec):
+        # seeded operands (uniform in [-1, 1); softmax rows standard normal): matrix-core power,
+        # and with it the clock, depends on the data, so zeros would overstate the rate
+        g = np.random.default_rng(0)
+        ins = {}
+        for b in spec["buffers"][:-1]:
+            shape = (b["rows"], b["cols"])
+            ins[b["name"]] = (g.standard_normal(shape, dtype=np.float32) if spec["kernels"][0]["kind"] == "softmax"
+                              else g.random(shape, dtype=np.float32) * 2 - 1)
+        return ins
+
     for kind, shp, idt, odt in cases:
         if kind == "gemm":
             m, n, k = shp
             tile = 0
-            if not a.no_tune and m * n * k <= 1e10:
+            if a.gemm_tile and m * n * k > 1e10:
+                tile = a.gemm_tile
+            elif not a.no_tune and m * n * k <= 1e10:
                 tile, _, _ = psc.psc_autotune_gemm(m, n, k, idt, odt, iters=20)
             elif not a.no_tune:
                 # large shapes: only the large-tile kernels are candidates (the K-split ones are
-                # for few output tiles and would take seconds each here)
+                # for few output tiles and would take seconds each here), each timed on the
+                # seeded operands of the measurement below
                 best = None
-                for t in (1, 2, 4, 5, 16):
+                ins = seeded_inputs(one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt]))
+                for t in (1, 2, 4, 5, 16, 20):
                     rr = psc.SpecRunner(one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt], tile=t), "coarse")
-                    psc.psc_sched_prepare(rr.sched)
-                    psc.psc_kernel_time(rr.sched, 0, 1)
-                    u = psc.psc_kernel_time(rr.sched, 0, 3)
+                    rr.set_inputs(ins)
+                    rr.run(with_inputs=True, with_outputs=False)
+                    psc.psc_kernel_time(rr.sched, 0, 2)
+                    u = psc.psc_kernel_time(rr.sched, 0, 5)
                     rr.close()
                     print(f"#   tile {t}: {u:.1f} us", file=sys.stderr, flush=True)
                     if best is None or u < best[1]:
@@ -470,14 +489,7 @@ def kernels_main(a):
                 label = f"transpose {r_}x{c_} {idt}->{odt} " + {"": "(automatic tile)", "1": "(64x64 tiles)",
                                                                 "2": "(64x128 tiles)", "3": "(128x64 tiles)"}[kind[9:]]
         r = psc.SpecRunner(spec, "coarse")
-        # seeded operands (uniform in [-1, 1); softmax rows standard normal): matrix-core power, and
-        # with it the clock, depends on the data, so zeros would overstate the rate
-        g = np.random.default_rng(0)
-        ins = {}
-        for b in spec["buffers"][:-1]:
-            shape = (b["rows"], b["cols"])
-            ins[b["name"]] = (g.standard_normal(shape, dtype=np.float32) if kind == "softmax"
-                              else g.random(shape, dtype=np.float32) * 2 - 1)
+        ins = seeded_inputs(spec)
         r.set_inputs(ins)
         del ins
         r.run(with_inputs=True, with_outputs=False)

@@ -607,7 +607,10 @@ psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32
  * K-split 16-row kernels reading operands directly into matrix-core registers (16x16, 16x32,
  * 16x64), 16 a 256x256 BF16 tile of eight wavefronts, 17..19 BF16 K-split kernels that load each
  * wavefront's whole share of K at once (16x16, 16x32, 32x32; for FP32 operands they mean 12, 10
- * and 9).  A GEMM whose params leave tile at
+ * and 9), 20 a 256x256 BF16 tile of four wavefronts with 128x128 each (32x32 matrix-core
+ * blocks).  Tiles 16 and 20 need M and N multiples of 256, K of 64, 16-byte aligned A and B and
+ * leading dimensions that are multiples of 8, else they run as tile 4; with FP32 operands they
+ * run as tile 1.  A GEMM whose params leave tile at
  * 0 takes the process-wide cache entry for its (M, N, K, operand dtype, output dtype) when there
  * is one, and a size heuristic otherwise; the choice is made when a schedule is prepared.  The
  * cache is thread safe.  (The paper leaves autotuning to future work, Sec. VII.)

@@ -859,6 +859,152 @@ __device__ __forceinline__ void gemm_bf16_big_tile(const GemmArgs &p, int bid, u
 }
 
 // ---------------------------------------------------------------------------------------------
+// Large BF16 GEMM tile with one wavefront per SIMD and direct global-to-LDS copies: 256 x 256
+// outputs per 256-thread block, K step 64, four wavefronts (2 x 2) each owning a 128 x 128
+// sub-tile of 4 x 4 blocks of v_mfma_f32_32x32x16_bf16 (256 accumulators per lane, held in the
+// accumulator registers).  Against the eight-wavefront tile above, a 128 x 128 sub-tile reads
+// (128 + 128) x 64 fragment elements per K step instead of (128 + 64) x 64 for half the outputs:
+// 128 KB of LDS fragment reads per K step per CU instead of 192 KB for the same products.
+// Operands go from global memory straight into LDS (global_load_lds_dwordx4: each lane names its
+// own 16-byte source, the 64 lanes of one instruction fill 1 KB of LDS in lane order), so a stage
+// in flight holds no registers and costs no LDS write instructions.  Two 64 KB stages; the copy
+// of step s + 1 is issued right after the barrier that opens step s, one barrier per step.
+// LDS layout of a stage, unpadded and XOR-swizzled in 16-byte units so that the fragment reads
+// of 16 lanes touch distinct banks:
+//   A (256 rows x 64 k, 128 B a row):  k unit c of row r is stored at unit c ^ ((r / 2) % 8)
+//   B (64 k rows x 256 n, 512 B a row): n unit c of row k is stored at unit c ^ (2 (k % 4))
+// Matrix-core layouts (32 x 32 output block, lane l of 64):
+//   A: row l % 32, k 8 (l / 32) + e;   B: column l % 32, k 8 (l / 32) + e   (e < 8)
+//   accumulator element r of lane l: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+// B's eight k per lane come from two transposing LDS reads per 16-lane group: group g covers
+// columns 16 (g % 2) .. + 15 and k 8 (g / 2) .. + 7; lane rl of the group reads k row
+// 8 (g / 2) + rl / 4 (and 4 rows below), columns 4 (rl % 4) .. + 3.
+// Requires M % 256 == 0, N % 256 == 0, K % 64 == 0, 16-byte aligned operands and leading
+// dimensions that are multiples of 8 (the launch factory checks).
+// ---------------------------------------------------------------------------------------------
+constexpr int gemm_bf16_w4_smem() { return 2 * 65536; }
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <bool OUT_BF16>
+__device__ __forceinline__ void gemm_bf16_w4_tile(const GemmArgs &p, int bid, unsigned char *smem) {
+  constexpr int BK = 64, FM = 4, FN = 4, STAGE = 65536, BOFF = 32768;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // four wavefronts
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
+  const int m0 = tm * 256, n0 = tn * 256;
+
+  // Copies.  A chunk q (rows 8q .. 8q + 7): lane l fills unit l % 8 of row 8q + l / 8 with k unit
+  // (l % 8) ^ ((4q + l / 16) % 8) = (l % 8) ^ (l / 16) ^ 4 (q % 2).  B chunk q (k rows 2q, 2q + 1):
+  // lane l fills unit l % 32 of row 2q + l / 32 with n unit (l % 32) ^ (2 (l / 32)) ^ 4 (q % 2).
+  // Wavefront w copies the A chunks and the B chunks 8w .. 8w + 7 of every stage.
+  const int a_unit = (lane & 7) ^ (lane >> 4), b_unit = (lane & 31) ^ (2 * (lane >> 5));
+  const int a_odd = 8 * ((a_unit ^ 4) - a_unit), b_odd = 8 * ((b_unit ^ 4) - b_unit);
+  const uint16_t *const a_src =
+      static_cast<const uint16_t *>(p.A) + int64_t(m0 + 64 * wave + (lane >> 3)) * p.lda + 8 * a_unit;
+  const uint16_t *const b_src =
+      static_cast<const uint16_t *>(p.B) + int64_t(16 * wave + (lane >> 5)) * p.ldb + n0 + 8 * b_unit;
+  const int64_t a_chunk = int64_t(8) * p.lda, b_chunk = int64_t(2) * p.ldb;
+  auto copy = [&](int k0, unsigned char *stage) {
+    const uint16_t *qa = a_src + k0;
+    const uint16_t *qb = b_src + int64_t(k0) * p.ldb;
+    unsigned char *da = stage + wave * 8192, *db = stage + BOFF + wave * 8192;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      __builtin_amdgcn_global_load_lds(qa + i * a_chunk + ((i & 1) ? a_odd : 0), (lds_void *)(da + i * 1024), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      __builtin_amdgcn_global_load_lds(qb + i * b_chunk + ((i & 1) ? b_odd : 0), (lds_void *)(db + i * 1024), 16, 0, 0);
+  };
+
+  // Fragment reads.  A: row wm 128 + 32 i + l % 32, k unit 2m + l / 32 for the slice kk = 16 m,
+  // stored at unit (2m) ^ v with v = (l / 32) ^ ((l % 32) / 2 % 8).  B: n unit
+  // wn 16 + 4 j + u with u = 2 (g % 2) + (rl % 4) / 2 in k row kk + 8 (g / 2) + rl / 4, stored at
+  // unit wn 16 + 4 (j ^ (x / 4)) + x % 4 with x = u ^ (2 ((rl / 4) % 4)).
+  const int v = (lane >> 5) ^ (((lane & 31) >> 1) & 7);
+  const int a_row = (wm * 128 + (lane & 31)) * 128;
+  const int g = lane >> 4, rl = lane & 15;
+  const int x = (2 * (g & 1) + ((rl & 3) >> 1)) ^ (2 * ((rl >> 2) & 3));
+  const int b_base = BOFF + (8 * (g >> 1) + (rl >> 2)) * 512 + 16 * (wn * 16 + (x & 3)) + 8 * (rl & 1);
+  const int b_even = b_base + 64 * (x >> 2), b_oddj = b_base + 64 * (1 - (x >> 2));  // j = 0 / j = 1
+
+  floatx16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  // One step: the fragment reads of slices 0 and 1, the products of slice 0 interleaved with the
+  // reads of slices 2 and 3, the copy of the next K step into the other stage, then the products
+  // of slices 1 to 3 while that copy is in flight.  The compiler cannot tell the two stages apart
+  // and waits for outstanding copies before any later LDS read; with no read after the copy inside
+  // a step, that wait falls on the barrier of the next step, where it is needed anyway.  The last
+  // step copies K step 0 again into the idle stage (no branch in the step, so the instruction
+  // groups below apply), and the loop's end waits for it.
+  auto step = [&](const unsigned char *stage, int k_next, unsigned char *next) {
+    bf16x8 a[BK / 16][FM], b[BK / 16][FN];
+#pragma unroll
+    for (int m = 0; m < BK / 16; ++m) {
+      const unsigned char *pa = stage + a_row + 16 * ((2 * m) ^ v);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[m][i] = *reinterpret_cast<const bf16x8 *>(pa + i * 4096);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const unsigned char *q = stage + ((j & 1) ? b_oddj : b_even) + (j >> 1) * 128 + m * 16 * 512;
+        const shortx4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) shortx4 *)(q));
+        const shortx4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) shortx4 *)(q + 4 * 512));
+        const short e[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        memcpy(&b[m][j], e, 16);
+      }
+    }
+    copy(k_next, next);
+#pragma unroll
+    for (int m = 0; m < BK / 16; ++m)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[m][i], b[m][j], acc[i][j], 0, 0, 0);
+    // instruction groups (masks: 0x100 LDS read, 0x008 matrix product, 0x020 global read)
+    __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 48, 0);
+  };
+
+  const int steps = p.K / BK;
+  copy(0, smem);
+  for (int s = 0; s < steps; ++s) {
+    // vmcnt(0): this wavefront's copies into the stage of step s have reached LDS; the barrier
+    // then covers every wavefront's, and the end of every wavefront's reads of step s - 1
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    step(smem + (s & 1) * STAGE, s + 1 < steps ? (s + 1) * BK : 0, smem + ((s + 1) & 1) * STAGE);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // the last step's copy
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * 128 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        store_elem<OUT_BF16>(p.C, int64_t(row) * p.ldc + col, p.alpha * acc[i][j][r]);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Skinny GEMM tile for few output tiles and a long K: a 16 x TN output tile (TN = 16 * FN), K cut
 // into four contiguous ranges, one per wavefront; no barrier inside the K loop.  Per k step each
 // lane reads one vector of its A row (E consecutive k: 4 FP32 or 8 BF16) straight into its

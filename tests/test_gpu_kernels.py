@@ -69,6 +69,23 @@ def test_gemm_bf16_ternary_exact(tile):
     np.testing.assert_array_equal(_run(spec, inp), oracle_outputs(spec, inp)["C"])
 
 
+@pytest.mark.parametrize("tile", [16, 20])
+@pytest.mark.parametrize("m,n,k", [(256, 256, 64), (512, 768, 448), (768, 512, 1024)])
+def test_gemm_bf16_whole_tile_exact(tile, m, n, k):
+    # the 256 x 256 tiles run only on whole tiles: check that the launch kept the tile, and that
+    # every element is exact (integer operands, sums below 2^8 in magnitude)
+    g = np.random.default_rng(8)
+    spec = one_kernel_spec("gemm", [(m, k), (k, n), (m, n)], ["bf16", "bf16", "f32"], tile=tile)
+    inp = {"A": g.integers(-1, 2, (m, k)).astype(np.float32), "B": g.integers(-1, 2, (k, n)).astype(np.float32)}
+    runner = psc.SpecRunner(spec, "coarse")
+    try:
+        psc.psc_sched_prepare(runner.sched)
+        assert psc.psc_sched_kernel_tile(runner.sched, 0) == tile
+    finally:
+        runner.close()
+    np.testing.assert_array_equal(_run(spec, inp), oracle_outputs(spec, inp)["C"])
+
+
 @pytest.mark.parametrize("r,c", [(1, 1), (64, 64), (512, 64), (64, 512), (130, 257), (1024, 64), (0, 5),
                                  (136, 264), (72, 200), (8, 4104), (256, 384), (200, 136)])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
