@@ -685,6 +685,17 @@ psc_status psc_autotune_schedule(psc_dag *dag, int32_t policy, const psc_sched_o
 /* [GPU after prepare] Tile configuration a prepared schedule uses for GEMM kernel `kernel`. */
 psc_status psc_sched_kernel_tile(const psc_sched *sched, int32_t kernel, int32_t *tile);
 
+/* [GPU after prepare] The device executor a prepared PSC_DEVICE schedule launches: its workgroup
+ * count, workgroups resident per CU, and the tile-function groups of the compiled instance it
+ * uses (bit i = group i; groups 0-5 FP32 GEMM tiles, 6-12 BF16 GEMM tiles, 13 softmax, transpose
+ * and add).  The library holds several instances of the executor, each with a subset of the tile
+ * functions: registers are the union of what an instance holds, so a smaller instance keeps more
+ * workgroups per CU; prepare takes, among the instances that cover every tile function the DAG
+ * needs, the one with the most resident workgroups.  Any pointer may be NULL.
+ * PSC_ERR_STATE if the schedule is not prepared or not a PSC_DEVICE schedule. */
+psc_status psc_sched_executor_info(const psc_sched *sched, int32_t *workers, int32_t *per_cu,
+                                   uint32_t *groups);
+
 /* Frees device storage, streams, events and graphs of the schedule.  NULL is ignored. */
 psc_status psc_sched_destroy(psc_sched *sched);
 

@@ -158,6 +158,7 @@ _SIGS = {
                           C.POINTER(C.c_float), _I],
     "psc_autotune_dag": [_P, _I, _I, C.POINTER(_I)],
     "psc_sched_kernel_tile": [_P, _I, C.POINTER(_I)],
+    "psc_sched_executor_info": [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_uint32)],
     "psc_mlp_create": [_I, C.POINTER(_P)],
     "psc_mlp_destroy": [_P],
     "psc_mlp_set_params": [_P, C.c_void_p, _I64],
@@ -717,6 +718,13 @@ def psc_sched_kernel_tile(sched, kernel):
     t = _I()
     _check(_lib.psc_sched_kernel_tile(sched, int(kernel), C.byref(t)))
     return t.value
+
+
+def psc_sched_executor_info(sched):
+    """(workers, workgroups per CU, tile-function group mask) of a prepared PSC_DEVICE schedule."""
+    w, p, g = _I(), _I(), C.c_uint32()
+    _check(_lib.psc_sched_executor_info(sched, C.byref(w), C.byref(p), C.byref(g)))
+    return w.value, p.value, g.value
 
 
 def psc_sched_destroy(sched):

@@ -40,6 +40,7 @@ void device_info(int device, char *name, int name_cap, char *arch, int arch_cap,
 int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, float *best_us, float *us_per_tile,
                   int cap);
 int sched_kernel_tile(const psc_sched &s, int32_t kernel);
+void sched_executor_info(const psc_sched &s, int32_t *workers, int32_t *per_cu, uint32_t *groups);
 void tile_cache_set(int M, int N, int K, int ab, int c, int tile);
 int tile_cache_get(int M, int N, int K, int ab, int c);
 void tile_cache_clear();
@@ -952,6 +953,13 @@ psc_status psc_sched_kernel_tile(const psc_sched *sched, int32_t kernel, int32_t
     need(kernel >= 0 && kernel < int32_t(sched->dag->g.kers.size()), PSC_ERR_ARG, "kernel id out of range");
     need(sched->dag->g.kers[kernel].kind == PSC_GEMM, PSC_ERR_ARG, "not a GEMM kernel");
     *tile = psc::sched_kernel_tile(*sched, kernel);
+  });
+}
+
+psc_status psc_sched_executor_info(const psc_sched *sched, int32_t *workers, int32_t *per_cu, uint32_t *groups) {
+  return guard([&] {
+    need(sched, PSC_ERR_ARG, "NULL argument");
+    psc::sched_executor_info(*sched, workers, per_cu, groups);
   });
 }
 

@@ -24,6 +24,8 @@
 
 #include "tiles.hpp"
 
+#include <utility>
+
 namespace psc {
 
 namespace {
@@ -67,78 +69,102 @@ __device__ __forceinline__ T uniform_load(const unsigned char *p) {
   return out;
 }
 
-__device__ __forceinline__ void run_task(const ExecNode *ndp, int tile, unsigned char *smem) {
-  const ExecNode &nd = *ndp;
-  switch (__builtin_amdgcn_readfirstlane(nd.variant)) {
-    case 110: gemm_f32_tile<64, 64, 16, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 111: gemm_f32_tile<64, 64, 16, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 114: gemm_f32_tile<32, 32, 32, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 115: gemm_f32_tile<32, 32, 32, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 138: gemm_f32_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 139: gemm_f32_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 142: gemm_f32_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 143: gemm_f32_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 148: gemm_f32_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 149: gemm_f32_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 150: gemm_f32_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 151: gemm_f32_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 152: gemm_direct_tile<1, false, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 153: gemm_direct_tile<1, false, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 154: gemm_direct_tile<1, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 155: gemm_direct_tile<1, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 158: gemm_direct_tile<2, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 159: gemm_direct_tile<2, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 162: gemm_direct_tile<4, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 163: gemm_direct_tile<4, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 210: gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 211: gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 214: gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 215: gemm_bf16_tile<32, 32, 64, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 238: gemm_bf16_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 239: gemm_bf16_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 242: gemm_bf16_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 243: gemm_bf16_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 248: gemm_bf16_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 249: gemm_bf16_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 250: gemm_bf16_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 252: gemm_direct_tile<1, true, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 253: gemm_direct_tile<1, true, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 254: gemm_direct_tile<1, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 255: gemm_direct_tile<1, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 258: gemm_direct_tile<2, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 259: gemm_direct_tile<2, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 262: gemm_direct_tile<4, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 263: gemm_direct_tile<4, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 251: gemm_bf16_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem); break;
-    case 300: softmax_task<0, false, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 301: softmax_task<0, false, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 302: softmax_task<0, false, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 303: softmax_task<0, false, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 312: softmax_task<1, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 313: softmax_task<1, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 314: softmax_task<1, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 315: softmax_task<1, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 320: softmax_task<2, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 321: softmax_task<2, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 322: softmax_task<2, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 323: softmax_task<2, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 328: softmax_task<4, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 329: softmax_task<4, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 330: softmax_task<4, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 331: softmax_task<4, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 336: softmax_task<8, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 337: softmax_task<8, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 338: softmax_task<8, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 339: softmax_task<8, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile); break;
-    case 400: transpose_tile<float>(uniform_load<TransArgs>(nd.args), tile, smem); break;
-    case 401: transpose_tile<uint16_t>(uniform_load<TransArgs>(nd.args), tile, smem); break;
-    case 410: add_task<false, false>(uniform_load<AddArgs>(nd.args), tile); break;
-    case 411: add_task<false, true>(uniform_load<AddArgs>(nd.args), tile); break;
-    case 412: add_task<true, false>(uniform_load<AddArgs>(nd.args), tile); break;
-    case 413: add_task<true, true>(uniform_load<AddArgs>(nd.args), tile); break;
-    default: break;  // 0: empty kernel, nothing to compute
-  }
+#define PSC_TASK(V, ...)                                \
+  case V:                                               \
+    if constexpr ((G & exec_variant_group(V)) != 0u) {  \
+      __VA_ARGS__;                                      \
+      return true;                                      \
+    }                                                   \
+    return false
+
+constexpr uint32_t kGAll = kGElem | 0x1FFFu, kGF32All = kGElem | 0x3Fu, kGBf16All = kGElem | 0x1FC0u;
+// Wavefronts per SIMD each instance is compiled for, the most its tile functions fit without
+// spilling registers to memory: the element-wise instance three (three workgroups' LDS fill a
+// CU), the aligned direct-load and attention instances two, the instances with every FP32, every
+// BF16 or every tile function one.
+constexpr int exec_waves(uint32_t g) {
+  return g == kGElem ? 3 : (g == kGAll || g == kGF32All || g == kGBf16All) ? 1 : 2;
 }
+
+// Runs one task; false if its variant's tile function is not compiled into this instance (the
+// host picks an instance that covers every variant of the DAG, so this is a safeguard).
+template <uint32_t G>
+__device__ __forceinline__ bool run_task(const ExecNode *ndp, int tile, unsigned char *smem) {
+  const ExecNode &nd = *ndp;
+  const int v = __builtin_amdgcn_readfirstlane(nd.variant);
+  switch (v) {
+    PSC_TASK(110, gemm_f32_tile<64, 64, 16, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(111, gemm_f32_tile<64, 64, 16, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(114, gemm_f32_tile<32, 32, 32, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(115, gemm_f32_tile<32, 32, 32, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(138, gemm_f32_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(139, gemm_f32_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(142, gemm_f32_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(143, gemm_f32_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(148, gemm_f32_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(149, gemm_f32_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(150, gemm_f32_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(151, gemm_f32_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(152, gemm_direct_tile<1, false, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(153, gemm_direct_tile<1, false, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(154, gemm_direct_tile<1, false, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(155, gemm_direct_tile<1, false, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(158, gemm_direct_tile<2, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(159, gemm_direct_tile<2, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(162, gemm_direct_tile<4, false, true, false, 8>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(163, gemm_direct_tile<4, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(210, gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(211, gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(214, gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(215, gemm_bf16_tile<32, 32, 64, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(238, gemm_bf16_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(239, gemm_bf16_splitk_tile<32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(242, gemm_bf16_splitk_tile<16, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(243, gemm_bf16_splitk_tile<16, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(248, gemm_bf16_splitk_tile<16, 16, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(249, gemm_bf16_splitk_tile<16, 16, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(250, gemm_bf16_splitk_tile<16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(252, gemm_direct_tile<1, true, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(253, gemm_direct_tile<1, true, false, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(254, gemm_direct_tile<1, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(255, gemm_direct_tile<1, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(258, gemm_direct_tile<2, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(259, gemm_direct_tile<2, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(262, gemm_direct_tile<4, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(263, gemm_direct_tile<4, true, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(251, gemm_bf16_splitk_tile<16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(300, softmax_task<0, false, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(301, softmax_task<0, false, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(302, softmax_task<0, false, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(303, softmax_task<0, false, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(312, softmax_task<1, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(313, softmax_task<1, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(314, softmax_task<1, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(315, softmax_task<1, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(320, softmax_task<2, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(321, softmax_task<2, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(322, softmax_task<2, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(323, softmax_task<2, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(328, softmax_task<4, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(329, softmax_task<4, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(330, softmax_task<4, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(331, softmax_task<4, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(336, softmax_task<8, true, false, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(337, softmax_task<8, true, false, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(338, softmax_task<8, true, true, false>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(339, softmax_task<8, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
+    PSC_TASK(400, transpose_tile<float>(uniform_load<TransArgs>(nd.args), tile, smem));
+    PSC_TASK(401, transpose_tile<uint16_t>(uniform_load<TransArgs>(nd.args), tile, smem));
+    PSC_TASK(410, add_task<false, false>(uniform_load<AddArgs>(nd.args), tile));
+    PSC_TASK(411, add_task<false, true>(uniform_load<AddArgs>(nd.args), tile));
+    PSC_TASK(412, add_task<true, false>(uniform_load<AddArgs>(nd.args), tile));
+    PSC_TASK(413, add_task<true, true>(uniform_load<AddArgs>(nd.args), tile));
+    default: break;
+  }
+  return v == 0;  // 0: empty kernel, nothing to compute
+}
+
+#undef PSC_TASK
 
 constexpr int kExecSmem = 49152;  // the largest tile function's LDS (FP32 K-split tiles)
 
@@ -179,7 +205,8 @@ __device__ __forceinline__ bool wait_preds(const ExecArgs &a, const ExecNode &nd
 // Every branch that encloses a barrier depends only on wavefront-uniform values: list bounds and
 // task entries are read with readfirstlane, and the wait's verdict is broadcast through LDS and
 // read the same way, so all 256 threads take the same path each iteration.
-__global__ __launch_bounds__(256) void exec_kernel(ExecArgs a) {
+template <uint32_t G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exec_waves(G)))) void exec_kernel(ExecArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kExecSmem];
   __shared__ uint32_t s_ok;
   const int32_t w = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x));
@@ -210,7 +237,13 @@ __global__ __launch_bounds__(256) void exec_kernel(ExecArgs a) {
     }
     if (threadIdx.x == 0)
       __hip_atomic_fetch_min(&a.t_first[t.node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    run_task(nd, t.tile, smem);
+    if (!run_task<G>(nd, t.tile, smem)) {  // uniform: the variant is read with readfirstlane
+      if (threadIdx.x == 0) {
+        __hip_atomic_fetch_or(&a.ctl[0], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.host_err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      break;
+    }
     if (t.signal > 0) {
       // One release for the workgroup: every wavefront waits until its stores have reached the
       // L2, the barrier orders that before thread 0's release fence (a write-back of the whole
@@ -229,6 +262,28 @@ __global__ __launch_bounds__(256) void exec_kernel(ExecArgs a) {
     }
   }
 }
+
+// The compiled instances, each the tile-function groups it holds.  A single kernel holding every
+// tile function needs the union of their registers (over 400 per lane with the matrix-core
+// accumulators, one workgroup per CU); an instance holding only what a DAG uses fits several
+// workgroups per CU.  The all-groups instance comes last and covers any DAG.
+constexpr uint32_t kInstances[] = {
+    kGElem,                                                    // element-wise kernels only
+    kGElem | (1u << 3) | (1u << 4) | (1u << 5),                 // FP32: aligned direct-load tiles
+    kGElem | (1u << 10) | (1u << 11) | (1u << 12),              // BF16: aligned direct-load tiles
+    kGElem | (1u << 0) | (1u << 3) | (1u << 4) | (1u << 5),     // FP32 attention: + 64 x 64 tile
+    kGElem | (1u << 6) | (1u << 10) | (1u << 11) | (1u << 12),  // BF16 attention: + 64 x 64 tile
+    kGF32All,                                                  // every FP32 tile function
+    kGBf16All,                                                 // every BF16 tile function
+    kGAll};                                                    // everything
+constexpr int kNumInstances = sizeof(kInstances) / sizeof(kInstances[0]);
+
+template <int... I>
+constexpr const void *instance_fn(int i, std::integer_sequence<int, I...>) {
+  const void *fns[] = {(const void *)&exec_kernel<kInstances[I]>...};
+  return fns[i];
+}
+const void *exec_fn(int i) { return instance_fn(i, std::make_integer_sequence<int, kNumInstances>{}); }
 
 struct PCfg {
   int cfg, bm, bn;
@@ -336,20 +391,26 @@ hipError_t launch_exec_reset(const ExecArgs &a, hipStream_t stream) {
   return hipLaunchKernel((const void *)&exec_reset_kernel, dim3((n + 255) / 256), dim3(256), args, 0, stream);
 }
 
-hipError_t launch_exec(const ExecArgs &a, hipStream_t stream) {
+hipError_t launch_exec(const ExecArgs &a, int instance, hipStream_t stream) {
+  if (instance < 0 || instance >= kNumInstances) return hipErrorInvalidValue;
   void *args[] = {const_cast<ExecArgs *>(&a)};
-  return hipLaunchKernel((const void *)&exec_kernel, dim3(a.n_workers > 0 ? a.n_workers : 1), dim3(256), args, 0,
-                         stream);
+  return hipLaunchKernel(exec_fn(instance), dim3(a.n_workers > 0 ? a.n_workers : 1), dim3(256), args, 0, stream);
 }
 
-int exec_max_workers(int device) {
+int exec_num_instances() { return kNumInstances; }
+
+uint32_t exec_instance_groups(int instance) {
+  return instance >= 0 && instance < kNumInstances ? kInstances[instance] : 0u;
+}
+
+int exec_max_workers(int device, int instance) {
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
     (void)hipGetLastError();
     cus = 256;
   }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)&exec_kernel, 256, 0) != hipSuccess ||
-      per_cu < 1) {
+  if (instance < 0 || instance >= kNumInstances ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, exec_fn(instance), 256, 0) != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
     per_cu = 1;
   }

@@ -55,10 +55,39 @@ struct ExecArgs {
 // (GEMM tiles are chosen to give at least that many tasks where possible).
 ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int out_dtype, int tile, int want);
 
+// Tile-function groups: the group bit of a node variant (0 for the empty variant 0).  Groups
+// 0-5: FP32 GEMM tiles (64x64 and 32x32 staged through LDS, split-K, direct-load with 1, 2 and 4
+// column blocks); 6-12: the BF16 ones (and a separate group for the unaligned direct-load
+// tile); 13: softmax, transpose and add.
+constexpr uint32_t kGElem = 1u << 13;
+__host__ __device__ constexpr uint32_t exec_variant_group(int v) {
+  return v == 110 || v == 111 ? 1u << 0
+       : v == 114 || v == 115 ? 1u << 1
+       : v >= 138 && v <= 151 ? 1u << 2
+       : v >= 152 && v <= 155 ? 1u << 3
+       : v == 158 || v == 159 ? 1u << 4
+       : v == 162 || v == 163 ? 1u << 5
+       : v == 210 || v == 211 ? 1u << 6
+       : v == 214 || v == 215 ? 1u << 7
+       : v >= 238 && v <= 251 ? 1u << 8
+       : v == 252 || v == 253 ? 1u << 9
+       : v == 254 || v == 255 ? 1u << 10
+       : v == 258 || v == 259 ? 1u << 11
+       : v == 262 || v == 263 ? 1u << 12
+       : v >= 300 && v <= 413 ? kGElem
+                              : 0u;
+}
+
+// Compiled executor instances (0 .. exec_num_instances() - 1), each holding the tile-function
+// groups exec_instance_groups(i); the last holds every group.  exec_max_workers: workgroups of
+// instance i the device holds resident at once (CUs x workgroups per CU by its registers and LDS).
+int exec_num_instances();
+uint32_t exec_instance_groups(int instance);
+int exec_max_workers(int device, int instance);
+
 // Launch helpers (enqueue on `stream`).  The executor runs a.n_workers workgroups, at most as
 // many as the GPU holds resident at once (a task may wait for any other workgroup's earlier task).
 hipError_t launch_exec_reset(const ExecArgs &a, hipStream_t stream);
-hipError_t launch_exec(const ExecArgs &a, hipStream_t stream);
-int exec_max_workers(int device);
+hipError_t launch_exec(const ExecArgs &a, int instance, hipStream_t stream);
 
 }  // namespace psc

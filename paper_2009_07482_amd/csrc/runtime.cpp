@@ -111,6 +111,7 @@ struct Device {
   // PSC_DEVICE executor
   void *exec_mem = nullptr;
   ExecArgs ea{};
+  int exec_instance = 0;       // compiled executor instance (tile-function groups) for this DAG
   uint32_t *h_err = nullptr;  // page-locked word receiving the executor's error flag
   double clock_mhz = 100.0;   // device wall clock rate
 
@@ -238,11 +239,12 @@ struct ExecPlan {
   std::vector<int32_t> work_off;
 };
 
-ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
+// The executor's node descriptions for max_workers workgroups: each kernel's tile is chosen for the
+// workgroups it can expect (all of them divided by the kernels at its depth, the longest path
+// from a root).
+std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
-  ExecPlan ep;
-  ep.nodes.resize(nk);
-  // kernels beside each kernel: those at the same depth (longest path from a root)
+  std::vector<ExecNode> nodes(nk);
   std::vector<int32_t> depth(nk, 0), width;
   for (int32_t k : g.bfs_order())
     for (int32_t q : g.succ[k]) depth[q] = std::max(depth[q], depth[k] + 1);
@@ -251,12 +253,21 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
     ++width[depth[k]];
   }
   const int32_t Wmax = std::max(1, max_workers);
-  uint64_t total = 0;
   for (int32_t k = 0; k < nk; ++k) {
     const Kernel &ker = g.kers[k];
     const int want = std::max(1, Wmax / std::max(1, width[depth[k]]));
-    ep.nodes[k] = make_exec_node(ker.kind, launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
-                                 launch[k].tile, want);
+    nodes[k] = make_exec_node(ker.kind, launch[k].args, in_dtype_of(g, ker), g.bufs[ker.outs[0]].dtype,
+                              launch[k].tile, want);
+  }
+  return nodes;
+}
+
+ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  ExecPlan ep;
+  ep.nodes = exec_nodes(g, launch, max_workers);
+  uint64_t total = 0;
+  for (int32_t k = 0; k < nk; ++k) {
     ep.nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
     ep.nodes[k].pred_off = static_cast<int32_t>(ep.pred.size());
     ep.pred.insert(ep.pred.end(), g.pred[k].begin(), g.pred[k].end());
@@ -340,9 +351,31 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
   return ep;
 }
 
+// The executor instance for a DAG: among the compiled instances, by decreasing resident
+// workgroups, the first whose tile-function groups cover every node variant the DAG gets at that
+// worker count (the tile choice depends on the worker count); the last instance covers all.
+int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int device, int32_t *workers) {
+  const int n = exec_num_instances();
+  std::vector<std::pair<int32_t, int>> cand;  // (-workers, instance): more workers first, then order
+  for (int i = 0; i < n; ++i) cand.push_back({-exec_max_workers(device, i), i});
+  std::sort(cand.begin(), cand.end());
+  for (const auto &c : cand) {
+    uint32_t need = 0;
+    for (const ExecNode &nd : exec_nodes(g, launch, -c.first)) need |= exec_variant_group(nd.variant);
+    if ((need & ~exec_instance_groups(c.second)) == 0) {
+      *workers = -c.first;
+      return c.second;
+    }
+  }
+  *workers = exec_max_workers(device, n - 1);
+  return n - 1;
+}
+
 void prepare_executor(const Dag &g, Device &d) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
-  ExecPlan ep = plan_executor(g, d.launch, exec_max_workers(d.device));
+  int32_t max_workers = 1;
+  d.exec_instance = pick_exec_instance(g, d.launch, d.device, &max_workers);
+  ExecPlan ep = plan_executor(g, d.launch, max_workers);
   const std::vector<ExecNode> &nodes = ep.nodes;
   const std::vector<int32_t> &pred = ep.pred;
   const std::vector<ExecTask> &tasks = ep.tasks;
@@ -846,7 +879,7 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
       if (s.plan.ops[o].type == PSC_OP_H2D) do_copy(cd[o], s0);
     *d.h_err = 0;  // the previous run has completed: psc_run waits for its end
     PSC_HIP(launch_exec_reset(d.ea, s0));
-    PSC_HIP(launch_exec(d.ea, s0));
+    PSC_HIP(launch_exec(d.ea, d.exec_instance, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
       if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
     PSC_HIP(hipEventRecord(d.end, s0));
@@ -914,8 +947,9 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   }
   d.have_marks = d.marks != nullptr || s.plan.device;
   if (s.plan.device && *d.h_err)
-    fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) +
-                          "): a wait for a predecessor kernel exceeded its bound");
+    fail(PSC_ERR_HIP, std::string("device executor stopped (flag ") + std::to_string(*d.h_err) + "): " +
+                          (*d.h_err == 2 ? "a task's tile function is not in the executor instance"
+                                         : "a wait for a predecessor kernel exceeded its bound"));
   if (timed && s.plan.device) {
     const int32_t nk = d.ea.n_nodes;
     std::vector<uint64_t> tf(nk), tl(nk);
@@ -1259,6 +1293,20 @@ int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, flo
 int sched_kernel_tile(const psc_sched &s, int32_t kernel) {
   if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
   return s.dev->launch[kernel].tile;
+}
+
+void sched_executor_info(const psc_sched &s, int32_t *workers, int32_t *per_cu, uint32_t *groups) {
+  if (!s.dev) fail(PSC_ERR_STATE, "schedule not prepared");
+  if (!s.plan.device) fail(PSC_ERR_STATE, "not a PSC_DEVICE schedule");
+  const Device &d = *s.dev;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d.device) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  if (workers) *workers = d.ea.n_workers;
+  if (per_cu) *per_cu = exec_max_workers(d.device, d.exec_instance) / cus;
+  if (groups) *groups = exec_instance_groups(d.exec_instance);
 }
 
 void *host_alloc(size_t bytes) {
