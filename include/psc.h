@@ -77,7 +77,11 @@ typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_AD
  * runs the tiles of every kernel from per-workgroup task lists that the host plans ahead of the
  * run (list scheduling of tiles onto workgroups in one topological order), each workgroup waiting
  * on the completion counters of a task's predecessor kernels; host copies run before (H2D) and
- * after (D2H) it on one stream.  Its exported structure puts each kernel on its own queue with a wait on every
+ * after (D2H) it on one stream.  The grid is sized to the workgroups the GPU holds at once
+ * (psc_sched_executor_info), and progress assumes they all become resident: a task may wait for
+ * any other workgroup's earlier task.  If other work keeps CUs occupied for longer than a wait's
+ * bound (5 s of device time), the waiting workgroups flag the error, every workgroup leaves its
+ * list, and psc_run fails with PSC_ERR_HIP instead of hanging.  Its exported structure puts each kernel on its own queue with a wait on every
  * predecessor kernel and on the H2D copies of its inputs, which is what the device enforces.
  * Eager and HEFT: the dynamic coarse-grained baselines of Sec. V (Experiments 2 and 3, after
  * StarPU's policies), run through the scheduling loop of Algorithm 1 (schedule, select, cb):
