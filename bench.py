@@ -425,8 +425,8 @@ def kernels_main(a):
     cases = [("softmax", (262144, 1024), "f32", "f32"), ("softmax", (131072, 2048), "f32", "bf16"),
              ("softmax", (262144, 2048), "bf16", "bf16"), ("transpose", (16384, 16384), "f32", "f32"),
              ("transpose", (16384, 16384), "bf16", "bf16"), ("transpose1", (16384, 16384), "f32", "f32"),
-             ("transpose1", (16384, 16384), "bf16", "bf16"), ("transpose3", (16384, 16384), "f32", "f32"),
-             ("transpose3", (16384, 16384), "bf16", "bf16"), ("add", (16384, 16384), "f32", "f32"),
+             ("transpose1", (16384, 16384), "bf16", "bf16"), ("transpose2", (16384, 16384), "f32", "f32"),
+             ("transpose2", (16384, 16384), "bf16", "bf16"), ("add", (16384, 16384), "f32", "f32"),
              ("gemm", (4096, 4096, 4096), "bf16", "f32"), ("gemm", (8192, 8192, 8192), "bf16", "bf16"),
              ("gemm", (4096, 4096, 4096), "f32", "f32"), ("gemm", (1024, 64, 1024), "bf16", "bf16"),
              ("gemm", (512, 64, 512), "f32", "f32")]
@@ -474,7 +474,8 @@ def kernels_main(a):
         else:
             r_, c_ = shp
             if kind.startswith("transpose"):
-                # transpose2 / transpose3: the 64 x 128 and 128 x 64 tiles
+                # transpose1 / transpose2 / transpose3 / transpose4: the 64 x 64, 64 x 128,
+                # 128 x 64 and 64 x 256 tiles
                 spec = one_kernel("transpose", [(r_, c_), (c_, r_)], [idt, odt], tile=int(kind[9:] or 0))
                 work = r_ * c_ * (es[idt] + es[odt])
             elif kind == "add":
@@ -487,7 +488,8 @@ def kernels_main(a):
             label = f"{kind} {r_}x{c_} {idt}->{odt}"
             if kind.startswith("transpose"):
                 label = f"transpose {r_}x{c_} {idt}->{odt} " + {"": "(automatic tile)", "1": "(64x64 tiles)",
-                                                                "2": "(64x128 tiles)", "3": "(128x64 tiles)"}[kind[9:]]
+                                                                "2": "(64x128 tiles)", "3": "(128x64 tiles)",
+                                                                "4": "(64x256 tiles)"}[kind[9:]]
         r = psc.SpecRunner(spec, "coarse")
         ins = seeded_inputs(spec)
         r.set_inputs(ins)

@@ -144,8 +144,9 @@ typedef struct psc_kernel_params {
   int32_t alpha_set;    /* nonzero: use alpha as given (so alpha = 0 is expressible) */
   int32_t tile;         /* GEMM tile configuration index, -1 or 0 = automatic; for a transpose
                            the tile of the input a block moves: 1 = 64 x 64, 2 = 64 x 128,
-                           3 = 128 x 64 (rows x columns; 2 and 3 need 16-byte aligned operands,
-                           else 1), 0 = automatic (2 for transposes of 256 MiB and more, else 1) */
+                           3 = 128 x 64, 4 = 64 x 256 (rows x columns; 2 to 4 need 16-byte
+                           aligned operands, else 1), 0 = automatic (4 for transposes of 256 MiB
+                           and more, else 1) */
   int32_t reserved;
 } psc_kernel_params;
 

@@ -372,16 +372,17 @@ bool make_softmax(Launch &L, SoftmaxArgs a, int in_dtype, int out_dtype) {
 
 #define PSC_TRC(T, TR, TC) (nt ? (const void *)&transpose_rc_kernel<T, TR, TC, true> : (const void *)&transpose_rc_kernel<T, TR, TC, false>)
 
-// tile: 1 64 x 64, 2 64 x 128, 3 128 x 64 (rows x columns of the input); the rectangular tiles
-// need aligned operands (else 64 x 64).  Automatic (0): 64 x 128 for streaming sizes (on a 16384^2
-// transpose 1-2% faster than 64 x 64: 66.8% / 68.0% of HBM bandwidth for FP32 / BF16 against
-// 65.5% / 67.5%; 128 x 64 and streaming hints on only the loads or only the stores were slower),
-// 64 x 64 otherwise.
+// tile: 1 64 x 64, 2 64 x 128, 3 128 x 64, 4 64 x 256 (rows x columns of the input); the
+// rectangular tiles need aligned operands (else 64 x 64).  Automatic (0): 64 x 256 for streaming
+// sizes, 64 x 64 otherwise.  Measured on a 16384^2 transpose with streaming hints (HBM fraction,
+// FP32 / BF16): 64 x 256 70.2-70.5% / 71.2-72.1%; 128 x 256 (BF16) 71.2%; 64 x 128 66.9% / 67.9%;
+// 64 x 64 65.4% / 67.1%; 128 x 128 66.3% / 68.2%; 32 x 256 68.7-68.9% / 52.5%; 64 x 512 (BF16)
+// 68.3%; without the hints every shape 1.5-4 points lower.
 bool make_transpose(Launch &L, TransArgs a, int dtype, int tile) {
   const int64_t v = dtype == 1 ? 8 : 4;  // elements per 16-byte vector
   const bool vec = aligned16(a.A) && aligned16(a.B) && a.lda % v == 0 && a.ldb % v == 0;
   const bool nt = int64_t(a.R) * a.C * (dtype == 1 ? 2 : 4) >= kStreamBytes;
-  if (tile < 1 || tile > 3) tile = nt ? 2 : 1;
+  if (tile < 1 || tile > 4) tile = nt ? 4 : 1;
   if (!vec) tile = 1;
   int tr = 64, tcl = 64;
   if (tile == 1 && vec)
@@ -391,6 +392,8 @@ bool make_transpose(Launch &L, TransArgs a, int dtype, int tile) {
     L.func = dtype == 1 ? (const void *)&transpose_kernel<uint16_t> : (const void *)&transpose_kernel<float>;
   else if (tile == 2)
     L.func = dtype == 1 ? PSC_TRC(uint16_t, 64, 128) : PSC_TRC(float, 64, 128), tcl = 128;
+  else if (tile == 4)
+    L.func = dtype == 1 ? PSC_TRC(uint16_t, 64, 256) : PSC_TRC(float, 64, 256), tcl = 256;
   else
     L.func = dtype == 1 ? PSC_TRC(uint16_t, 128, 64) : PSC_TRC(float, 128, 64), tr = 128;
   L.tile = tile;

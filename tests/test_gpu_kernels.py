@@ -89,7 +89,7 @@ def test_gemm_bf16_whole_tile_exact(tile, m, n, k):
 @pytest.mark.parametrize("r,c", [(1, 1), (64, 64), (512, 64), (64, 512), (130, 257), (1024, 64), (0, 5),
                                  (136, 264), (72, 200), (8, 4104), (256, 384), (200, 136)])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 def test_transpose_exact(r, c, dt, tile):
     spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt], tile=tile)
     a = uniform(7, (r, c))
@@ -170,7 +170,7 @@ def test_add_and_transpose_on_column_windows(dt):
 
 # Outputs of 256 MiB and more take the streaming (non-temporal) variants; ragged edges on both axes.
 @pytest.mark.parametrize("dt,r,c", [("f32", 8200, 8216), ("bf16", 10000, 13432)])
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 def test_transpose_large_streaming(dt, r, c, tile):
     print(f"transpose {r}x{c} {dt} tile {tile}", flush=True)
     spec = one_kernel_spec("transpose", [(r, c), (c, r)], [dt, dt], tile=tile)
