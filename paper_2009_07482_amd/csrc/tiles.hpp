@@ -415,7 +415,8 @@ __device__ __forceinline__ void gemm_f32_splitk_tile(const GemmArgs &p, int bid,
 
   load(w);  // chunk w; chunks >= nchunks load zeros
   for (int it = 0; it < iters; ++it) {
-    __syncthreads();
+    // no block barrier in this loop: each wavefront stages and reads only its own LDS region,
+    // and one wavefront's LDS operations take effect in program order
 #pragma unroll
     for (int j = 0; j < UA; ++j) {
       const int u = lane + 64 * j, r = u / (BK / 4), c = (u % (BK / 4)) * 4;
@@ -429,7 +430,6 @@ __device__ __forceinline__ void gemm_f32_splitk_tile(const GemmArgs &p, int bid,
       const int u = lane + 64 * j, r = u / (TN / 4), c = (u % (TN / 4)) * 4;
       *reinterpret_cast<float4 *>(&Bs[r * SB + c]) = rb[j];
     }
-    __syncthreads();
     if (it + 1 < iters) load((it + 1) * 4 + w);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -528,7 +528,8 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
 
   load(w);
   for (int it = 0; it < iters; ++it) {
-    __syncthreads();
+    // no block barrier in this loop: each wavefront stages and reads only its own LDS region,
+    // and one wavefront's LDS operations take effect in program order
 #pragma unroll
     for (int j = 0; j < UA; ++j) {
       const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
@@ -544,7 +545,6 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
       for (int e = 0; e < 8; ++e)
         *reinterpret_cast<uint32_t *>(&Bt[(c + e) * KP + 2 * kp]) = uint32_t(lo[e]) | (uint32_t(hi[e]) << 16);
     }
-    __syncthreads();
     if (it + 1 < iters) load((it + 1) * 4 + w);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
