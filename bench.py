@@ -336,14 +336,15 @@ def stored_traffic(kernel_key, tile):
     import re
     digest = source_digest(kernel_key.startswith("exec_kernel"))
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
-        txt = open(f).read()
-        kv = dict(re.findall(r"^- (\w+): `([^`]*)`", txt, re.M))
-        if kv.get("kernel") == kernel_key and kv.get("source_digest") == digest and \
-                kv.get("tile", "None") == str(tile):
-            try:
-                return float(kv["traffic_bytes_per_launch"])
-            except (KeyError, ValueError):
-                return None
+        # one entry per block of "- key: `value`" lines (a file may hold several tiles)
+        for block in re.split(r"\n\s*\n", open(f).read()):
+            kv = dict(re.findall(r"^- (\w+): `([^`]*)`", block, re.M))
+            if kv.get("kernel") == kernel_key and kv.get("source_digest") == digest and \
+                    kv.get("tile", "None") == str(tile):
+                try:
+                    return float(kv["traffic_bytes_per_launch"])
+                except (KeyError, ValueError):
+                    return None
     return None
 
 
