@@ -654,7 +654,10 @@ psc_status psc_tile_cache_load(const char *path, const char *key, int32_t *n_loa
 /* [GPU] Times every tile configuration for C (M x N) = A (M x K) * B (K x N) on zero-filled
  * device buffers (iters back-to-back launches between HIP events, after 3 warm-up launches),
  * stores the fastest in the cache and returns it in *best_tile and its mean microseconds in
- * *best_us.  us_per_tile[t] for t < cap receives every configuration's time (index 0 unused).
+ * *best_us.  us_per_tile[t] for t < cap receives every configuration's time (index 0 unused);
+ * a configuration that resolves to another for this shape and dtype (16-20 with FP32 operands,
+ * 16 and 20 on shapes that are not whole 256 x 256 tiles) is not timed and its entry is left
+ * unchanged, so the cache always names the tile a launch uses.
  * Any output pointer may be NULL.  Errors: PSC_ERR_ARG, PSC_ERR_HIP, PSC_ERR_OOM. */
 psc_status psc_autotune_gemm(int32_t device, int32_t M, int32_t N, int32_t K, int32_t ab_dtype,
                              int32_t c_dtype, int32_t iters, int32_t *best_tile, float *best_us,

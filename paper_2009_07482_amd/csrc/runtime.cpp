@@ -1267,7 +1267,10 @@ int autotune_gemm(int device, int M, int N, int K, int ab, int c, int iters, flo
       g.lda = K; g.ldb = N; g.ldc = N;
       g.M = M; g.N = N; g.K = K; g.alpha = 1.0f;
       Launch L;
-      if (!make_gemm(L, g, ab, c, t)) continue;
+      // a configuration that resolves to another one for this shape and dtype (BF16-only tiles
+      // with FP32 operands, whole-tile configurations on a shape they do not fit) is not timed:
+      // the cache must name the tile a launch actually uses
+      if (!make_gemm(L, g, ab, c, t) || L.tile != t) continue;
       for (int w = 0; w < 3; ++w) launch(L, st);
       PSC_HIP(hipEventRecord(e0, st));
       for (int i = 0; i < iters; ++i) launch(L, st);

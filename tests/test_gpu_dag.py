@@ -207,18 +207,21 @@ def test_device_executor_matches_streams_bit_identical(mha512):
 
 
 @pytest.mark.parametrize("gemm_dtype", ["f32", "bf16"])
-def test_device_executor_instance_holds_two_workgroups_per_cu(gemm_dtype):
+def test_device_executor_takes_a_smaller_instance(gemm_dtype):
     # an attention DAG needs the 64 x 64 and direct-load GEMM tiles and the element-wise kernels
-    # only: the executor instance holding just those keeps two workgroups per CU (the one holding
-    # every tile function, one); its results match the oracle
+    # only: the executor takes an instance holding just those, not the one holding every tile
+    # function, with as many workgroups as the runtime says the device holds of it (two per CU on
+    # the MI355X boxes measured: 244-256 registers; the all-function instance fits one); its
+    # results match the oracle
     spec = workloads.mha_spec(512, 512, 8, gemm_dtype=gemm_dtype)
     inp = workloads.mha_inputs(1, 512, 512)
     ref = odag.read_buffer(spec, odag.run_dag(spec, inp), "Y0")
     r = psc.SpecRunner(spec, "device")
     psc.psc_sched_prepare(r.sched)
     workers, per_cu, groups = psc.psc_sched_executor_info(r.sched)
-    print(f"{gemm_dtype}: {workers} workers, {per_cu} per CU, groups {groups:#x}", flush=True)
-    assert per_cu >= 2 and workers % per_cu == 0
+    cus = psc.psc_device_info(0)["compute_units"]
+    print(f"{gemm_dtype}: {workers} workers, {per_cu} per CU on {cus} CUs, groups {groups:#x}", flush=True)
+    assert per_cu >= 1 and 0 < workers <= per_cu * cus
     assert groups != 0x3FFF and groups & (1 << 13)
     r.set_inputs(inp)
     r.run()
