@@ -56,6 +56,50 @@ __device__ __forceinline__ void add_task(const AddArgs &p, int tile) {
   }
 }
 
+// Copies rows [tile rpt, (tile + 1) rpt) of a host copy, the region taken as units of 16 bytes
+// when every address, pitch and the width allow it (else 2 bytes: rows hold whole FP32 or BF16
+// elements), eight units in flight per thread: over the host link one access takes microseconds.
+__device__ __forceinline__ void copy_task(const CopyArgs &c, int tile) {
+  const int64_t r0 = int64_t(tile) * c.rows_per_task;
+  const int64_t nr = min(int64_t(c.rows), r0 + c.rows_per_task) - r0;
+  if (nr <= 0) return;
+  const bool v16 = ((reinterpret_cast<uintptr_t>(c.src) | reinterpret_cast<uintptr_t>(c.dst) |
+                     uint64_t(c.spitch) | uint64_t(c.dpitch) | uint64_t(c.width)) & 15u) == 0;
+  const unsigned char *src = c.src + r0 * c.spitch;
+  unsigned char *dst = c.dst + r0 * c.dpitch;
+  if (v16) {
+    const int64_t upr = c.width / 16, n = nr * upr;
+    for (int64_t base = threadIdx.x; base < n; base += 256 * 8) {
+      uint4 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t u = base + 256 * j;
+        if (u < n) v[j] = *reinterpret_cast<const uint4 *>(src + (u / upr) * c.spitch + (u % upr) * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t u = base + 256 * j;
+        if (u < n) *reinterpret_cast<uint4 *>(dst + (u / upr) * c.dpitch + (u % upr) * 16) = v[j];
+      }
+    }
+  } else {
+    const int64_t upr = c.width / 2, n = nr * upr;
+    for (int64_t base = threadIdx.x; base < n; base += 256 * 8) {
+      uint16_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t u = base + 256 * j;
+        if (u < n) v[j] = *reinterpret_cast<const uint16_t *>(src + (u / upr) * c.spitch + (u % upr) * 2);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t u = base + 256 * j;
+        if (u < n) *reinterpret_cast<uint16_t *>(dst + (u / upr) * c.dpitch + (u % upr) * 2) = v[j];
+      }
+    }
+  }
+}
+
 // Loads a kernel-argument record as wavefront-uniform (scalar) values.
 template <typename T>
 __device__ __forceinline__ T uniform_load(const unsigned char *p) {
@@ -155,6 +199,7 @@ __device__ __forceinline__ bool run_task(const ExecNode *ndp, int tile, unsigned
     PSC_TASK(339, softmax_task<8, true, true, true>(uniform_load<SoftmaxArgs>(nd.args), tile));
     PSC_TASK(400, transpose_tile<float>(uniform_load<TransArgs>(nd.args), tile, smem));
     PSC_TASK(401, transpose_tile<uint16_t>(uniform_load<TransArgs>(nd.args), tile, smem));
+    PSC_TASK(420, copy_task(uniform_load<CopyArgs>(nd.args), tile));
     PSC_TASK(410, add_task<false, false>(uniform_load<AddArgs>(nd.args), tile));
     PSC_TASK(411, add_task<false, true>(uniform_load<AddArgs>(nd.args), tile));
     PSC_TASK(412, add_task<true, false>(uniform_load<AddArgs>(nd.args), tile));
@@ -252,10 +297,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exec_waves(
       __syncthreads();
       if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the end time is read before the add: a consumer may see the count complete (and stamp
+        // its own start) while this returning add is still on its way back
+        const uint64_t now = wall_clock64();
         const uint32_t before =
             __hip_atomic_fetch_add(&a.done[t.node], uint32_t(t.signal), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (before + uint32_t(t.signal) == uint32_t(nd->n_tiles))
-          __hip_atomic_store(&a.t_last[t.node], uint64_t(wall_clock64()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.t_last[t.node], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     } else {
       __syncthreads();  // the next task reuses the LDS

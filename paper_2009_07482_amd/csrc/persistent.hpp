@@ -25,6 +25,19 @@ struct alignas(16) ExecNode {
   unsigned char args[96];  // GemmArgs / SoftmaxArgs / TransArgs / AddArgs
 };
 
+// An isolated upload or read-back run by the executor's own workgroups (variant 420): rows of
+// `width` bytes from src (row pitch spitch) to dst (dpitch), task t covering rows
+// [t rows_per_task, (t + 1) rows_per_task).  One side is page-locked host memory the device
+// reads or writes directly; the host fills the record before every run.
+struct CopyArgs {
+  const unsigned char *src;
+  unsigned char *dst;
+  int64_t spitch, dpitch, width;
+  int32_t rows, rows_per_task;
+};
+constexpr int kCopyVariant = 420;
+static_assert(sizeof(CopyArgs) <= sizeof(ExecNode::args), "copy record fits a node's arguments");
+
 // One entry of a workgroup's task list.  signal > 0: after this task, publish `signal`
 // completed tiles of `node` (the task and the ones of the same node right before it).
 struct alignas(16) ExecTask {
@@ -58,7 +71,7 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
 // Tile-function groups: the group bit of a node variant (0 for the empty variant 0).  Groups
 // 0-5: FP32 GEMM tiles (64x64 and 32x32 staged through LDS, split-K, direct-load with 1, 2 and 4
 // column blocks); 6-12: the BF16 ones (and a separate group for the unaligned direct-load
-// tile); 13: softmax, transpose and add.
+// tile); 13: softmax, transpose, add and the host copies.
 constexpr uint32_t kGElem = 1u << 13;
 __host__ __device__ constexpr uint32_t exec_variant_group(int v) {
   return v == 110 || v == 111 ? 1u << 0
@@ -74,7 +87,7 @@ __host__ __device__ constexpr uint32_t exec_variant_group(int v) {
        : v == 254 || v == 255 ? 1u << 10
        : v == 258 || v == 259 ? 1u << 11
        : v == 262 || v == 263 ? 1u << 12
-       : v >= 300 && v <= 413 ? kGElem
+       : (v >= 300 && v <= 413) || v == 420 ? kGElem
                               : 0u;
 }
 

@@ -83,6 +83,17 @@ void dyn_callback(void *p) {
   st.cv.notify_one();
 }
 
+// The host copies of a PSC_DEVICE plan the executor runs as nodes of its own (after the
+// kernels: node n_kernels + i), in plan op order: each isolated upload, with the kernels that
+// wait for it, and each read-back, with the kernel that produces it.
+struct ExecCopy {
+  int32_t op = -1, buffer = -1;
+  bool h2d = true;
+  std::vector<int32_t> kernels;
+  int32_t rows = 0, rows_per_task = 1;
+  int64_t width = 0;  // bytes per row
+};
+
 struct Device {
   int device = 0;
   void *arena = nullptr;
@@ -112,6 +123,12 @@ struct Device {
   void *exec_mem = nullptr;
   ExecArgs ea{};
   int exec_instance = 0;       // compiled executor instance (tile-function groups) for this DAG
+  void *exec_mem_copy = nullptr;      // the plan with the host copies (ea_copy)
+  ExecArgs ea_copy{};
+  const ExecArgs *ea_run = &ea;       // the plan the last run used
+  std::vector<ExecCopy> exec_copies;  // host copies run as executor nodes (after the kernels)
+  std::vector<char> exec_dma;         // per plan op: this run copied it by DMA instead
+  ExecNode *h_copy_nodes = nullptr;   // page-locked: their records, rewritten before every run
   uint32_t *h_err = nullptr;  // page-locked word receiving the executor's error flag
   double clock_mhz = 100.0;   // device wall clock rate
 
@@ -120,8 +137,10 @@ struct Device {
     aql.reset();                                           // (waits for its own run the same way)
     disp.reset();
     if (exec_mem) (void)hipFree(exec_mem);
+    if (exec_mem_copy) (void)hipFree(exec_mem_copy);
     if (marks) (void)hipFree(marks);
     if (h_err) (void)hipHostFree(h_err);
+    if (h_copy_nodes) (void)hipHostFree(h_copy_nodes);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (hipEvent_t e : op_ev)
@@ -262,26 +281,64 @@ std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch
   return nodes;
 }
 
-ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
-  const int32_t nk = static_cast<int32_t>(g.kers.size());
-  ExecPlan ep;
-  ep.nodes = exec_nodes(g, launch, max_workers);
-  uint64_t total = 0;
-  for (int32_t k = 0; k < nk; ++k) {
-    ep.nodes[k].n_pred = static_cast<int32_t>(g.pred[k].size());
-    ep.nodes[k].pred_off = static_cast<int32_t>(ep.pred.size());
-    ep.pred.insert(ep.pred.end(), g.pred[k].begin(), g.pred[k].end());
-    total += uint64_t(ep.nodes[k].n_tiles);
+std::vector<ExecCopy> exec_copies(const Dag &g, const SchedPlan &plan) {
+  std::vector<ExecCopy> c;
+  std::vector<int32_t> idx(plan.ops.size(), -1);
+  for (size_t o = 0; o < plan.ops.size(); ++o) {
+    const Op &op = plan.ops[o];
+    if (op.type == PSC_OP_KERNEL) continue;
+    idx[o] = static_cast<int32_t>(c.size());
+    ExecCopy x;
+    x.op = static_cast<int32_t>(o);
+    x.buffer = op.buffer;
+    x.h2d = op.type == PSC_OP_H2D;
+    const Buffer &b = g.bufs[op.buffer];
+    x.rows = b.rows;
+    x.width = int64_t(b.cols) * elem_size(b.dtype);
+    // tasks of about 64 KiB
+    x.rows_per_task = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(b.rows, 65536 / std::max<int64_t>(1, x.width))));
+    c.push_back(std::move(x));
   }
-  if (total >= (uint64_t(1) << 31)) fail(PSC_ERR_UNSUPPORTED, "too many executor tasks");
-  const int32_t W = static_cast<int32_t>(std::max<uint64_t>(1, std::min<uint64_t>(total, uint64_t(std::max(1, max_workers)))));
+  for (size_t o = 0; o < plan.ops.size(); ++o) {
+    const Op &op = plan.ops[o];
+    for (int32_t w : op.waits) {
+      if (op.type == PSC_OP_KERNEL && idx[w] >= 0 && c[idx[w]].h2d) c[idx[w]].kernels.push_back(op.kernel);
+      if (op.type == PSC_OP_D2H && plan.ops[w].type == PSC_OP_KERNEL) c[idx[o]].kernels.push_back(plan.ops[w].kernel);
+    }
+  }
+  return c;
+}
+
+// Copy tasks run on at most this many workgroups of their own (W / 16 of the grid).
+constexpr int32_t kCopyWorkers = 32;
+
+ExecNode make_copy_node(const ExecCopy &x) {
+  ExecNode n{};
+  if (x.rows == 0 || x.width == 0) {
+    n.variant = 0;
+    n.n_tiles = 1;
+    return n;
+  }
+  n.variant = kCopyVariant;
+  n.n_tiles = (x.rows + x.rows_per_task - 1) / x.rows_per_task;
+  n.tile_m = x.rows_per_task;
+  n.tile_n = static_cast<int32_t>(std::min<int64_t>(x.width, INT32_MAX));
+  return n;
+}
+
+// List schedule of the kernels' tiles onto W workgroups (lists[0 .. W)): kernels in descending
+// bottom-level order among those whose predecessors are placed, each tile on the workgroup
+// predicted to finish it first.  Returns every kernel's bottom level.
+std::vector<double> schedule_kernels(const Dag &g, const std::vector<ExecNode> &nodes, int32_t W,
+                                     std::vector<std::vector<ExecTask>> &lists) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
   std::vector<double> cost(nk), bl(nk, 0.0), finish(nk, 0.0);
-  for (int32_t k = 0; k < nk; ++k) cost[k] = exec_task_us(g, g.kers[k], ep.nodes[k]);
+  for (int32_t k = 0; k < nk; ++k) cost[k] = exec_task_us(g, g.kers[k], nodes[k]);
   const std::vector<int32_t> topo = g.bfs_order();
   for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
     double m = 0;
     for (int32_t q : g.succ[*it]) m = std::max(m, bl[q]);
-    bl[*it] = cost[*it] * std::ceil(double(ep.nodes[*it].n_tiles) / W) + m;
+    bl[*it] = cost[*it] * std::ceil(double(nodes[*it].n_tiles) / W) + m;
   }
   using Item = std::pair<double, int32_t>;  // (-rank, kernel)
   std::priority_queue<Item, std::vector<Item>, std::greater<Item>> ready;
@@ -300,7 +357,6 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
   using Free = std::pair<double, int32_t>;  // (time the workgroup is free, workgroup); lazy entries
   std::priority_queue<Free, std::vector<Free>, std::greater<Free>> free_at;
   for (int32_t w = 0; w < W; ++w) free_at.push({0.0, w});
-  std::vector<std::vector<ExecTask>> lists(W);
   std::vector<int32_t> used;
   while (!ready.empty()) {
     const int32_t k = ready.top().second;
@@ -310,7 +366,7 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
     for (int32_t p : g.pred[k]) rt = std::max(rt, finish[p]);
     const double sw = kRelease + (g.pred[k].empty() ? 0.0 : kAcquire);
     used.clear();
-    for (int32_t t = 0; t < ep.nodes[k].n_tiles; ++t) {
+    for (int32_t t = 0; t < nodes[k].n_tiles; ++t) {
       // continue on the earliest-free workgroup already running this kernel ...
       int32_t wc = -1;
       for (int32_t w : used)
@@ -336,12 +392,76 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
     for (int32_t q : g.succ[k])
       if (--indeg[q] == 0) ready.push({-bl[q], q});
   }
+  return bl;
+}
+
+// The executor's plan: node descriptions, predecessor lists and the per-workgroup task lists.
+// Without copies: the kernels' list schedule on every workgroup.  With copies (the executor
+// runs the uploads and read-backs itself): the last CW = W / 16 (at most 32) workgroups run
+// only copy tasks -- every upload, the first needed first (by its readers' bottom level), then
+// every read-back -- dealt round robin, while the others run the kernels' list schedule; a
+// kernel also waits for its inputs' uploads, a read-back for its writer.  Each list is a
+// subsequence of one order in which every task comes after its predecessors' (uploads, kernels
+// in placement order, read-backs), so with all workgroups resident every wait ends.  Host only.
+ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers,
+                       const std::vector<ExecCopy> &copies) {
+  const int32_t nk = static_cast<int32_t>(g.kers.size());
+  const int32_t nc = static_cast<int32_t>(copies.size());
+  ExecPlan ep;
+  ep.nodes = exec_nodes(g, launch, max_workers);
+  std::vector<std::vector<int32_t>> P(nk);
+  for (int32_t k = 0; k < nk; ++k) P[k] = g.pred[k];
+  for (int32_t c = 0; c < nc; ++c) {
+    ep.nodes.push_back(make_copy_node(copies[c]));
+    P.emplace_back();
+    for (int32_t k : copies[c].kernels) {
+      if (copies[c].h2d) P[k].push_back(nk + c);
+      else P[nk + c].push_back(k);
+    }
+  }
+  uint64_t total = 0;
+  for (size_t v = 0; v < ep.nodes.size(); ++v) {
+    ep.nodes[v].n_pred = static_cast<int32_t>(P[v].size());
+    ep.nodes[v].pred_off = static_cast<int32_t>(ep.pred.size());
+    ep.pred.insert(ep.pred.end(), P[v].begin(), P[v].end());
+    total += uint64_t(ep.nodes[v].n_tiles);
+  }
+  if (total >= (uint64_t(1) << 31)) fail(PSC_ERR_UNSUPPORTED, "too many executor tasks");
+  const int32_t W = static_cast<int32_t>(std::max<uint64_t>(1, std::min<uint64_t>(total, uint64_t(std::max(1, max_workers)))));
+  const int32_t CW = nc == 0 || W < 2 ? 0 : std::min(kCopyWorkers, std::max(1, W / 16));
+  const int32_t WK = W - CW;  // workgroups running kernels
+  std::vector<std::vector<ExecTask>> lists(W);
+  const std::vector<double> bl = schedule_kernels(g, ep.nodes, WK, lists);
+  if (nc) {
+    std::vector<int32_t> ups, downs;
+    std::vector<double> pri(nc, 0.0);
+    for (int32_t c = 0; c < nc; ++c) {
+      (copies[c].h2d ? ups : downs).push_back(c);
+      for (int32_t k : copies[c].kernels) pri[c] = std::max(pri[c], bl[k]);
+    }
+    std::stable_sort(ups.begin(), ups.end(), [&](int32_t x, int32_t y) { return pri[x] > pri[y]; });
+    std::stable_sort(downs.begin(), downs.end(), [&](int32_t x, int32_t y) { return pri[x] > pri[y]; });
+    std::vector<ExecTask> seq;
+    for (int32_t c : ups)
+      for (int32_t t = 0; t < ep.nodes[nk + c].n_tiles; ++t) seq.push_back(ExecTask{nk + c, t, 0, 0});
+    const size_t n_up = seq.size();
+    for (int32_t c : downs)
+      for (int32_t t = 0; t < ep.nodes[nk + c].n_tiles; ++t) seq.push_back(ExecTask{nk + c, t, 0, 0});
+    if (CW > 0) {
+      for (size_t i = 0; i < seq.size(); ++i) lists[WK + int32_t(i % CW)].push_back(seq[i]);
+    } else {  // one workgroup: uploads, kernels, read-backs
+      std::vector<ExecTask> one(seq.begin(), seq.begin() + n_up);
+      one.insert(one.end(), lists[0].begin(), lists[0].end());
+      one.insert(one.end(), seq.begin() + n_up, seq.end());
+      lists[0] = std::move(one);
+    }
+  }
   ep.work_off.assign(W + 1, 0);
   ep.tasks.reserve(total);
   for (int32_t w = 0; w < W; ++w) {
     auto &L = lists[w];
     int32_t run = 0;
-    for (size_t i = 0; i < L.size(); ++i) {  // publish at the end of each run of one kernel's tiles
+    for (size_t i = 0; i < L.size(); ++i) {  // publish at the end of each run of one node's tiles
       run = (i > 0 && L[i - 1].node == L[i].node) ? run + 1 : 1;
       if (i + 1 == L.size() || L[i + 1].node != L[i].node) L[i].signal = run;
     }
@@ -371,34 +491,27 @@ int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int devi
   return n - 1;
 }
 
-void prepare_executor(const Dag &g, Device &d) {
-  const int32_t nk = static_cast<int32_t>(g.kers.size());
-  int32_t max_workers = 1;
-  d.exec_instance = pick_exec_instance(g, d.launch, d.device, &max_workers);
-  ExecPlan ep = plan_executor(g, d.launch, max_workers);
-  const std::vector<ExecNode> &nodes = ep.nodes;
-  const std::vector<int32_t> &pred = ep.pred;
-  const std::vector<ExecTask> &tasks = ep.tasks;
-  const std::vector<int32_t> &work_off = ep.work_off;
-  const int32_t W = static_cast<int32_t>(work_off.size()) - 1;
+// One executor plan in device memory (its own allocation, freed with the schedule).
+void upload_exec_plan(const ExecPlan &ep, Device &d, void *&mem, ExecArgs &a) {
+  const int32_t nn = static_cast<int32_t>(ep.nodes.size());
+  const int32_t W = static_cast<int32_t>(ep.work_off.size()) - 1;
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t o_nodes = 0, o_pred = o_nodes + up(sizeof(ExecNode) * std::max(1, nk));
-  const size_t o_tasks = o_pred + up(4 * std::max<size_t>(1, pred.size()));
-  const size_t o_off = o_tasks + up(sizeof(ExecTask) * std::max<size_t>(1, tasks.size()));
+  const size_t o_nodes = 0, o_pred = o_nodes + up(sizeof(ExecNode) * std::max(1, nn));
+  const size_t o_tasks = o_pred + up(4 * std::max<size_t>(1, ep.pred.size()));
+  const size_t o_off = o_tasks + up(sizeof(ExecTask) * std::max<size_t>(1, ep.tasks.size()));
   const size_t o_done = o_off + up(4 * size_t(W + 1));
-  const size_t o_ctl = o_done + up(4 * std::max(1, nk));
+  const size_t o_ctl = o_done + up(4 * std::max(1, nn));
   const size_t o_tf = o_ctl + 256;
-  const size_t o_tl = o_tf + up(8 * std::max(1, nk));
-  const size_t o_ts = o_tl + up(8 * std::max(1, nk));
+  const size_t o_tl = o_tf + up(8 * std::max(1, nn));
+  const size_t o_ts = o_tl + up(8 * std::max(1, nn));
   const size_t bytes = o_ts + 256;
-  hipError_t e = hipMalloc(&d.exec_mem, bytes);
+  hipError_t e = hipMalloc(&mem, bytes);
   if (e != hipSuccess) fail(PSC_ERR_OOM, std::string("hipMalloc (executor state): ") + hipGetErrorString(e));
-  char *base = static_cast<char *>(d.exec_mem);
-  PSC_HIP(hipMemcpy(base + o_nodes, nodes.data(), sizeof(ExecNode) * nk, hipMemcpyHostToDevice));
-  if (!pred.empty()) PSC_HIP(hipMemcpy(base + o_pred, pred.data(), 4 * pred.size(), hipMemcpyHostToDevice));
-  PSC_HIP(hipMemcpy(base + o_tasks, tasks.data(), sizeof(ExecTask) * tasks.size(), hipMemcpyHostToDevice));
-  PSC_HIP(hipMemcpy(base + o_off, work_off.data(), 4 * work_off.size(), hipMemcpyHostToDevice));
-  ExecArgs &a = d.ea;
+  char *base = static_cast<char *>(mem);
+  PSC_HIP(hipMemcpy(base + o_nodes, ep.nodes.data(), sizeof(ExecNode) * nn, hipMemcpyHostToDevice));
+  if (!ep.pred.empty()) PSC_HIP(hipMemcpy(base + o_pred, ep.pred.data(), 4 * ep.pred.size(), hipMemcpyHostToDevice));
+  PSC_HIP(hipMemcpy(base + o_tasks, ep.tasks.data(), sizeof(ExecTask) * ep.tasks.size(), hipMemcpyHostToDevice));
+  PSC_HIP(hipMemcpy(base + o_off, ep.work_off.data(), 4 * ep.work_off.size(), hipMemcpyHostToDevice));
   a.nodes = reinterpret_cast<const ExecNode *>(base + o_nodes);
   a.pred = reinterpret_cast<const int32_t *>(base + o_pred);
   a.tasks = reinterpret_cast<const ExecTask *>(base + o_tasks);
@@ -408,18 +521,34 @@ void prepare_executor(const Dag &g, Device &d) {
   a.t_first = reinterpret_cast<uint64_t *>(base + o_tf);
   a.t_last = reinterpret_cast<uint64_t *>(base + o_tl);
   a.t_start = reinterpret_cast<uint64_t *>(base + o_ts);
-  a.n_nodes = nk;
+  a.n_nodes = nn;
   a.n_workers = W;
-  PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
-  *d.h_err = 0;
   a.host_err = d.h_err;
+  // one wait may last 5 s of device time (the clock runs at clock_mhz)
+  a.max_wait = uint64_t(5.0e6 * d.clock_mhz);
+}
+
+// Two plans: the kernels alone (device-resident runs, and runs whose host memory the device
+// cannot address), and the kernels with the host copies run by the executor.
+void prepare_executor(const Dag &g, const SchedPlan &plan, Device &d) {
+  int32_t max_workers = 1;
+  d.exec_instance = pick_exec_instance(g, d.launch, d.device, &max_workers);
+  d.exec_copies = exec_copies(g, plan);
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
     d.clock_mhz = khz / 1000.0;
   else
     (void)hipGetLastError();  // keep the default rate; leave no sticky error behind
-  // one wait may last 5 s of device time (the clock runs at clock_mhz)
-  a.max_wait = uint64_t(5.0e6 * d.clock_mhz);
+  PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
+  *d.h_err = 0;
+  upload_exec_plan(plan_executor(g, d.launch, max_workers, {}), d, d.exec_mem, d.ea);
+  const size_t nc = d.exec_copies.size();
+  if (nc) {
+    const ExecPlan ep = plan_executor(g, d.launch, max_workers, d.exec_copies);
+    upload_exec_plan(ep, d, d.exec_mem_copy, d.ea_copy);
+    PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_copy_nodes), sizeof(ExecNode) * nc, hipHostMallocDefault));
+    for (size_t c = 0; c < nc; ++c) d.h_copy_nodes[c] = ep.nodes[ep.nodes.size() - nc + c];  // counts, predecessors
+  }
 }
 
 }  // namespace
@@ -487,7 +616,7 @@ void prepare(psc_sched &s) {
       (void)hipGetLastError();
   }
   if (dev_mode) {
-    prepare_executor(g, *d);
+    prepare_executor(g, s.plan, *d);
   } else if (s.plan.dynamic) {
     d->dyn = std::make_unique<DynState>();
   } else {
@@ -874,14 +1003,56 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
   double host_ms = 0;
   if (s.plan.device) {
     const auto h0 = std::chrono::steady_clock::now();
+    // The executor runs each upload and read-back whose host memory the device can address
+    // itself (page-locked memory mapped at the same address), as tasks of its copy plan beside
+    // the kernels; the others are DMA copies before (uploads) or after (read-backs) it, their
+    // nodes empty.  With no copy for the executor the kernels-only plan runs.
+    std::vector<char> &dma = d.exec_dma;
+    dma.assign(s.plan.ops.size(), 0);
+    const size_t nc = d.exec_copies.size();
+    size_t n_exec = 0;
+    for (size_t c = 0; c < nc; ++c) {
+      const ExecCopy &x = d.exec_copies[c];
+      const CopyDesc &cp = cd[x.op];
+      ExecNode &n = d.h_copy_nodes[c];
+      n.variant = 0;
+      if (!cp.active || x.rows == 0 || x.width == 0) continue;
+      const void *host = x.h2d ? cp.src : cp.dst;
+      hipPointerAttribute_t at{};
+      const bool mapped = hipPointerGetAttributes(&at, host) == hipSuccess && at.type == hipMemoryTypeHost &&
+                          at.devicePointer == host;
+      if (!mapped) {
+        (void)hipGetLastError();  // an unregistered pointer is an expected outcome, not an error
+        dma[x.op] = 1;
+        continue;
+      }
+      CopyArgs a{};
+      a.src = static_cast<const unsigned char *>(cp.src);
+      a.dst = static_cast<unsigned char *>(cp.dst);
+      a.spitch = int64_t(cp.spitch);
+      a.dpitch = int64_t(cp.dpitch);
+      a.width = int64_t(cp.width);
+      a.rows = x.rows;
+      a.rows_per_task = x.rows_per_task;
+      n.variant = kCopyVariant;
+      memcpy(n.args, &a, sizeof(a));
+      ++n_exec;
+    }
+    if (n_exec == 0)  // kernels-only plan: every active copy by DMA
+      for (size_t c = 0; c < nc; ++c) dma[d.exec_copies[c].op] = cd[d.exec_copies[c].op].active;
+    d.ea_run = n_exec ? &d.ea_copy : &d.ea;
+    const ExecArgs &ea = *d.ea_run;
     PSC_HIP(hipEventRecord(d.start, s0));
+    if (n_exec)
+      PSC_HIP(hipMemcpyAsync(const_cast<ExecNode *>(ea.nodes) + (ea.n_nodes - int32_t(nc)), d.h_copy_nodes,
+                             sizeof(ExecNode) * nc, hipMemcpyHostToDevice, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
-      if (s.plan.ops[o].type == PSC_OP_H2D) do_copy(cd[o], s0);
+      if (s.plan.ops[o].type == PSC_OP_H2D && dma[o]) do_copy(cd[o], s0);
     *d.h_err = 0;  // the previous run has completed: psc_run waits for its end
-    PSC_HIP(launch_exec_reset(d.ea, s0));
-    PSC_HIP(launch_exec(d.ea, d.exec_instance, s0));
+    PSC_HIP(launch_exec_reset(ea, s0));
+    PSC_HIP(launch_exec(ea, d.exec_instance, s0));
     for (size_t o = 0; o < s.plan.ops.size(); ++o)
-      if (s.plan.ops[o].type == PSC_OP_D2H) do_copy(cd[o], s0);
+      if (s.plan.ops[o].type == PSC_OP_D2H && dma[o]) do_copy(cd[o], s0);
     PSC_HIP(hipEventRecord(d.end, s0));
     host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   } else if (s.plan.dynamic) {
@@ -951,22 +1122,31 @@ void run(psc_sched &s, const psc_host_io *io, int32_t n_io, psc_run_stats *stats
                           (*d.h_err == 2 ? "a task's tile function is not in the executor instance"
                                          : "a wait for a predecessor kernel exceeded its bound"));
   if (timed && s.plan.device) {
-    const int32_t nk = d.ea.n_nodes;
+    const ExecArgs &ea = *d.ea_run;
+    const int32_t nk = ea.n_nodes;
     std::vector<uint64_t> tf(nk), tl(nk);
     uint64_t t0 = 0;
-    PSC_HIP(hipMemcpy(tf.data(), d.ea.t_first, 8 * nk, hipMemcpyDeviceToHost));
-    PSC_HIP(hipMemcpy(tl.data(), d.ea.t_last, 8 * nk, hipMemcpyDeviceToHost));
-    PSC_HIP(hipMemcpy(&t0, d.ea.t_start, 8, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(tf.data(), ea.t_first, 8 * nk, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(tl.data(), ea.t_last, 8 * nk, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(&t0, ea.t_start, 8, hipMemcpyDeviceToHost));
     d.times.assign(s.plan.ops.size(), psc_op_time{0, 0, 0.f, 0.f});
     d.active.assign(s.plan.ops.size(), 0);
+    std::vector<int32_t> node_of(s.plan.ops.size(), -1);  // executor node of each op
+    if (d.ea_run == &d.ea_copy) {
+      const int32_t nkern = nk - int32_t(d.exec_copies.size());
+      for (size_t c = 0; c < d.exec_copies.size(); ++c)
+        if (!d.exec_dma[d.exec_copies[c].op] && cd[d.exec_copies[c].op].active)
+          node_of[d.exec_copies[c].op] = nkern + int32_t(c);
+    }
     for (size_t o = 0; o < s.plan.ops.size(); ++o) {
       const Op &op = s.plan.ops[o];
       d.times[o].op = int32_t(o);
       d.times[o].stream = op.stream;
-      d.active[o] = op.type == PSC_OP_KERNEL && !d.launch[op.kernel].empty;
-      if (op.type == PSC_OP_KERNEL) {
-        d.times[o].start_us = float(double(int64_t(tf[op.kernel] - t0)) / d.clock_mhz);
-        d.times[o].end_us = float(double(int64_t(tl[op.kernel] - t0)) / d.clock_mhz);
+      if (op.type == PSC_OP_KERNEL) node_of[o] = d.launch[op.kernel].empty ? -1 : op.kernel;
+      d.active[o] = node_of[o] >= 0;
+      if (node_of[o] >= 0) {  // copies by DMA keep no device times
+        d.times[o].start_us = float(double(int64_t(tf[node_of[o]] - t0)) / d.clock_mhz);
+        d.times[o].end_us = float(double(int64_t(tl[node_of[o]] - t0)) / d.clock_mhz);
       }
     }
     d.have_times = true;
@@ -1080,7 +1260,7 @@ void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t c
   }
   std::vector<Launch> launch(g.kers.size());
   for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, d, int32_t(k), launch[k]);
-  const ExecPlan ep = plan_executor(g, launch, workers);
+  const ExecPlan ep = plan_executor(g, launch, workers, exec_copies(g, build_plan(g, PSC_DEVICE, s.opts)));
   *n_tasks = static_cast<int32_t>(ep.tasks.size());
   if (!tasks && !work_off) return;
   if (cap < *n_tasks) fail(PSC_ERR_ARG, "capacity too small");
@@ -1146,8 +1326,8 @@ void component_times(const psc_sched &s, float *done_us, int32_t cap, int32_t *n
     for (int32_t q : g.succ[k]) end[k] = end[k] && g.kers[q].component != g.kers[k].component;
   }
   if (s.plan.device) {
-    PSC_HIP(hipMemcpy(at.data(), d.ea.t_last, 8 * size_t(nk), hipMemcpyDeviceToHost));
-    PSC_HIP(hipMemcpy(&at[nk], d.ea.t_start, 8, hipMemcpyDeviceToHost));
+    PSC_HIP(hipMemcpy(at.data(), d.ea_run->t_last, 8 * size_t(nk), hipMemcpyDeviceToHost));  // kernels first
+    PSC_HIP(hipMemcpy(&at[nk], d.ea_run->t_start, 8, hipMemcpyDeviceToHost));
   } else {
     PSC_HIP(hipMemcpy(at.data(), d.marks, 8 * size_t(nk + 1), hipMemcpyDeviceToHost));
   }

@@ -330,26 +330,40 @@ def test_eft_spreads_work_over_every_stream():
     ("forkjoin", workloads.forkjoin_spec(256), 3),
 ])
 def test_device_executor_plan_cannot_deadlock(name, spec, workers):
-    """The PSC_DEVICE task lists: every tile of every kernel exactly once, published exactly once
-    (signals of a kernel add up to its tile count, each at the end of a run of its tiles), and the
-    wait-for relation -- list order within a workgroup plus 'a kernel's tasks wait for all tasks of
-    its predecessors' -- is acyclic, which with all workgroups resident means every wait ends."""
+    """The PSC_DEVICE task lists: every tile of every node (the kernels, then the host copies the
+    executor runs: the schedule's uploads and read-backs in op order) exactly once, published
+    exactly once (signals of a node add up to its tile count, each at the end of a run of its
+    tiles), and the wait-for relation -- list order within a workgroup plus 'a node's tasks wait
+    for all tasks of its predecessors' (a kernel's: its predecessor kernels and its inputs'
+    uploads; a read-back's: the kernel writing it) -- is acyclic, which with all workgroups
+    resident means every wait ends.  Copy tasks sit on the last W / 16 (at most 32) workgroups,
+    which run nothing else."""
     import numpy as np
     dag = psc.build_dag(spec)
     s = psc.psc_schedule(dag, "device")
     lists = psc.psc_sched_device_tasks(s, workers)
+    ops = psc.psc_sched_export(s)
     psc.psc_sched_destroy(s)
     psc.psc_dag_destroy(dag)
     nk = len(spec["kernels"])
+    copy_ops = [o for o in ops if o["type"] != "kernel"]
+    node_of_op = {o["id"]: nk + i for i, o in enumerate(copy_ops)}
+    node_of_op.update({o["id"]: o["kernel"] for o in ops if o["type"] == "kernel"})
+    nn = nk + len(copy_ops)
     tiles = {}
-    for L in lists:
+    for w, L in enumerate(lists):
         for (k, t, _) in L:
             tiles.setdefault(k, []).append(t)
-    assert sorted(tiles) == list(range(nk))
+    copy_workers = {w for w, L in enumerate(lists) if any(k >= nk for (k, _, _) in L)}
+    if workers >= 2:
+        # copy tasks only on workgroups that run no kernel task, and at most 32 of them
+        assert all(all(k >= nk for (k, _, _) in lists[w]) for w in copy_workers)
+        assert len(copy_workers) <= 32
+    assert sorted(tiles) == list(range(nn))
     ntiles = {k: len(v) for k, v in tiles.items()}
     for k, v in tiles.items():
         assert sorted(v) == list(range(len(v))), k
-    signalled = {k: 0 for k in range(nk)}
+    signalled = {k: 0 for k in range(nn)}
     for L in lists:
         for i, (k, t, sig) in enumerate(L):
             last_of_run = i + 1 == len(L) or L[i + 1][0] != k
@@ -364,10 +378,13 @@ def test_device_executor_plan_cannot_deadlock(name, spec, workers):
     # wait-for graph on kernel "stages": a task of kernel k at list position i waits for every task
     # of k's predecessors and for the task before it in its list.  Acyclic iff a topological order
     # of all tasks exists; check with Kahn's algorithm over tasks.
-    by = {b["name"]: b for b in spec["buffers"]}
-    preds = {k: set() for k in range(nk)}
+    preds = {k: set() for k in range(nn)}
     for (src, _, dst, _) in spec["edges"]:
         preds[dst].add(src)
+    for o in ops:   # uploads before their readers, read-backs after their writers
+        for w in o["waits"]:
+            if o["type"] != "h2d":
+                preds[node_of_op[o["id"]]].add(node_of_op[w])
     ids = {}
     for w, L in enumerate(lists):
         for i, (k, t, _) in enumerate(L):

@@ -229,6 +229,37 @@ def test_device_executor_takes_a_smaller_instance(gemm_dtype):
     r.close()
 
 
+def test_device_executor_runs_copies_beside_kernels():
+    """PSC_DEVICE with page-locked host buffers: the executor's own workgroups run the uploads
+    and the read-back as tasks, so later layers' weights arrive while the first layer computes.
+    Per-op device clocks: every upload ends before its readers start, the read-back starts after
+    its writer ends, an upload overlaps a kernel, and the output matches the oracle."""
+    spec = workloads.mha_spec(512, 512, 8, layers=3, gemm_dtype="bf16")
+    inp = workloads.mha_inputs(1, 512, 512, 3)
+    ref = odag.read_buffer(spec, odag.run_dag(spec, inp), "Y2")
+    r = psc.SpecRunner(spec, "device", record_ops=True)
+    r.set_inputs(inp)
+    r.run()
+    r.run()
+    got = r.result("Y2")
+    times = psc.psc_sched_op_times(r.sched)
+    exp = r.export()
+    r.close()
+    assert normwise(got, ref) < 2e-2
+    t = {o["id"]: (tt[2], tt[3]) for tt, o in zip(times, exp["ops"])}
+    copies = [o for o in exp["ops"] if o["type"] != "kernel"]
+    assert all(t[o["id"]][1] > 0 for o in copies), "a copy was not run by the executor"
+    for o in exp["ops"]:
+        for w in o["waits"]:
+            if o["type"] != "kernel" or exp["ops"][w]["type"] != "kernel":
+                assert t[w][1] <= t[o["id"]][0] + 0.5, (w, o["id"])
+    kernels = [t[o["id"]] for o in exp["ops"] if o["type"] == "kernel"]
+    ups = [t[o["id"]] for o in copies if o["type"] == "h2d"]
+    overlapping = sum(1 for c in ups for k in kernels if c[0] < k[1] and k[0] < c[1])
+    print(f"upload/kernel overlapping pairs: {overlapping}", flush=True)
+    assert overlapping >= 1
+
+
 def test_device_executor_node_times_respect_dependencies():
     spec = workloads.mha_spec(256, 256, 4, layers=2)
     inp = workloads.mha_inputs(2, 256, 256, 2)
