@@ -76,8 +76,13 @@ typedef enum psc_kind { PSC_GEMM = 0, PSC_TRANSPOSE = 1, PSC_SOFTMAX = 2, PSC_AD
  * Device: the precedences are enforced on the GPU at tile granularity: one persistent kernel
  * runs the tiles of every kernel from per-workgroup task lists that the host plans ahead of the
  * run (list scheduling of tiles onto workgroups in one topological order), each workgroup waiting
- * on the completion counters of a task's predecessor kernels; host copies run before (H2D) and
- * after (D2H) it on one stream.  The grid is sized to the workgroups the GPU holds at once
+ * on the completion counters of a task's predecessor kernels.  Uploads and read-backs of
+ * page-locked host memory that the device maps at the same address are run by the executor too,
+ * as copy tasks on W / 16 (at most 32) workgroups of their own -- the first-needed upload first
+ * -- so later layers' inputs arrive while earlier layers compute, each kernel waiting on its
+ * inputs' upload counters; other host memory is copied by DMA on one stream before (H2D) and
+ * after (D2H) the executor, and device-resident runs use a plan without copy tasks.  Op times of
+ * executor-run copies come from the device clock, DMA copies have none.  The grid is sized to the workgroups the GPU holds at once
  * (psc_sched_executor_info), and progress assumes they all become resident: a task may wait for
  * any other workgroup's earlier task.  If other work keeps CUs occupied for longer than a wait's
  * bound (5 s of device time), the waiting workgroups flag the error, every workgroup leaves its
@@ -600,8 +605,11 @@ psc_status psc_sched_samples(const psc_sched *sched, float *features, float *log
  * workgroup w's list is tasks [work_off[w], work_off[w+1]); signal > 0 means that after this
  * task the workgroup publishes that many completed tiles of the kernel (the run of its tiles
  * ending here).  *n_tasks = total; with tasks and work_off NULL only the total is returned;
- * work_off holds workers + 1 entries.  Any schedule of the DAG may be passed (its policy is not
- * used).  PSC_ERR_ARG if cap < *n_tasks. */
+ * work_off holds workers + 1 entries.  The plan shown is the one with the host copies:
+ * node ids below the kernel count are kernels, the following ones the device plan's uploads and
+ * read-backs in op order (psc_sched_export of a PSC_DEVICE schedule), their tasks on the last
+ * workers / 16 (at most 32) workgroups.  Any schedule of the DAG may be passed (its policy is not
+ * used; copy_roots is).  PSC_ERR_ARG if cap < *n_tasks. */
 psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32_t *tasks, int32_t cap,
                                   int32_t *n_tasks, int32_t *work_off);
 
