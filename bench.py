@@ -458,7 +458,7 @@ def kernels_main(a):
                 # seeded operands of the measurement below
                 best = None
                 ins = seeded_inputs(one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt]))
-                for t in (1, 2, 4, 5, 16, 20):
+                for t in (1, 2, 4, 5, 16, 20, 21):
                     rr = psc.SpecRunner(one_kernel("gemm", [(m, k), (k, n), (m, n)], [idt, idt, odt], tile=t), "coarse")
                     rr.set_inputs(ins)
                     rr.run(with_inputs=True, with_outputs=False)

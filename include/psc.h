@@ -620,8 +620,9 @@ psc_status psc_sched_device_tasks(const psc_sched *sched, int32_t workers, int32
  * K-split 16-row kernels reading operands directly into matrix-core registers (16x16, 16x32,
  * 16x64), 16 a 256x256 BF16 tile of eight wavefronts, 17..19 BF16 K-split kernels that load each
  * wavefront's whole share of K at once (16x16, 16x32, 32x32; for FP32 operands they mean 12, 10
- * and 9), 20 a 256x256 BF16 tile of four wavefronts with 128x128 each (32x32 matrix-core
- * blocks).  Tiles 16 and 20 need M and N multiples of 256, K of 64, 16-byte aligned A and B and
+ * and 9), 20 and 21 256x256 BF16 tiles whose operands go straight from global memory into LDS,
+ * of four wavefronts with 128x128 each and of eight with 128x64 each (32x32 matrix-core blocks).
+ * Tiles 16, 20 and 21 need M and N multiples of 256, K of 64, 16-byte aligned A and B and
  * leading dimensions that are multiples of 8, else they run as tile 4; with FP32 operands they
  * run as tile 1.  A GEMM whose params leave tile at
  * 0 takes the process-wide cache entry for its (M, N, K, operand dtype, output dtype) when there
@@ -663,8 +664,8 @@ psc_status psc_tile_cache_load(const char *path, const char *key, int32_t *n_loa
  * device buffers (iters back-to-back launches between HIP events, after 3 warm-up launches),
  * stores the fastest in the cache and returns it in *best_tile and its mean microseconds in
  * *best_us.  us_per_tile[t] for t < cap receives every configuration's time (index 0 unused);
- * a configuration that resolves to another for this shape and dtype (16-20 with FP32 operands,
- * 16 and 20 on shapes that are not whole 256 x 256 tiles) is not timed and its entry is left
+ * a configuration that resolves to another for this shape and dtype (16-21 with FP32 operands,
+ * 16, 20 and 21 on shapes that are not whole 256 x 256 tiles) is not timed and its entry is left
  * unchanged, so the cache always names the tile a launch uses.
  * Any output pointer may be NULL.  Errors: PSC_ERR_ARG, PSC_ERR_HIP, PSC_ERR_OOM. */
 psc_status psc_autotune_gemm(int32_t device, int32_t M, int32_t N, int32_t K, int32_t ab_dtype,

@@ -90,10 +90,10 @@ __global__ __launch_bounds__(512) void gemm_bf16_big_kernel(GemmArgs p) {
   gemm_bf16_big_tile<OUT_BF16>(p, group_tile(xcd_tile(blockIdx.x, gridDim.x), gridDim.x / p.tiles_n, p.tiles_n, 4), smem);
 }
 
-template <bool OUT_BF16>
-__global__ __launch_bounds__(256) void gemm_bf16_w4_kernel(GemmArgs p) {
+template <int WN, bool OUT_BF16>
+__global__ __launch_bounds__(128 * WN) void gemm_bf16_w4_kernel(GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_bf16_w4_smem()];
-  gemm_bf16_w4_tile<OUT_BF16>(p, group_tile(xcd_tile(blockIdx.x, gridDim.x), gridDim.x / p.tiles_n, p.tiles_n, 4), smem);
+  gemm_bf16_w4_tile<WN, OUT_BF16>(p, group_tile(xcd_tile(blockIdx.x, gridDim.x), gridDim.x / p.tiles_n, p.tiles_n, 4), smem);
 }
 
 template <int FN, bool VEC, bool OUT_BF16>
@@ -177,7 +177,7 @@ constexpr TileCfg kTiles[] = {{0, 0, false},     {128, 128, false}, {64, 64, fal
                               {64, 32, true},    {32, 32, true},    {16, 32, true},   {32, 16, true},
                               {16, 16, true},    {16, 16, true},    {16, 32, true},   {16, 64, true},
                               {256, 256, false}, {16, 16, true},    {16, 32, true},   {32, 32, true},
-                              {256, 256, false}};
+                              {256, 256, false}, {256, 256, false}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 #define PSC_VO(KERNEL, ...)                                                                     \
@@ -224,7 +224,8 @@ const void *gemm_fn(int ab_dtype, int tile, bool vec, bool obf) {
       case 17: return PSC_VO(gemm_bf16_deep_kernel, 16, 16, 4);
       case 18: return PSC_VO(gemm_bf16_deep_kernel, 16, 32, 4);
       case 19: return PSC_VO(gemm_bf16_deep_kernel, 32, 32, 2);
-      case 20: return obf ? (const void *)&gemm_bf16_w4_kernel<true> : (const void *)&gemm_bf16_w4_kernel<false>;
+      case 20: return obf ? (const void *)&gemm_bf16_w4_kernel<2, true> : (const void *)&gemm_bf16_w4_kernel<2, false>;
+      case 21: return obf ? (const void *)&gemm_bf16_w4_kernel<4, true> : (const void *)&gemm_bf16_w4_kernel<4, false>;
     }
   }
   return nullptr;
@@ -302,9 +303,9 @@ int gemm_auto_tile(int M, int N, int K, int dtype) {
 bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (tile <= 0 || tile >= kNumTiles) tile = tile_cache_get(a.M, a.N, a.K, ab_dtype, c_dtype);
   if (tile <= 0 || tile >= kNumTiles) tile = gemm_auto_tile(a.M, a.N, a.K, ab_dtype);
-  if ((tile == 16 || tile == 20) && ab_dtype == 0) tile = 1;  // the 256 x 256 tiles exist for BF16 only
+  if ((tile == 16 || tile >= 20) && ab_dtype == 0) tile = 1;  // the 256 x 256 tiles exist for BF16 only
   if (ab_dtype == 0 && tile >= 17 && tile <= 19) tile = tile == 17 ? 12 : tile == 18 ? 10 : 9;  // BF16 only
-  if (tile == 16 || tile == 20) {  // whole tiles, aligned operands only
+  if (tile == 16 || tile >= 20) {  // whole tiles, aligned operands only
     const bool fits = a.M % 256 == 0 && a.N % 256 == 0 && a.K % 64 == 0 && a.K > 0 && aligned16(a.A) &&
                       aligned16(a.B) && a.lda % 8 == 0 && a.ldb % 8 == 0;
     if (!fits) tile = 4;
@@ -320,7 +321,7 @@ bool make_gemm(Launch &L, GemmArgs a, int ab_dtype, int c_dtype, int tile) {
   if (!fn) return false;
   L.func = fn;
   L.grid = dim3(unsigned(int64_t(tiles_m) * a.tiles_n), 1, 1);
-  L.block = dim3(tile == 16 ? 512 : 256, 1, 1);  // four wavefronts, eight for the 256 x 256 tile 16
+  L.block = dim3(tile == 16 || tile == 21 ? 512 : 256, 1, 1);  // four wavefronts, eight for tiles 16 and 21
   L.shmem = 0;
   L.empty = a.M == 0 || a.N == 0;
   L.tile = tile;

@@ -887,34 +887,38 @@ constexpr int gemm_bf16_w4_smem() { return 2 * 65536; }
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <bool OUT_BF16>
+// WN wavefront columns: WN = 2, four wavefronts of 128 x 128 (one per SIMD); WN = 4, eight
+// wavefronts of 128 x 64 (two per SIMD, 128 accumulators each).
+template <int WN, bool OUT_BF16>
 __device__ __forceinline__ void gemm_bf16_w4_tile(const GemmArgs &p, int bid, unsigned char *smem) {
-  constexpr int BK = 64, FM = 4, FN = 4, STAGE = 65536, BOFF = 32768;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // four wavefronts
-  const int wm = wave >> 1, wn = wave & 1;
+  constexpr int BK = 64, FM = 4, FN = 8 / WN, STAGE = 65536, BOFF = 32768;
+  constexpr int NW = 2 * WN, CPW = 32 / NW;  // wavefronts; A (and B) chunks each copies per stage
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
   const int tm = bid / p.tiles_n, tn = bid % p.tiles_n;
   const int m0 = tm * 256, n0 = tn * 256;
 
   // Copies.  A chunk q (rows 8q .. 8q + 7): lane l fills unit l % 8 of row 8q + l / 8 with k unit
   // (l % 8) ^ ((4q + l / 16) % 8) = (l % 8) ^ (l / 16) ^ 4 (q % 2).  B chunk q (k rows 2q, 2q + 1):
   // lane l fills unit l % 32 of row 2q + l / 32 with n unit (l % 32) ^ (2 (l / 32)) ^ 4 (q % 2).
-  // Wavefront w copies the A chunks and the B chunks 8w .. 8w + 7 of every stage.
+  // Wavefront w copies the A chunks and the B chunks CPW w .. CPW w + CPW - 1 of every stage
+  // (CPW even, so a chunk's parity is its index's within the wavefront's share).
   const int a_unit = (lane & 7) ^ (lane >> 4), b_unit = (lane & 31) ^ (2 * (lane >> 5));
   const int a_odd = 8 * ((a_unit ^ 4) - a_unit), b_odd = 8 * ((b_unit ^ 4) - b_unit);
   const uint16_t *const a_src =
-      static_cast<const uint16_t *>(p.A) + int64_t(m0 + 64 * wave + (lane >> 3)) * p.lda + 8 * a_unit;
+      static_cast<const uint16_t *>(p.A) + int64_t(m0 + 8 * CPW * wave + (lane >> 3)) * p.lda + 8 * a_unit;
   const uint16_t *const b_src =
-      static_cast<const uint16_t *>(p.B) + int64_t(16 * wave + (lane >> 5)) * p.ldb + n0 + 8 * b_unit;
+      static_cast<const uint16_t *>(p.B) + int64_t(2 * CPW * wave + (lane >> 5)) * p.ldb + n0 + 8 * b_unit;
   const int64_t a_chunk = int64_t(8) * p.lda, b_chunk = int64_t(2) * p.ldb;
   auto copy = [&](int k0, unsigned char *stage) {
     const uint16_t *qa = a_src + k0;
     const uint16_t *qb = b_src + int64_t(k0) * p.ldb;
-    unsigned char *da = stage + wave * 8192, *db = stage + BOFF + wave * 8192;
+    unsigned char *da = stage + wave * CPW * 1024, *db = stage + BOFF + wave * CPW * 1024;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < CPW; ++i)
       __builtin_amdgcn_global_load_lds(qa + i * a_chunk + ((i & 1) ? a_odd : 0), (lds_void *)(da + i * 1024), 16, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < CPW; ++i)
       __builtin_amdgcn_global_load_lds(qb + i * b_chunk + ((i & 1) ? b_odd : 0), (lds_void *)(db + i * 1024), 16, 0, 0);
   };
 
@@ -926,7 +930,7 @@ __device__ __forceinline__ void gemm_bf16_w4_tile(const GemmArgs &p, int bid, un
   const int a_row = (wm * 128 + (lane & 31)) * 128;
   const int g = lane >> 4, rl = lane & 15;
   const int x = (2 * (g & 1) + ((rl & 3) >> 1)) ^ (2 * ((rl >> 2) & 3));
-  const int b_base = BOFF + (8 * (g >> 1) + (rl >> 2)) * 512 + 16 * (wn * 16 + (x & 3)) + 8 * (rl & 1);
+  const int b_base = BOFF + (8 * (g >> 1) + (rl >> 2)) * 512 + 16 * (wn * 4 * FN + (x & 3)) + 8 * (rl & 1);
   const int b_even = b_base + 64 * (x >> 2), b_oddj = b_base + 64 * (1 - (x >> 2));  // j = 0 / j = 1
 
   floatx16 acc[FM][FN];
@@ -969,16 +973,19 @@ __device__ __forceinline__ void gemm_bf16_w4_tile(const GemmArgs &p, int bid, un
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[m][i], b[m][j], acc[i][j], 0, 0, 0);
-    // instruction groups (masks: 0x100 LDS read, 0x008 matrix product, 0x020 global read)
-    __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
+    // instruction groups (masks: 0x100 LDS read, 0x008 matrix product, 0x020 global read): the
+    // reads of slices 0 and 1, slice 0's products each followed by two of the reads of slices 2
+    // and 3, the copy, the other products
+    constexpr int RD = FM + 2 * FN, PR = FM * FN;  // LDS reads and products per slice
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * RD, 0);
 #pragma unroll
-    for (int t = 0; t < 12; ++t) {
+    for (int t = 0; t < RD; ++t) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
-    __builtin_amdgcn_sched_group_barrier(0x020, 16, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 48, 0);
+    if constexpr (PR > RD) __builtin_amdgcn_sched_group_barrier(0x008, PR - RD, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 2 * CPW, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 3 * PR, 0);
   };
 
   const int steps = p.K / BK;
@@ -995,7 +1002,7 @@ __device__ __forceinline__ void gemm_bf16_w4_tile(const GemmArgs &p, int bid, un
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn * 128 + j * 32 + (lane & 31);
+      const int col = n0 + wn * 32 * FN + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);

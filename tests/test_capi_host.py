@@ -258,8 +258,8 @@ def test_classify_default_component_is_whole_dag():
 
 def test_tile_cache_roundtrip():
     n = psc.psc_gemm_tile_count()
-    assert n == 21   # automatic (0) + 5 large + 7 LDS K-split + 3 direct K-split + 256x256 BF16 + 3 deep K-split
-    #                  + 256x256 BF16 of four wavefronts
+    assert n == 22   # automatic (0) + 5 large + 7 LDS K-split + 3 direct K-split + 256x256 BF16 + 3 deep K-split
+    #                  + 256x256 BF16 with direct copies, four and eight wavefronts
     psc.psc_tile_cache_clear()
     assert psc.psc_tile_cache_get(512, 64, 512, "f32", "f32") == 0
     psc.psc_tile_cache_set(512, 64, 512, "f32", "f32", 9)

@@ -69,7 +69,7 @@ def test_gemm_bf16_ternary_exact(tile):
     np.testing.assert_array_equal(_run(spec, inp), oracle_outputs(spec, inp)["C"])
 
 
-@pytest.mark.parametrize("tile", [16, 20])
+@pytest.mark.parametrize("tile", [16, 20, 21])
 @pytest.mark.parametrize("m,n,k", [(256, 256, 64), (512, 768, 448), (768, 512, 1024)])
 def test_gemm_bf16_whole_tile_exact(tile, m, n, k):
     # the 256 x 256 tiles run only on whole tiles: check that the launch kept the tile, and that
