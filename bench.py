@@ -315,7 +315,9 @@ def timeline_profile(a):
         psc.psc_dag_destroy(d1)
         opts = FINE_CANDIDATES[bi]
     policy = opts.pop("policy", "fine")
-    r = psc.SpecRunner(spec, policy, **opts)
+    # the device executor runs its copies inside its one kernel: a kernel trace shows one launch,
+    # so its per-op device clocks are recorded and summarised instead
+    r = psc.SpecRunner(spec, policy, **opts, **({"record_ops": True} if policy == "device" else {}))
     r.set_inputs(inp)
     r.run()
     res = {"resident_ms": [], "with_copies_ms": []}
@@ -323,6 +325,19 @@ def timeline_profile(a):
         res["resident_ms"].append(r.run(with_inputs=False, with_outputs=False)["makespan_ms"])
     for _ in range(3):
         res["with_copies_ms"].append(r.run()["makespan_ms"])
+    if policy == "device":
+        # the last run with copies: per-op start/end (us from the executor's reset) by type
+        ops = psc.psc_sched_export(r.sched)
+        t = {o: (a_, b_) for (o, _, a_, b_) in psc.psc_sched_op_times(r.sched)}
+        iv = {k: [t[o["id"]] for o in ops if o["type"] == k and t[o["id"]][1] > 0] for k in ("h2d", "kernel", "d2h")}
+        ups, kers = iv["h2d"], iv["kernel"]
+        res["device_ops"] = {
+            "uploads": len(ups), "upload_span_us": [min(u[0] for u in ups), max(u[1] for u in ups)] if ups else None,
+            "kernel_span_us": [min(k[0] for k in kers), max(k[1] for k in kers)],
+            "kernels_started_before_last_upload_ended": sum(1 for k in kers if ups and k[0] < max(u[1] for u in ups)),
+            "upload_kernel_overlapping_pairs": sum(1 for u in ups for k in kers if u[0] < k[1] and k[0] < u[1]),
+            "readback_span_us": [min(d[0] for d in iv["d2h"]), max(d[1] for d in iv["d2h"])] if iv["d2h"] else None}
+        res["executor"] = dict(zip(("workers", "per_cu", "groups"), psc.psc_sched_executor_info(r.sched)))
     r.close()
     print(json.dumps({"config": a.config, "target": "timeline", "policy": policy, "fine_opts": opts,
                       "schedule": describe(opts) if policy == "fine" else policy,
