@@ -787,19 +787,29 @@ def dag_bench(spec, inp, a, tune=True, with_device=True, label=""):
             # (its uploads overlap the first layers' kernels)
             "fine_copy_stream": ("fine", dict(fine_opts, copy_stream=True))}
     if with_device:
-        plan["device_executor"] = ("device", dict(copy_roots=True))
+        # the executor with the most resident workgroups its instance allows, and with one per CU
+        # (which is faster depends on the DAG); the row reports the faster
+        plan["device_executor_most"] = ("device", dict(copy_roots=True))
+        plan["device_executor_1cu"] = ("device", dict(copy_roots=True, exec_per_cu=1))
     res, keep = {}, {}
     for name, (policy, kw) in plan.items():
         r = psc.SpecRunner(spec, policy, **kw)
         r.set_inputs(inp)
         res[name] = measure_runner(r, a.steps, a.warmup)
-        res[name]["schedule"] = describe(kw if policy != "device" else None) if policy != "coarse" else describe(dict(kw, n_streams=1))
+        if policy == "device":
+            w, pcu, grp = psc.psc_sched_executor_info(r.sched)
+            res[name]["schedule"] = describe(None) + f": {w} workgroups, {pcu} per CU, tile-function groups {grp:#x}"
+        else:
+            res[name]["schedule"] = describe(kw) if policy != "coarse" else describe(dict(kw, n_streams=1))
         print(f"# {label} {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
         if name == "fine":
             keep[name] = r
         else:
             r.close()
     res["coarse"] = min((res["coarse_hip"], res["coarse_aql"]), key=lambda v: v["ms_per_step"])
+    if with_device:
+        res["device_executor"] = min((res["device_executor_most"], res["device_executor_1cu"]),
+                                     key=lambda v: v["ms_per_step"])
     return res, fine_opts, keep, tuned
 
 

@@ -212,7 +212,12 @@ typedef struct psc_sched_opts {
                            first kernel that reads any of them (e.g. one copy of a d x d weight
                            matrix instead of one 128-byte-row rectangle per attention head).  The
                            host then gives the root's array (psc_host_io names the root). */
-  int32_t reserved[1];
+  int32_t exec_per_cu;  /* PSC_DEVICE only: at most this many executor workgroups per CU (>= 0).
+                           0: the covering executor instance with the most resident workgroups
+                           (two per CU for the attention DAGs); 1: one per CU.  Which is faster
+                           depends on the DAG: measured, one per CU on the one-layer 512
+                           attention DAG (0.119 against 0.155 ms), two on the 12-layer 1024
+                           one (3.93 against 4.38 ms), so the benchmark times both. */
 } psc_sched_opts;
 
 /* One op of an exported schedule.  Its cross-stream precedences are waits[wait_off ..

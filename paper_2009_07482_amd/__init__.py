@@ -67,7 +67,7 @@ class psc_sched_opts(C.Structure):
                 ("use_graph", C.c_int32), ("record_ops", C.c_int32), ("device", C.c_int32),
                 ("cost", C.c_void_p), ("host_threads", C.c_int32), ("mark_components", C.c_int32),
                 ("fault_inject_op", C.c_int32), ("timeout_ms", C.c_int32), ("dispatch", C.c_int32),
-                ("out_of_order", C.c_int32), ("copy_roots", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("out_of_order", C.c_int32), ("copy_roots", C.c_int32), ("exec_per_cu", C.c_int32)]
 
 
 class psc_op(C.Structure):
@@ -340,7 +340,7 @@ def psc_dag_classify(dag, component):
 
 def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, record_ops=False,
               device=0, cost=None, host_threads=0, mark_components=False, fault_inject_op=0,
-              timeout_ms=0, dispatch="hip", out_of_order=False, copy_roots=False):
+              timeout_ms=0, dispatch="hip", out_of_order=False, copy_roots=False, exec_per_cu=0):
     o = psc_sched_opts()
     o.n_streams = int(n_streams)
     o.mapper = MAPPERS[mapper] if isinstance(mapper, str) else int(mapper)
@@ -356,6 +356,7 @@ def make_opts(n_streams=4, mapper="rr", copy_stream=False, use_graph=False, reco
     o.dispatch = DISPATCH[dispatch] if isinstance(dispatch, str) else int(dispatch)
     o.out_of_order = int(bool(out_of_order))
     o.copy_roots = int(bool(copy_roots))
+    o.exec_per_cu = int(exec_per_cu)
     return o
 
 

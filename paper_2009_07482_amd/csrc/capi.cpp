@@ -353,6 +353,7 @@ std::unique_ptr<psc_sched> new_sched(psc_dag *dag, int32_t policy, const psc_sch
   need(o.dispatch == PSC_DISPATCH_HIP || o.dispatch == PSC_DISPATCH_AQL, PSC_ERR_ARG, "unknown dispatch");
   need(o.out_of_order == 0 || o.out_of_order == 1, PSC_ERR_ARG, "out_of_order must be 0 or 1");
   need(o.copy_roots == 0 || o.copy_roots == 1, PSC_ERR_ARG, "copy_roots must be 0 or 1");
+  need(o.exec_per_cu >= 0, PSC_ERR_ARG, "exec_per_cu must be >= 0");
   if (o.out_of_order)
     need(policy == PSC_FINE && o.dispatch == PSC_DISPATCH_AQL, PSC_ERR_UNSUPPORTED,
          "out-of-order queues need PSC_FINE with PSC_DISPATCH_AQL (HIP streams are in order)");

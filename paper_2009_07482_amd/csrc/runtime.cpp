@@ -471,13 +471,24 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
   return ep;
 }
 
-// The executor instance for a DAG: among the compiled instances, by decreasing resident
-// workgroups, the first whose tile-function groups cover every node variant the DAG gets at that
-// worker count (the tile choice depends on the worker count); the last instance covers all.
-int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int device, int32_t *workers) {
+// The executor instance for a DAG: among the compiled instances with at most per_cu_cap
+// workgroups per CU (0: any), by decreasing resident workgroups, the first whose tile-function
+// groups cover every node variant the DAG gets at that worker count (the tile choice depends on
+// the worker count); the last instance covers all.
+int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int device, int32_t per_cu_cap,
+                       int32_t *workers) {
   const int n = exec_num_instances();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
   std::vector<std::pair<int32_t, int>> cand;  // (-workers, instance): more workers first, then order
-  for (int i = 0; i < n; ++i) cand.push_back({-exec_max_workers(device, i), i});
+  for (int i = 0; i < n; ++i) {
+    const int32_t w = exec_max_workers(device, i);
+    if (per_cu_cap > 0 && w > per_cu_cap * cus && i != n - 1) continue;
+    cand.push_back({-(per_cu_cap > 0 ? std::min(w, per_cu_cap * cus) : w), i});
+  }
   std::sort(cand.begin(), cand.end());
   for (const auto &c : cand) {
     uint32_t need = 0;
@@ -488,6 +499,7 @@ int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int devi
     }
   }
   *workers = exec_max_workers(device, n - 1);
+  if (per_cu_cap > 0) *workers = std::min(*workers, per_cu_cap * cus);
   return n - 1;
 }
 
@@ -530,9 +542,9 @@ void upload_exec_plan(const ExecPlan &ep, Device &d, void *&mem, ExecArgs &a) {
 
 // Two plans: the kernels alone (device-resident runs, and runs whose host memory the device
 // cannot address), and the kernels with the host copies run by the executor.
-void prepare_executor(const Dag &g, const SchedPlan &plan, Device &d) {
+void prepare_executor(const Dag &g, const SchedPlan &plan, int32_t per_cu_cap, Device &d) {
   int32_t max_workers = 1;
-  d.exec_instance = pick_exec_instance(g, d.launch, d.device, &max_workers);
+  d.exec_instance = pick_exec_instance(g, d.launch, d.device, per_cu_cap, &max_workers);
   d.exec_copies = exec_copies(g, plan);
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
@@ -616,7 +628,7 @@ void prepare(psc_sched &s) {
       (void)hipGetLastError();
   }
   if (dev_mode) {
-    prepare_executor(g, s.plan, *d);
+    prepare_executor(g, s.plan, s.opts.exec_per_cu, *d);
   } else if (s.plan.dynamic) {
     d->dyn = std::make_unique<DynState>();
   } else {
@@ -1488,7 +1500,10 @@ void sched_executor_info(const psc_sched &s, int32_t *workers, int32_t *per_cu, 
     cus = 1;
   }
   if (workers) *workers = d.ea.n_workers;
-  if (per_cu) *per_cu = exec_max_workers(d.device, d.exec_instance) / cus;
+  if (per_cu) {
+    *per_cu = exec_max_workers(d.device, d.exec_instance) / cus;
+    if (s.opts.exec_per_cu > 0) *per_cu = std::min(*per_cu, s.opts.exec_per_cu);
+  }
   if (groups) *groups = exec_instance_groups(d.exec_instance);
 }
 

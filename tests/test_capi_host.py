@@ -492,6 +492,17 @@ def test_out_of_order_queues_issue_kernels_by_level_with_every_wait():
     assert ok, errs[:5]
 
 
+def test_exec_per_cu_must_not_be_negative():
+    dag = psc.build_dag(workloads.forkjoin_spec(4))
+    try:
+        with pytest.raises(psc.PscError) as e:
+            psc.psc_schedule(dag, "device", exec_per_cu=-1)
+        assert e.value.status == psc.PSC_ERR_ARG
+        psc.psc_sched_destroy(psc.psc_schedule(dag, "device", exec_per_cu=1))
+    finally:
+        psc.psc_dag_destroy(dag)
+
+
 def test_out_of_order_needs_fine_aql():
     spec = workloads.forkjoin_spec(16)
     dag = psc.build_dag(spec)

@@ -229,6 +229,23 @@ def test_device_executor_takes_a_smaller_instance(gemm_dtype):
     r.close()
 
 
+def test_device_executor_one_workgroup_per_cu_on_request():
+    # exec_per_cu = 1 caps the executor at one workgroup per CU; same results as the default
+    spec = workloads.mha_spec(512, 512, 8)
+    inp = workloads.mha_inputs(1, 512, 512)
+    ref = odag.read_buffer(spec, odag.run_dag(spec, inp), "Y0")
+    cus = psc.psc_device_info(0)["compute_units"]
+    r = psc.SpecRunner(spec, "device", exec_per_cu=1)
+    psc.psc_sched_prepare(r.sched)
+    workers, per_cu, groups = psc.psc_sched_executor_info(r.sched)
+    print(f"{workers} workers, {per_cu} per CU, groups {groups:#x}", flush=True)
+    assert per_cu == 1 and 0 < workers <= cus
+    r.set_inputs(inp)
+    r.run()
+    assert normwise(r.result("Y0"), ref) < 1e-4
+    r.close()
+
+
 def test_device_executor_runs_copies_beside_kernels():
     """PSC_DEVICE with page-locked host buffers: the executor's own workgroups run the uploads
     and the read-back as tasks, so later layers' weights arrive while the first layer computes.
