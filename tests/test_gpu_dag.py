@@ -280,6 +280,50 @@ def test_device_executor_runs_copies_beside_kernels():
     assert overlapping >= 1
 
 
+@pytest.mark.parametrize("pageable", ["all", "weights"])
+def test_device_executor_copies_pageable_memory_by_dma(pageable):
+    """Host memory the device cannot address (ordinary pageable arrays) is copied by DMA before
+    and after the executor: with every array pageable the kernels-only plan runs, with only the
+    weights pageable the copy plan runs with those upload nodes empty.  Results match the oracle
+    either way, and only executor-run copies carry device times."""
+    spec = workloads.mha_spec(256, 256, 4, layers=2, gemm_dtype="bf16")
+    inp = workloads.mha_inputs(2, 256, 256, 2)
+    ref = odag.read_buffer(spec, odag.run_dag(spec, inp), "Y1")
+    r = psc.SpecRunner(spec, "device", copy_roots=True, record_ops=True)
+    r.set_inputs(inp)
+    io, keep = [], []
+    for n, h in r.inputs.items():
+        if pageable == "all" or n != "X":
+            a = np.array(h.array, copy=True)   # ordinary (pageable) memory, same bytes
+            keep.append(a)
+            io.append((n, a.ctypes.data, a.nbytes))
+        else:
+            io.append((n, h.ptr, h.nbytes))
+    out = np.zeros((256, 256), np.float32) if pageable == "all" else None
+    if out is not None:
+        io.append(("Y1", out.ctypes.data, out.nbytes))
+    else:
+        io += [(n, r.outputs[n].ptr, r.outputs[n].nbytes) for n in r.out_names]
+    psc.psc_run(r.sched, io)
+    got = out if out is not None else r.result("Y1")
+    times = psc.psc_sched_op_times(r.sched)
+    exp = r.export()
+    r.close()
+    assert normwise(got, ref) < 2e-2
+    timed = {o["type"]: 0 for o in exp["ops"]}
+    for tt, o in zip(times, exp["ops"]):
+        if tt[3] > 0:
+            timed[o["type"]] += 1
+    print(f"{pageable} pageable: ops with device times {timed}", flush=True)
+    assert timed["kernel"] == len(spec["kernels"])
+    if pageable == "all":
+        assert timed["h2d"] == 0 and timed["d2h"] == 0
+    elif timed["h2d"] + timed["d2h"] == 0:
+        pytest.skip("this runtime does not map page-locked host memory at the same device address")
+    else:
+        assert timed["h2d"] == 1 and timed["d2h"] == 1   # X and Y1 by the executor, weights by DMA
+
+
 def test_device_executor_node_times_respect_dependencies():
     spec = workloads.mha_spec(256, 256, 4, layers=2)
     inp = workloads.mha_inputs(2, 256, 256, 2)
