@@ -258,13 +258,16 @@ def kernel_profile(a):
                 if (A_["rows"], B_["cols"], A_["cols"]) == tuple(int(v) for v in a.profile_shape.split("x")):
                     psc.psc_tile_cache_set(A_["rows"], B_["cols"], A_["cols"], A_["dtype"], C_["dtype"], a.profile_tile)
     if a.kernel_profile == "executor":
-        r = psc.SpecRunner(spec, "device")
+        # --fine-opts may set the executor's options (e.g. {"exec_per_cu": 1})
+        r = psc.SpecRunner(spec, "device", **(json.loads(a.fine_opts) if a.fine_opts else {}))
         r.set_inputs(inp)
         r.run()
         for _ in range(100):
             r.run(with_inputs=False, with_outputs=False)
+        w, pcu, grp = psc.psc_sched_executor_info(r.sched)
         info.update({"kernel": "exec_kernel (whole DAG, one launch)", "match": "exec_kernel",
-                     "work_per_launch": workloads.spec_flops(spec), "launches": 100})
+                     "work_per_launch": workloads.spec_flops(spec), "launches": 100,
+                     "executor": {"workers": w, "per_cu": pcu, "groups": grp}})
     else:
         r = psc.SpecRunner(spec, "fine", n_streams=4, mapper="component")
         r.set_inputs(inp)
