@@ -605,7 +605,8 @@ psc_status psc_sched_samples(const psc_sched *sched, float *features, float *log
 
 /* Host-only view of the PSC_DEVICE executor's plan for `workers` workgroups (the run uses one per
  * resident slot of the GPU): every kernel is cut into tasks (output tiles or row groups), and
- * the tasks are list-scheduled onto the workgroups.  tasks[3*i .. 3*i+2] = (kernel, tile,
+ * the tasks are list-scheduled onto the workgroups.  Tasks are sized here for `workers`
+ * workgroups; a run holding more than one workgroup per CU sizes them for one per CU.  tasks[3*i .. 3*i+2] = (kernel, tile,
  * signal) of the i-th task, where the lists of workgroups 0, 1, ... follow each other and
  * workgroup w's list is tasks [work_off[w], work_off[w+1]); signal > 0 means that after this
  * task the workgroup publishes that many completed tiles of the kernel (the run of its tiles

@@ -258,10 +258,13 @@ struct ExecPlan {
   std::vector<int32_t> work_off;
 };
 
-// The executor's node descriptions for max_workers workgroups: each kernel's tile is chosen for the
-// workgroups it can expect (all of them divided by the kernels at its depth, the longest path
-// from a root).
-std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers) {
+// The executor's node descriptions when tiles are sized for `tile_workers` workgroups: each
+// kernel's tile is chosen for the workgroups it can expect (all of them divided by the kernels at
+// its depth, the longest path from a root).  A run holding more than one workgroup per CU sizes
+// them for one per CU: the second workgroup hides the first's latency rather than adding CUs to
+// split a kernel over (measured: 8-10% shorter on the 512 attention DAG at two per CU, ~2% on the
+// 12-layer DAG, the same at one per CU).
+std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch, int32_t tile_workers) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   std::vector<ExecNode> nodes(nk);
   std::vector<int32_t> depth(nk, 0), width;
@@ -271,7 +274,7 @@ std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch
     if (depth[k] >= int32_t(width.size())) width.resize(depth[k] + 1, 0);
     ++width[depth[k]];
   }
-  const int32_t Wmax = std::max(1, max_workers);
+  const int32_t Wmax = std::max(1, tile_workers);
   for (int32_t k = 0; k < nk; ++k) {
     const Kernel &ker = g.kers[k];
     const int want = std::max(1, Wmax / std::max(1, width[depth[k]]));
@@ -404,11 +407,11 @@ std::vector<double> schedule_kernels(const Dag &g, const std::vector<ExecNode> &
 // subsequence of one order in which every task comes after its predecessors' (uploads, kernels
 // in placement order, read-backs), so with all workgroups resident every wait ends.  Host only.
 ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t max_workers,
-                       const std::vector<ExecCopy> &copies) {
+                       int32_t tile_workers, const std::vector<ExecCopy> &copies) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   const int32_t nc = static_cast<int32_t>(copies.size());
   ExecPlan ep;
-  ep.nodes = exec_nodes(g, launch, max_workers);
+  ep.nodes = exec_nodes(g, launch, tile_workers);
   std::vector<std::vector<int32_t>> P(nk);
   for (int32_t k = 0; k < nk; ++k) P[k] = g.pred[k];
   for (int32_t c = 0; c < nc; ++c) {
@@ -474,9 +477,9 @@ ExecPlan plan_executor(const Dag &g, const std::vector<Launch> &launch, int32_t 
 // The executor instance for a DAG: among the compiled instances with at most per_cu_cap
 // workgroups per CU (0: any), by decreasing resident workgroups, the first whose tile-function
 // groups cover every node variant the DAG gets at that worker count (the tile choice depends on
-// the worker count); the last instance covers all.
+// the worker count, capped at one per CU: *tile_workers); the last instance covers all.
 int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int device, int32_t per_cu_cap,
-                       int32_t *workers) {
+                       int32_t *workers, int32_t *tile_workers) {
   const int n = exec_num_instances();
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) {
@@ -492,14 +495,16 @@ int pick_exec_instance(const Dag &g, const std::vector<Launch> &launch, int devi
   std::sort(cand.begin(), cand.end());
   for (const auto &c : cand) {
     uint32_t need = 0;
-    for (const ExecNode &nd : exec_nodes(g, launch, -c.first)) need |= exec_variant_group(nd.variant);
+    for (const ExecNode &nd : exec_nodes(g, launch, std::min(-c.first, cus))) need |= exec_variant_group(nd.variant);
     if ((need & ~exec_instance_groups(c.second)) == 0) {
       *workers = -c.first;
+      *tile_workers = std::min(*workers, cus);
       return c.second;
     }
   }
   *workers = exec_max_workers(device, n - 1);
   if (per_cu_cap > 0) *workers = std::min(*workers, per_cu_cap * cus);
+  *tile_workers = std::min(*workers, cus);
   return n - 1;
 }
 
@@ -543,8 +548,8 @@ void upload_exec_plan(const ExecPlan &ep, Device &d, void *&mem, ExecArgs &a) {
 // Two plans: the kernels alone (device-resident runs, and runs whose host memory the device
 // cannot address), and the kernels with the host copies run by the executor.
 void prepare_executor(const Dag &g, const SchedPlan &plan, int32_t per_cu_cap, Device &d) {
-  int32_t max_workers = 1;
-  d.exec_instance = pick_exec_instance(g, d.launch, d.device, per_cu_cap, &max_workers);
+  int32_t max_workers = 1, tile_workers = 1;
+  d.exec_instance = pick_exec_instance(g, d.launch, d.device, per_cu_cap, &max_workers, &tile_workers);
   d.exec_copies = exec_copies(g, plan);
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.device) == hipSuccess && khz > 0)
@@ -553,10 +558,10 @@ void prepare_executor(const Dag &g, const SchedPlan &plan, int32_t per_cu_cap, D
     (void)hipGetLastError();  // keep the default rate; leave no sticky error behind
   PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_err), 16, hipHostMallocDefault));
   *d.h_err = 0;
-  upload_exec_plan(plan_executor(g, d.launch, max_workers, {}), d, d.exec_mem, d.ea);
+  upload_exec_plan(plan_executor(g, d.launch, max_workers, tile_workers, {}), d, d.exec_mem, d.ea);
   const size_t nc = d.exec_copies.size();
   if (nc) {
-    const ExecPlan ep = plan_executor(g, d.launch, max_workers, d.exec_copies);
+    const ExecPlan ep = plan_executor(g, d.launch, max_workers, tile_workers, d.exec_copies);
     upload_exec_plan(ep, d, d.exec_mem_copy, d.ea_copy);
     PSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&d.h_copy_nodes), sizeof(ExecNode) * nc, hipHostMallocDefault));
     for (size_t c = 0; c < nc; ++c) d.h_copy_nodes[c] = ep.nodes[ep.nodes.size() - nc + c];  // counts, predecessors
@@ -1272,7 +1277,7 @@ void device_tasks(const psc_sched &s, int32_t workers, int32_t *tasks, int32_t c
   }
   std::vector<Launch> launch(g.kers.size());
   for (size_t k = 0; k < g.kers.size(); ++k) build_launch(g, d, int32_t(k), launch[k]);
-  const ExecPlan ep = plan_executor(g, launch, workers, exec_copies(g, build_plan(g, PSC_DEVICE, s.opts)));
+  const ExecPlan ep = plan_executor(g, launch, workers, workers, exec_copies(g, build_plan(g, PSC_DEVICE, s.opts)));
   *n_tasks = static_cast<int32_t>(ep.tasks.size());
   if (!tasks && !work_off) return;
   if (cap < *n_tasks) fail(PSC_ERR_ARG, "capacity too small");
