@@ -354,22 +354,22 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
                                      : (aligned16(g.A) && aligned16(g.B) && g.lda % 8 == 0 && g.ldb % 8 == 0);
       // The executor's own tile choice: its parallelism comes from kernels running side by side,
       // so a task should carry more work than the standalone kernels' small tiles (made to fill
-      // the GPU with one kernel).  `want` is the number of workgroups this kernel can expect
-      // (all of them divided by the kernels beside it): take the largest tile that still gives
-      // at least `want` tasks, else the smallest.  Candidates, largest first: 16 x 64 / 16 x 32 /
-      // 16 x 16 direct-load tiles for outputs at most 64 wide; for wider outputs 64 x 64 (LDS
-      // staged), then the same direct-load tiles -- one memory round trip per wavefront for its
-      // share of K, where an LDS-staged 32 x 32 tile pays one per K step (measured: the
-      // 512 x 512 x 512 output projection of the attention DAG in 256 tasks, 3.6% shorter
-      // makespan).  (`tile`, the standalone choice, is unused.)
+      // the GPU with one kernel).  `want` is the number of workgroups this kernel can expect:
+      // take the largest tile that still gives at least `want` tasks, else the smallest.
+      // Candidates, largest first: 64 x 64 (LDS staged), then 16 x 64 / 16 x 32 / 16 x 16
+      // direct-load tiles -- one memory round trip per wavefront for its share of K, where an
+      // LDS-staged 32 x 32 tile pays one per K step (measured: the 512 x 512 x 512 output
+      // projection of the attention DAG in 256 tasks, 3.6% shorter makespan).  A 16-row task
+      // re-reads the whole K x N operand for 16 output rows; the 64 x 64 tile reads it a quarter
+      // as often, which took the 12-layer DAG's 1024 x 64 x 1024 projections (16 tasks each)
+      // from 3.78 to 3.16 ms.  (`tile`, the standalone choice, is unused.)
       (void)tile;
       int cfg = -1;
       if (!vec) {
         cfg = in_dtype == 0 ? 13 : 12;
       } else {
-        static constexpr int narrow[] = {15, 14, 13}, wide[] = {2, 15, 14, 13};
-        const int *c0 = g.N <= 64 ? narrow : wide;
-        const int nc = g.N <= 64 ? 3 : 4;
+        static constexpr int c0[] = {2, 15, 14, 13};
+        constexpr int nc = sizeof(c0) / sizeof(c0[0]);
         for (int i = 0; i < nc && cfg < 0; ++i) {
           int bm = 16, bn = 16;
           for (const PCfg &c : kPersistentGemm)

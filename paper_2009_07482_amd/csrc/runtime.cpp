@@ -259,11 +259,14 @@ struct ExecPlan {
 };
 
 // The executor's node descriptions when tiles are sized for `tile_workers` workgroups: each
-// kernel's tile is chosen for the workgroups it can expect (all of them divided by the kernels at
-// its depth, the longest path from a root).  A run holding more than one workgroup per CU sizes
-// them for one per CU: the second workgroup hides the first's latency rather than adding CUs to
-// split a kernel over (measured: 8-10% shorter on the 512 attention DAG at two per CU, ~2% on the
-// 12-layer DAG, the same at one per CU).
+// kernel's tile is chosen for the workgroups it can expect, half of them divided by the kernels
+// at its depth (the longest path from a root) -- kernels of neighbouring depths run side by side
+// in the list schedule, so a depth's kernels seldom have all workgroups to themselves (measured
+// on the 512 attention DAG: 0.110 ms against 0.116-0.119 with all of them and 0.128 with a
+// quarter).  A run holding more than one workgroup per CU sizes them for one per CU: the second
+// workgroup hides the first's latency rather than adding CUs to split a kernel over (measured:
+// 8-10% shorter on the 512 attention DAG at two per CU, ~2% on the 12-layer DAG, the same at one
+// per CU).
 std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch, int32_t tile_workers) {
   const int32_t nk = static_cast<int32_t>(g.kers.size());
   std::vector<ExecNode> nodes(nk);
@@ -274,7 +277,7 @@ std::vector<ExecNode> exec_nodes(const Dag &g, const std::vector<Launch> &launch
     if (depth[k] >= int32_t(width.size())) width.resize(depth[k] + 1, 0);
     ++width[depth[k]];
   }
-  const int32_t Wmax = std::max(1, tile_workers);
+  const int32_t Wmax = std::max(1, tile_workers / 2);
   for (int32_t k = 0; k < nk; ++k) {
     const Kernel &ker = g.kers[k];
     const int want = std::max(1, Wmax / std::max(1, width[depth[k]]));
