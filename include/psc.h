@@ -711,7 +711,8 @@ psc_status psc_sched_kernel_tile(const psc_sched *sched, int32_t kernel, int32_t
 /* [GPU after prepare] The device executor a prepared PSC_DEVICE schedule launches: its workgroup
  * count, workgroups resident per CU, and the tile-function groups of the compiled instance it
  * uses (bit i = group i; groups 0-5 FP32 GEMM tiles, 6-12 BF16 GEMM tiles, 13 softmax, transpose
- * and add).  The library holds several instances of the executor, each with a subset of the tile
+ * and add, 14 the BF16 64 x 64 K-split tile for K >= 256, held only by instances of one workgroup
+ * per CU).  The library holds several instances of the executor, each with a subset of the tile
  * functions: registers are the union of what an instance holds, so a smaller instance keeps more
  * workgroups per CU; prepare takes, among the instances that cover every tile function the DAG
  * needs, the one with the most resident workgroups.  Any pointer may be NULL.

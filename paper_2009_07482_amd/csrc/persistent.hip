@@ -121,7 +121,8 @@ __device__ __forceinline__ T uniform_load(const unsigned char *p) {
     }                                                   \
     return false
 
-constexpr uint32_t kGAll = kGElem | 0x1FFFu, kGF32All = kGElem | 0x3Fu, kGBf16All = kGElem | 0x1FC0u;
+constexpr uint32_t kGAll = kGElem | (1u << 14) | 0x1FFFu, kGF32All = kGElem | 0x3Fu,
+                   kGBf16All = kGElem | (1u << 14) | 0x1FC0u;
 // Wavefronts per SIMD each instance is compiled for, the most its tile functions fit without
 // spilling registers to memory: the element-wise instance three (three workgroups' LDS fill a
 // CU), the aligned direct-load and attention instances two, the instances with every FP32, every
@@ -159,6 +160,8 @@ __device__ __forceinline__ bool run_task(const ExecNode *ndp, int tile, unsigned
     PSC_TASK(163, gemm_direct_tile<4, false, true, true, 8>(uniform_load<GemmArgs>(nd.args), tile, smem));
     PSC_TASK(210, gemm_bf16_tile<64, 64, 64, 32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
     PSC_TASK(211, gemm_bf16_tile<64, 64, 64, 32, 32, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(266, gemm_bf16_splitk_tile<64, 64, true, false, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
+    PSC_TASK(267, gemm_bf16_splitk_tile<64, 64, true, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
     PSC_TASK(214, gemm_bf16_tile<32, 32, 64, 16, 16, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
     PSC_TASK(215, gemm_bf16_tile<32, 32, 64, 16, 16, true, true>(uniform_load<GemmArgs>(nd.args), tile, smem));
     PSC_TASK(238, gemm_bf16_splitk_tile<32, 32, true, false>(uniform_load<GemmArgs>(nd.args), tile, smem));
@@ -211,7 +214,11 @@ __device__ __forceinline__ bool run_task(const ExecNode *ndp, int tile, unsigned
 
 #undef PSC_TASK
 
-constexpr int kExecSmem = 49152;  // the largest tile function's LDS (FP32 K-split tiles)
+// LDS per workgroup: the largest tile function's -- 48 KiB (FP32 K-split tiles), or the 64 x 64
+// BF16 K-split tile's 72 KiB in the instances holding group 14.
+constexpr int exec_smem(uint32_t g) {
+  return (g & (1u << 14)) ? (gemm_bf16_splitk_smem<64, 64>() > 49152 ? gemm_bf16_splitk_smem<64, 64>() : 49152) : 49152;
+}
 
 __global__ __launch_bounds__(256) void exec_reset_kernel(ExecArgs a) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
@@ -252,7 +259,7 @@ __device__ __forceinline__ bool wait_preds(const ExecArgs &a, const ExecNode &nd
 // read the same way, so all 256 threads take the same path each iteration.
 template <uint32_t G>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exec_waves(G)))) void exec_kernel(ExecArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kExecSmem];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[exec_smem(G)];
   __shared__ uint32_t s_ok;
   const int32_t w = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x));
   const int32_t lo = __builtin_amdgcn_readfirstlane(a.work_off[w]);
@@ -336,7 +343,7 @@ const void *exec_fn(int i) { return instance_fn(i, std::make_integer_sequence<in
 struct PCfg {
   int cfg, bm, bn;
 };
-constexpr PCfg kPersistentGemm[] = {{2, 64, 64},  {3, 32, 32},  {9, 32, 32}, {10, 16, 32},
+constexpr PCfg kPersistentGemm[] = {{2, 64, 64},  {3, 32, 32},  {9, 32, 32}, {10, 16, 32}, {16, 64, 64},
                                     {12, 16, 16}, {13, 16, 16}, {14, 16, 32}, {15, 16, 64}};
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -362,7 +369,11 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
       // projection of the attention DAG in 256 tasks, 3.6% shorter makespan).  A 16-row task
       // re-reads the whole K x N operand for 16 output rows; the 64 x 64 tile reads it a quarter
       // as often, which took the 12-layer DAG's 1024 x 64 x 1024 projections (16 tasks each)
-      // from 3.78 to 3.16 ms.  (`tile`, the standalone choice, is unused.)
+      // from 3.78 to 3.16 ms.  A BF16 64 x 64 task with K >= 256 runs K-split instead (cfg 16:
+      // each wavefront multiplies the whole 64 x 64 block over its own quarter of K, one 64-deep
+      // chunk at a time, and the four partial blocks are summed through LDS): the staged tile
+      // steps through K one 64-deep slice per block barrier, a memory round trip each, sixteen
+      // for K = 1024 against four.  (`tile`, the standalone choice, is unused.)
       (void)tile;
       int cfg = -1;
       if (!vec) {
@@ -377,6 +388,7 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
           const int64_t tiles = int64_t((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
           if (tiles >= want || i == nc - 1) cfg = c0[i];
         }
+        if (cfg == 2 && in_dtype == 1 && g.K >= 256) cfg = 16;
       }
       int bm = 16, bn = 16;
       for (const PCfg &c : kPersistentGemm)

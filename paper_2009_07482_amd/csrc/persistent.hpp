@@ -71,7 +71,9 @@ ExecNode make_exec_node(int kind, const unsigned char *args, int in_dtype, int o
 // Tile-function groups: the group bit of a node variant (0 for the empty variant 0).  Groups
 // 0-5: FP32 GEMM tiles (64x64 and 32x32 staged through LDS, split-K, direct-load with 1, 2 and 4
 // column blocks); 6-12: the BF16 ones (and a separate group for the unaligned direct-load
-// tile); 13: softmax, transpose, add and the host copies.
+// tile); 13: softmax, transpose, add and the host copies; 14: the BF16 64x64 K-split tile (its
+// registers alone exceed what two workgroups per CU leave, so only the one-per-CU instances hold
+// it).
 constexpr uint32_t kGElem = 1u << 13;
 __host__ __device__ constexpr uint32_t exec_variant_group(int v) {
   return v == 110 || v == 111 ? 1u << 0
@@ -88,6 +90,7 @@ __host__ __device__ constexpr uint32_t exec_variant_group(int v) {
        : v == 258 || v == 259 ? 1u << 11
        : v == 262 || v == 263 ? 1u << 12
        : (v >= 300 && v <= 413) || v == 420 ? kGElem
+       : v == 266 || v == 267 ? 1u << 14
                               : 0u;
 }
 

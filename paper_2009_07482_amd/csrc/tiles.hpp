@@ -468,7 +468,12 @@ constexpr int gemm_bf16_splitk_smem() {
   return 4 * (TM + TN) * 72 * 2 > 4 * TM * TN * 4 ? 4 * (TM + TN) * 72 * 2 : 4 * TM * TN * 4;
 }
 
-template <int TM, int TN, bool VEC, bool OUT_BF16>
+// PREFETCH = false loads each chunk just before staging it instead of during the previous
+// chunk's products: no staging registers live beside the fragments and accumulators (for the
+// 64 x 64 tile, whose 64 accumulator registers per lane would otherwise push a two-wavefront-per-
+// SIMD kernel into spills), at the price of the overlap, which matters little when a wavefront
+// has only a few chunks.
+template <int TM, int TN, bool VEC, bool OUT_BF16, bool PREFETCH = true>
 __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid, unsigned char *smem) {
   constexpr int BK = 64, KP = BK + 8, FM = TM / 16, FN = TN / 16;
   constexpr int UA = TM * (BK / 8) / 64;        // uint4 (8 x bf16) loads per lane
@@ -526,10 +531,11 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  load(w);
+  if (PREFETCH) load(w);
   for (int it = 0; it < iters; ++it) {
     // no block barrier in this loop: each wavefront stages and reads only its own LDS region,
     // and one wavefront's LDS operations take effect in program order
+    if (!PREFETCH) load(it * 4 + w);
 #pragma unroll
     for (int j = 0; j < UA; ++j) {
       const int u = lane + 64 * j, r = u / (BK / 8), c = (u % (BK / 8)) * 8;
@@ -545,7 +551,7 @@ __device__ __forceinline__ void gemm_bf16_splitk_tile(const GemmArgs &p, int bid
       for (int e = 0; e < 8; ++e)
         *reinterpret_cast<uint32_t *>(&Bt[(c + e) * KP + 2 * kp]) = uint32_t(lo[e]) | (uint32_t(hi[e]) << 16);
     }
-    if (it + 1 < iters) load((it + 1) * 4 + w);
+    if (PREFETCH && it + 1 < iters) load((it + 1) * 4 + w);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       const int kq = kk + 8 * (lane >> 4);

@@ -209,10 +209,10 @@ def test_device_executor_matches_streams_bit_identical(mha512):
 @pytest.mark.parametrize("gemm_dtype", ["f32", "bf16"])
 def test_device_executor_takes_a_smaller_instance(gemm_dtype):
     # an attention DAG needs the 64 x 64 and direct-load GEMM tiles and the element-wise kernels
-    # only: the executor takes an instance holding just those, not the one holding every tile
-    # function, with as many workgroups as the runtime says the device holds of it (two per CU on
-    # the MI355X boxes measured: 244-256 registers; the all-function instance fits one); its
-    # results match the oracle
+    # only: the executor takes an instance holding just those (FP32: two per CU on the MI355X
+    # boxes measured, 244-256 registers; BF16 with K >= 256: its 64 x 64 K-split tile is held by
+    # the every-BF16-tile instance, one per CU), not the one holding every tile function, with as
+    # many workgroups as the runtime says the device holds of it; its results match the oracle
     spec = workloads.mha_spec(512, 512, 8, gemm_dtype=gemm_dtype)
     inp = workloads.mha_inputs(1, 512, 512)
     ref = odag.read_buffer(spec, odag.run_dag(spec, inp), "Y0")
@@ -222,11 +222,65 @@ def test_device_executor_takes_a_smaller_instance(gemm_dtype):
     cus = psc.psc_device_info(0)["compute_units"]
     print(f"{gemm_dtype}: {workers} workers, {per_cu} per CU on {cus} CUs, groups {groups:#x}", flush=True)
     assert per_cu >= 1 and 0 < workers <= per_cu * cus
-    assert groups != 0x3FFF and groups & (1 << 13)
+    assert groups != 0x7FFF and groups & (1 << 13)
+    assert not groups & 0x3F if gemm_dtype == "bf16" else not groups & 0x1FC0
     r.set_inputs(inp)
     r.run()
     assert normwise(r.result("Y0"), ref) < (1e-4 if gemm_dtype == "f32" else 2e-2)
     r.close()
+
+
+def _independent_gemms_spec(count, M, N, K):
+    """`count` independent BF16 GEMMs C_i = A_i B_i (M x K times K x N), outputs alternately FP32
+    and BF16: with this many kernels side by side each expects few workgroups, so the executor
+    gives them 64 x 64 tasks, which for BF16 with K >= 256 run K-split."""
+    bufs, kers = [], []
+    for i in range(count):
+        bufs += [{"name": f"A{i}", "dtype": "bf16", "rows": M, "cols": K, "view_of": None, "row_off": 0, "col_off": 0},
+                 {"name": f"B{i}", "dtype": "bf16", "rows": K, "cols": N, "view_of": None, "row_off": 0, "col_off": 0},
+                 {"name": f"C{i}", "dtype": "bf16" if i % 2 else "f32", "rows": M, "cols": N, "view_of": None,
+                  "row_off": 0, "col_off": 0}]
+        kers.append({"name": f"g{i}", "kind": "gemm", "inputs": [f"A{i}", f"B{i}"], "outputs": [f"C{i}"], "alpha": 1.0})
+    return {"buffers": bufs, "kernels": kers, "edges": [], "component": list(range(count))}
+
+
+@pytest.mark.parametrize("values", ["ternary", "uniform"])
+def test_device_executor_ksplit_64x64_tasks(values):
+    """The executor's 64 x 64 K-split BF16 task (each wavefront a quarter of K, partial blocks
+    summed through LDS) on ragged shapes: M = 200 and N = 136 leave partial row and column tiles,
+    K = 1000 a partial last 64-deep chunk.  Ternary operands make every product sum an integer
+    below 2^24, exact in FP32 whatever the summation order: FP32 outputs equal the oracle bit for
+    bit, BF16 outputs equal its storage-rounding emulation.  Uniform operands: the exact oracle
+    (unrounded inputs) within the BF16 bar of 2e-2, the emulating one (inputs and outputs rounded
+    where the GPU stores them) within 1e-5 for FP32 outputs and 5e-3 for BF16 outputs."""
+    M, N, K, count = 200, 136, 1000, 32
+    spec = _independent_gemms_spec(count, M, N, K)
+    g = np.random.default_rng(7)
+    inp = {}
+    for i in range(count):
+        for name, shape in ((f"A{i}", (M, K)), (f"B{i}", (K, N))):
+            inp[name] = (g.integers(-1, 2, size=shape).astype(np.float32) if values == "ternary"
+                         else g.uniform(-1.0, 1.0, size=shape).astype(np.float32))
+    r = psc.SpecRunner(spec, "device")
+    psc.psc_sched_prepare(r.sched)
+    workers, per_cu, groups = psc.psc_sched_executor_info(r.sched)
+    print(f"{workers} workers, {per_cu} per CU, groups {groups:#x}", flush=True)
+    assert groups & (1 << 14), "the plan does not use the K-split 64 x 64 task"
+    r.set_inputs(inp)
+    r.run()
+    out = {n: r.result(n) for n in r.out_names}
+    r.close()
+    exact = oracle_outputs(spec, inp)
+    emul = oracle_outputs(spec, inp, emulate=True)
+    for i in range(count):
+        name = f"C{i}"
+        if values == "ternary":
+            np.testing.assert_array_equal(out[name], emul[name], err_msg=name)
+            if i % 2 == 0:
+                np.testing.assert_array_equal(out[name], exact[name], err_msg=name)
+        else:
+            assert normwise(out[name], exact[name]) < 2e-2, name
+            assert normwise(out[name], emul[name]) < (5e-3 if i % 2 else 1e-5), name
 
 
 def test_device_executor_one_workgroup_per_cu_on_request():
